@@ -1,0 +1,142 @@
+/*
+ * bsf.h -- C ABI of libbsf, constant-cost space-variant elliptical filtering with
+ * four-direction box splines on AMD Instinct MI355X (gfx950).
+ *
+ * The filter (Chaudhury, Munoz-Barrutia, Unser, "Fast adaptive elliptical filtering
+ * using box splines"): every output pixel m is the projection of the image onto the
+ * four-direction box spline with that pixel's own scale vector a(m) = (a1,a2,a3,a4)
+ * (Section 6, the projections s[m]; Section 7 fixes N = 4 directions at 0, 45, 90 and
+ * 135 degrees and phi = delta).  a_d is the length of the generating segment along
+ * direction d in pixel units (Section 4, eq. generator), so the diagonal lags in
+ * lattice steps are a_d/sqrt2 (Section 7, a'_j = a_j/sqrt2).  Order n >= 1 is the
+ * n-fold self-convolution of the box spline (Section 4, closing remark); n = 1 is the
+ * paper's 16-tap mesh (Table 1, eq. final_eqn).
+ *
+ * It is computed as in Section 7: a global pre-integrator (n-fold running sums along
+ * (1,0), (1,1), (0,1), (-1,1), eq. RS) followed by a per-pixel localisation mesh of
+ * (n+1)^4 finite-difference taps at offsets set by a(m), each tap interpolated with
+ * the lattice box spline (eq. final_eqn).  Pre-integration runs per output tile on a
+ * restart window that holds the support of every pixel of the tile; this gives the
+ * same result in exact arithmetic and bounds the magnitudes the mesh cancels.
+ *
+ * Conventions
+ *   - Images are row-major: element (k1, k2) (k1 = column) lives at base[k2*pitch + k1].
+ *   - Pitches are in elements of the array they describe; scales are float32 and their
+ *     pitch counts pixels (4 floats each).
+ *   - Every pointer in a bsf_job is a device pointer owned by the caller.  Calls are
+ *     asynchronous on the given stream (a hipStream_t passed as void*, NULL = default
+ *     stream) and the caller keeps the buffers alive until the stream reaches them.
+ *   - No call throws.  Argument errors are reported synchronously; errors found by the
+ *     kernels (scale values out of range, a window larger than the chip's LDS, integer
+ *     range) set sticky device flags returned by bsf_get_device_error, and the affected
+ *     pixels are written as NaN.
+ */
+#ifndef BSF_H
+#define BSF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bsf_ctx bsf_ctx;
+
+typedef enum {
+    BSF_OK = 0,
+    BSF_ERR_INVALID_ARG = 1,   /* bad size, pitch, order, dtype/path pair or null pointer */
+    BSF_ERR_OUT_OF_MEMORY = 2, /* the workspace would exceed the context's limit         */
+    BSF_ERR_HIP = 3,           /* a HIP runtime call failed; bsf_last_error has the text  */
+    BSF_ERR_UNSUPPORTED = 4,   /* a restart window does not fit the on-chip memory        */
+    BSF_ERR_SCALE_RANGE = 5,   /* a scale is not finite or lies outside [0.5, 1e4]        */
+    BSF_ERR_RANGE = 6,         /* a pre-integrated value left the exact integer range     */
+    BSF_ERR_INEXACT_INPUT = 7  /* a float input was not on the 2^-24 grid (it was rounded) */
+} bsf_status;
+
+typedef enum { BSF_U8 = 0, BSF_F32 = 1, BSF_F64 = 2 } bsf_dtype;
+
+/* BSF_PATH_F64: output float64; mesh interpolation and accumulation in double-double,
+ *   so the result matches the exact filter to a few float64 ulps.
+ * BSF_PATH_F32_TILED: output float32; the same exact pre-integration, mesh in plain
+ *   float64 (error grows with the cancellation the mesh performs). */
+typedef enum { BSF_PATH_F64 = 0, BSF_PATH_F32_TILED = 1 } bsf_path;
+
+/* Boundary rule for samples outside the image (the paper leaves it open): clamp to
+ * the nearest edge pixel, or zero. */
+typedef enum { BSF_BORDER_CLAMP = 0, BSF_BORDER_ZERO = 1 } bsf_border;
+
+typedef struct {
+    int width, height;              /* >= 1                                              */
+    bsf_dtype in_dtype;             /* u8, f32 or f64                                     */
+    const void* in;                 /* [height][in_pitch] samples                         */
+    ptrdiff_t in_pitch;             /* >= width                                           */
+    const float* scales;            /* [height][scale_pitch][4] = (a1,a2,a3,a4) per pixel */
+    ptrdiff_t scale_pitch;          /* >= width, in pixels                                */
+    int order;                      /* n in {1, 2, 3}                                     */
+    bsf_path path;
+    bsf_border border;
+    float a_max;                    /* an upper bound on every a_d (sizes on-chip windows;
+                                       0 = reserve the largest window the chip allows)   */
+    void* out;                      /* [height][out_pitch] float64 (F64) / float32 (F32) */
+    ptrdiff_t out_pitch;            /* >= width                                           */
+} bsf_job;
+
+/* Create a context on HIP device `hip_device`.  `workspace_limit_bytes` caps the device
+ * memory the context may allocate for its own workspace (0 = 1 GiB).  The context owns
+ * its workspace and a small sticky error word; it is used by one host thread at a time. */
+bsf_status bsf_create(bsf_ctx** ctx, int hip_device, size_t workspace_limit_bytes);
+
+/* Release everything the context owns.  Waits for nothing: synchronise first. */
+bsf_status bsf_destroy(bsf_ctx* ctx);
+
+/* Device workspace one bsf_filter call on `job` needs, in bytes (host only). */
+bsf_status bsf_workspace_size(const bsf_job* job, size_t* bytes);
+
+/* out[m] = s[m] for every pixel (Section 6 projections computed by the two steps of
+ * Section 7).  Asynchronous on `stream`. */
+bsf_status bsf_filter(bsf_ctx* ctx, const bsf_job* job, void* stream);
+
+/* The same for `njobs` independent jobs of any sizes, orders and paths in one
+ * persistent launch (a device work queue of tiles).  Each output is bitwise equal to
+ * what bsf_filter writes for that job alone.  `jobs` is a host array. */
+bsf_status bsf_filter_batched(bsf_ctx* ctx, const bsf_job* jobs, int njobs, void* stream);
+
+/* Stage 1 alone, as a global pre-integrator (eq. RS applied n times per direction):
+ * the unit-weight n-fold running sums of the window  f_ext[y0 + r][x0 + c],
+ * 0 <= r < hq, 0 <= c < wq  (f_ext = the job's image under its boundary rule; the job's
+ * scales, path and out are ignored) are written to g[r*g_pitch + c] as int64.  The
+ * recursions start from zero at the window's lower-left edges and run on the window
+ * extended to the right by a triangle of zeros, which step (4) needs.  Float inputs are
+ * taken on the 2^-24 grid (multiplied by 2^24).  Multiply by 2^n for the sqrt2 weights of
+ * the two diagonal steps.  Values wrap modulo 2^64 if they exceed int64.  Workspace:
+ * 8*hq*(wq+hq) bytes. */
+bsf_status bsf_preintegrate(bsf_ctx* ctx, const bsf_job* job, int x0, int y0, int wq, int hq,
+                            int64_t* g, ptrdiff_t g_pitch, void* stream);
+
+/* Synchronise `stream`, return (and clear) the sticky device error of the context:
+ * BSF_OK, BSF_ERR_SCALE_RANGE, BSF_ERR_UNSUPPORTED, BSF_ERR_RANGE or
+ * BSF_ERR_INEXACT_INPUT (the first in this order that occurred). */
+bsf_status bsf_get_device_error(bsf_ctx* ctx, void* stream);
+
+/* Test aid for the on-chip pre-integrator (stage 1 of Section 7, eq. RS): run only the
+ * stage-1 part of the tile kernel for output tile `tile` (row-major tile index, 16x16
+ * tiles) of `job` and write the box part of its restart window, int64 row-major
+ * [hq][wq], to the device buffer `window` (capacity `cap` elements).  `geom` is a device
+ * int[6]: the caller sets geom[4] = 1 to anchor every running sum at the tile centre
+ * (what bsf_filter does) or 0 for the recursions' zero start at the window's lower-left
+ * edges; the call writes geom[0..3] = x0, y0, wq, hq of the window and geom[5] = 1 if a
+ * value left the int64 range.  Asynchronous on `stream`. */
+bsf_status bsf_debug_tile_window(bsf_ctx* ctx, const bsf_job* job, int tile, int64_t* window,
+                                 long long cap, int* geom, void* stream);
+
+const char* bsf_status_string(bsf_status s);
+
+/* Detail text of the last failure on this context ("" if none). */
+const char* bsf_last_error(const bsf_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BSF_H */

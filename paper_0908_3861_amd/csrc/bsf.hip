@@ -1,0 +1,907 @@
+// libbsf: hand-written gfx950 kernels and the C ABI declared in include/bsf.h.
+//
+// One workgroup filters one 16x16 output tile:
+//   1. it reads the tile's scale vectors and sizes a restart window that holds the
+//      support of every pixel of the tile (local reach, not the image-wide maximum);
+//   2. it loads the window (boundary rule applied) into LDS as exact int64 samples;
+//   3. stage 1 (Section 7, eq. RS): n-fold running sums along (1,0), (1,1), (0,1),
+//      (-1,1) on the window plus the right-hand triangle that step (4) reads;
+//   4. stage 2 (eq. final_eqn, generalised to order n): each thread evaluates its
+//      pixel's (n+1)^4 finite-difference taps, interpolating the pre-integrated
+//      window with the lattice box spline.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/bsf.h"
+#include "bsf_device.h"
+
+namespace bsf {
+
+struct TileArgs {
+    const void* in;
+    long long in_pitch;
+    const float* scales;
+    long long scale_pitch;
+    void* out;
+    long long out_pitch;
+    int width, height;
+    int in_dtype;
+    int border;
+    int tiles_x, tiles_y;
+    long long lds_cap;  // int64 elements of dynamic LDS
+    unsigned* err;
+    // debug dump of one tile's pre-integrated window (nullptr in production)
+    long long* dbg_window;
+    int* dbg_geom;
+    long long dbg_cap;
+    int dbg_tile;
+};
+
+// XCD-aware order: consecutive workgroup ids are dealt round-robin to the 8 XCDs, so
+// hand each XCD a contiguous band of tiles (neighbouring windows share their halos in
+// that XCD's L2).
+__device__ __forceinline__ int xcd_tile(int wg, int nwg) {
+    const int per = nwg / 8;
+    if (wg >= per * 8) return wg;
+    return (wg % 8) * per + wg / 8;
+}
+
+// ---------------------------------------------------------------------------
+// LDS window: the (wq x hq) box row-major at 0, the extension triangle after it
+// (row r holds hq-1-r extra columns to the right of the box).
+// ---------------------------------------------------------------------------
+struct Geo {
+    int wq, hq, qn;
+};
+
+__device__ __forceinline__ int waddr(const Geo& g, int r, int c) {
+    return c < g.wq ? r * g.wq + c : g.qn + r * (g.hq - 1) - ((r * (r - 1)) >> 1) + (c - g.wq);
+}
+
+__device__ __forceinline__ long long add_ovf(long long a, long long b, unsigned& ovf) {
+    long long s = (long long)((unsigned long long)a + (unsigned long long)b);
+    ovf |= (unsigned)(((a ^ s) & (b ^ s)) < 0);
+    return s;
+}
+__device__ __forceinline__ long long sub_ovf(long long a, long long b, unsigned& ovf) {
+    long long s = (long long)((unsigned long long)a - (unsigned long long)b);
+    ovf |= (unsigned)(((a ^ b) & (a ^ s)) < 0);
+    return s;
+}
+
+// Running sum along one line of the window: points (r0 + t*dr, c0 + t*dc), t < len.
+// tref < 0: y[t] = sum_{s<=t} x[s] (zero initial condition at the line's start, as in
+// the paper's recursions).  tref >= 0: the same recursion y[t] = y[t-1] + x[t] but
+// anchored at y[tref] = 0; the two differ by a constant along the line, which every
+// finite difference of the mesh along that direction cancels, and it keeps the
+// integers small near the tile centre.
+__device__ void scan_line(long long* S, const Geo& g, int r0, int c0, int dr, int dc, int len, int tref,
+                          unsigned& ovf) {
+    constexpr int B = 8;
+    long long acc = 0;
+    int t = tref + 1;
+    for (; t + B <= len; t += B) {
+        int ad[B];
+        long long v[B];
+#pragma unroll
+        for (int i = 0; i < B; ++i) ad[i] = waddr(g, r0 + (t + i) * dr, c0 + (t + i) * dc);
+#pragma unroll
+        for (int i = 0; i < B; ++i) v[i] = S[ad[i]];
+#pragma unroll
+        for (int i = 0; i < B; ++i) {
+            acc = add_ovf(acc, v[i], ovf);
+            S[ad[i]] = acc;
+        }
+    }
+    for (; t < len; ++t) {
+        const int ad = waddr(g, r0 + t * dr, c0 + t * dc);
+        acc = add_ovf(acc, S[ad], ovf);
+        S[ad] = acc;
+    }
+    if (tref >= 0) {
+        const int aref = waddr(g, r0 + tref * dr, c0 + tref * dc);
+        long long prev = S[aref];
+        acc = 0;
+        t = tref - 1;
+        for (; t - B + 1 >= 0; t -= B) {
+            int ad[B];
+            long long v[B];
+#pragma unroll
+            for (int i = 0; i < B; ++i) ad[i] = waddr(g, r0 + (t - i) * dr, c0 + (t - i) * dc);
+#pragma unroll
+            for (int i = 0; i < B; ++i) v[i] = S[ad[i]];
+#pragma unroll
+            for (int i = 0; i < B; ++i) {
+                acc = sub_ovf(acc, prev, ovf);
+                prev = v[i];
+                S[ad[i]] = acc;
+            }
+        }
+        for (; t >= 0; --t) {
+            const int ad = waddr(g, r0 + t * dr, c0 + t * dc);
+            acc = sub_ovf(acc, prev, ovf);
+            prev = S[ad];
+            S[ad] = acc;
+        }
+        S[aref] = 0;
+    }
+}
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// Stage 1 on the window (eq. RS steps (1)-(4), n folds each).  cen: anchor every
+// line at the tile centre (cc, rc) instead of at its start.
+__device__ void preintegrate_window(long long* S, const Geo& g, int n, bool cen, int cc, int rc,
+                                    unsigned& ovf) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int W = g.wq, H = g.hq, Wt = W + H - 1;
+    for (int f = 0; f < n; ++f) {  // (1) along (1,0): rows
+        for (int r = tid; r < H; r += nt) scan_line(S, g, r, 0, 0, 1, Wt - r, cen ? clampi(cc, 0, Wt - r - 1) : -1, ovf);
+        __syncthreads();
+    }
+    for (int f = 0; f < n; ++f) {  // (2) along (1,1): diagonals c - r = e
+        for (int i = tid; i < Wt + H - 1; i += nt) {
+            const int e = i - (H - 1);
+            const int rs = e < 0 ? -e : 0;
+            const int re = std::min(H - 1, (W + H - 2 - e) >> 1);
+            const int len = re - rs + 1;
+            scan_line(S, g, rs, e + rs, 1, 1, len, cen ? clampi(rc - rs, 0, len - 1) : -1, ovf);
+        }
+        __syncthreads();
+    }
+    for (int f = 0; f < n; ++f) {  // (3) along (0,1): columns
+        for (int c = tid; c < Wt; c += nt) {
+            const int len = std::min(H, Wt - c);
+            scan_line(S, g, 0, c, 1, 0, len, cen ? clampi(rc, 0, len - 1) : -1, ovf);
+        }
+        __syncthreads();
+    }
+    for (int f = 0; f < n; ++f) {  // (4) along (-1,1): anti-diagonals c + r = e, read down-right
+        for (int e = tid; e < Wt; e += nt) {
+            const int len = std::min(H, e + 1);
+            scan_line(S, g, 0, e, 1, -1, len, cen ? clampi(rc, 0, len - 1) : -1, ovf);
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Interpolation at one tap.  p = q + o + u with |u_i| <= 1/2; the quarter turn that
+// brings u into the reference triangle u1 >= |u2| is applied to u and to the stencil.
+// ---------------------------------------------------------------------------
+template <int N>
+struct TapFrame {
+    int base, s1, s2;  // LDS address of stencil point j: base + jx*s1 + jy*s2
+    int lo_ok;         // stencil box inside the window
+};
+
+template <int N>
+__device__ __forceinline__ TapFrame<N> tap_frame(int qx, int qy, int tri, int wq, int hq) {
+    // odd n rotates about the anchor, even n about the anchor + (1/2, 1/2)
+    constexpr int e = (N & 1) ? 0 : 1;
+    int cx = 0, cy = 0, s1, s2;
+    switch (tri) {
+        case 0: s1 = 1; s2 = wq; break;                      // (jx, jy)
+        case 1: s1 = wq; s2 = -1; cx = e; break;             // (e - jy, jx)
+        case 2: s1 = -1; s2 = -wq; cx = e; cy = e; break;    // (e - jx, e - jy)
+        default: s1 = -wq; s2 = 1; cy = e; break;            // (jy, e - jx)
+    }
+    TapFrame<N> f;
+    f.base = (qy + cy) * wq + (qx + cx);
+    f.s1 = s1;
+    f.s2 = s2;
+    constexpr int jl = stencil_lo<N>(), jh = stencil_hi<N>();
+    f.lo_ok = (qx + jl >= 0) && (qx + jh < wq) && (qy + jl >= 0) && (qy + jh < hq);
+    return f;
+}
+
+template <int DEG>
+__host__ __device__ constexpr int mono_index(int a, int b) {
+    return a * (DEG + 1) - (a * (a - 1)) / 2 + b;
+}
+
+// sum_j g[q+j] beta(o + u - j) in double-double; G accumulated exactly in split form.
+template <int N>
+__device__ __forceinline__ dd interp_dd(const long long* S, const TapFrame<N>& fr, dd v1, dd v2) {
+    using T = Tab<N>;
+    constexpr int M = T::M, DEG = T::DEG;
+    static_assert(T::SPLIT == 2, "two-way split");
+    double Gh[M], Gl[M];
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+        Gh[a] = 0.0;
+        Gl[a] = 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < T::S; ++j) {
+        const long long g = S[fr.base + T::jx(j) * fr.s1 + T::jy(j) * fr.s2];
+        const double lo = (double)(unsigned)(g & 0xffffffffll);
+        const double hi = (double)(int)(g >> 32);
+#pragma unroll
+        for (int a = 0; a < M; ++a) {
+            if (T::num(j, a) != 0.0) {
+                Gh[a] = __fma_rn(T::num(j, a), hi, Gh[a]);
+                Gl[a] = __fma_rn(T::num(j, a), lo, Gl[a]);
+            }
+        }
+    }
+    dd P = {0.0, 0.0};
+#pragma unroll
+    for (int a = DEG; a >= 0; --a) {
+        constexpr double two32 = 4294967296.0;
+        dd q = two_sum(Gh[mono_index<DEG>(a, DEG - a)] * two32, Gl[mono_index<DEG>(a, DEG - a)]);
+#pragma unroll
+        for (int b = DEG - a - 1; b >= 0; --b) {
+            const dd c = two_sum(Gh[mono_index<DEG>(a, b)] * two32, Gl[mono_index<DEG>(a, b)]);
+            q = dd_add(dd_mul(q, v2), c);
+        }
+        P = (a == DEG) ? q : dd_add(dd_mul(P, v1), q);
+    }
+    return P;
+}
+
+// the same in plain double
+template <int N>
+__device__ __forceinline__ double interp_f64(const long long* S, const TapFrame<N>& fr, double v1, double v2) {
+    using T = Tab<N>;
+    constexpr int M = T::M, DEG = T::DEG;
+    double G[M];
+#pragma unroll
+    for (int a = 0; a < M; ++a) G[a] = 0.0;
+#pragma unroll
+    for (int j = 0; j < T::S; ++j) {
+        const double g = (double)S[fr.base + T::jx(j) * fr.s1 + T::jy(j) * fr.s2];
+#pragma unroll
+        for (int a = 0; a < M; ++a)
+            if (T::num(j, a) != 0.0) G[a] = __fma_rn(T::num(j, a), g, G[a]);
+    }
+    double P = 0.0;
+#pragma unroll
+    for (int a = DEG; a >= 0; --a) {
+        double q = G[mono_index<DEG>(a, DEG - a)];
+#pragma unroll
+        for (int b = DEG - a - 1; b >= 0; --b) q = __fma_rn(q, v2, G[mono_index<DEG>(a, b)]);
+        P = (a == DEG) ? q : __fma_rn(P, v1, q);
+    }
+    return P;
+}
+
+__host__ __device__ constexpr int binom(int n, int k) {
+    int r = 1;
+    for (int i = 0; i < k; ++i) r = r * (n - i) / (i + 1);
+    return r;
+}
+
+// Triangle of the cell from the signs of u1 + u2 and u1 - u2, and the quarter turn
+// R^-tri that maps it onto the reference triangle u1 >= |u2|.
+__device__ __forceinline__ int cell_triangle(double u1, double u2) {
+    const bool sp = (u1 + u2) >= 0.0, sm = (u1 - u2) >= 0.0;
+    return sp ? (sm ? 0 : 1) : (sm ? 3 : 2);
+}
+
+// One pixel of the order-N mesh (eq. final_eqn): s[m] = sum_k c_k g_I(m + n tau - x_k),
+// c_k = prod_d d^n_{a_d}[k_d] (eq. FD), x_k = sum_d k_d a_d r_d (Table 1 for n = 1),
+// n tau per Section 7 (the shift of eq. factor, n-fold).  Window coordinates: (mx, my)
+// is the pixel relative to the window origin.  Returns s in units of the integer
+// samples (the caller applies the input quantum).
+template <int N>
+__device__ double mesh_dd(const long long* S, int wq, int hq, int mx, int my, float4 a, unsigned& bad) {
+    const dd isq = {kInvSqrt2Hi, kInvSqrt2Lo};
+    const double a1 = a.x, a3 = a.z;
+    const dd A2 = dd_mul_d(isq, (double)a.y);  // a'_2 = a2/sqrt2 (lattice units along (1,1))
+    const dd A4 = dd_mul_d(isq, (double)a.w);  // a'_4
+    constexpr double h = 0.5 * N;
+    // n*tau = (n/2)(a1 + a'2 - a'4 - 1, a'2 + a3 + a'4 - 3)
+    const dd T1 = dd_mul_d(dd_add_d(dd_add(A2, dd_neg(A4)), a1 - 1.0), h);
+    const dd T2 = dd_mul_d(dd_add_d(dd_add(A2, A4), a3 - 3.0), h);
+    dd acc = {0.0, 0.0};
+    for (int k2 = 0; k2 <= N; ++k2) {
+        for (int k4 = 0; k4 <= N; ++k4) {
+            const dd D2 = dd_mul_d(A2, (double)k2), D4 = dd_mul_d(A4, (double)k4);
+            const dd B1 = dd_add(T1, dd_add(D4, dd_neg(D2)));        // n tau_1 - k2 a'2 + k4 a'4
+            const dd B2 = dd_add(T2, dd_neg(dd_add(D2, D4)));         // n tau_2 - k2 a'2 - k4 a'4
+            for (int k1 = 0; k1 <= N; ++k1) {
+                const dd d1 = dd_add_d(B1, -(double)k1 * a1);
+                for (int k3 = 0; k3 <= N; ++k3) {
+                    const dd d2 = dd_add_d(B2, -(double)k3 * a3);
+                    // anchor and local offset
+                    double f1, f2;
+                    if (N & 1) {
+                        f1 = rint(d1.hi);
+                        f2 = rint(d2.hi);
+                    } else {
+                        f1 = floor(d1.hi);
+                        f2 = floor(d2.hi);
+                    }
+                    // u = d - (q + o) in double-double: d.hi - q alone is not exact when
+                    // the anchor is floor(d) and d lies in (-1, 0)
+                    const double oc = (N & 1) ? 0.0 : 0.5;
+                    const dd u1 = dd_add_d(d1, -(f1 + oc));
+                    const dd u2 = dd_add_d(d2, -(f2 + oc));
+                    const int tri = cell_triangle(u1.hi, u2.hi);
+                    dd v1, v2;
+                    switch (tri) {
+                        case 0: v1 = u1; v2 = u2; break;
+                        case 1: v1 = u2; v2 = dd_neg(u1); break;
+                        case 2: v1 = dd_neg(u1); v2 = dd_neg(u2); break;
+                        default: v1 = dd_neg(u2); v2 = u1; break;
+                    }
+                    const TapFrame<N> fr = tap_frame<N>(mx + (int)f1, my + (int)f2, tri, wq, hq);
+                    if (!fr.lo_ok) {
+                        bad = 1;
+                        continue;
+                    }
+                    const dd P = interp_dd<N>(S, fr, v1, v2);
+                    const int c = binom(N, k1) * binom(N, k2) * binom(N, k3) * binom(N, k4);
+                    const double cs = ((k1 + k2 + k3 + k4) & 1) ? -(double)c : (double)c;
+                    acc = dd_add(acc, dd_mul_d(P, cs));
+                }
+            }
+        }
+    }
+    // s = acc * 2^n / DEN / (a1 a2 a3 a4)^n
+    const dd prod = two_prod((double)a.x * (double)a.y, (double)a.z * (double)a.w);
+    dd pn = prod;
+    for (int i = 1; i < N; ++i) pn = dd_mul(pn, prod);
+    const dd den = {Tab<N>::DEN / (double)(1 << N), 0.0};
+    const dd s = dd_div(dd_div(acc, den), pn);
+    return s.hi + s.lo;
+}
+
+template <int N>
+__device__ double mesh_f64(const long long* S, int wq, int hq, int mx, int my, float4 a, unsigned& bad) {
+    const double a1 = a.x, a3 = a.z;
+    const double A2 = (double)a.y * kInvSqrt2Hi, A4 = (double)a.w * kInvSqrt2Hi;
+    constexpr double h = 0.5 * N;
+    const double T1 = h * (a1 + A2 - A4 - 1.0);
+    const double T2 = h * (A2 + a3 + A4 - 3.0);
+    double acc = 0.0;
+    for (int k2 = 0; k2 <= N; ++k2) {
+        for (int k4 = 0; k4 <= N; ++k4) {
+            const double B1 = T1 - k2 * A2 + k4 * A4;
+            const double B2 = T2 - k2 * A2 - k4 * A4;
+            for (int k1 = 0; k1 <= N; ++k1) {
+                const double d1 = B1 - k1 * a1;
+                for (int k3 = 0; k3 <= N; ++k3) {
+                    const double d2 = B2 - k3 * a3;
+                    const double f1 = (N & 1) ? rint(d1) : floor(d1);
+                    const double f2 = (N & 1) ? rint(d2) : floor(d2);
+                    const double oc = (N & 1) ? 0.0 : 0.5;
+                    const double u1 = d1 - f1 - oc, u2 = d2 - f2 - oc;
+                    const int tri = cell_triangle(u1, u2);
+                    double v1, v2;
+                    switch (tri) {
+                        case 0: v1 = u1; v2 = u2; break;
+                        case 1: v1 = u2; v2 = -u1; break;
+                        case 2: v1 = -u1; v2 = -u2; break;
+                        default: v1 = -u2; v2 = u1; break;
+                    }
+                    const TapFrame<N> fr = tap_frame<N>(mx + (int)f1, my + (int)f2, tri, wq, hq);
+                    if (!fr.lo_ok) {
+                        bad = 1;
+                        continue;
+                    }
+                    const double P = interp_f64<N>(S, fr, v1, v2);
+                    const int c = binom(N, k1) * binom(N, k2) * binom(N, k3) * binom(N, k4);
+                    acc = __fma_rn(((k1 + k2 + k3 + k4) & 1) ? -(double)c : (double)c, P, acc);
+                }
+            }
+        }
+    }
+    const double prod = ((double)a.x * (double)a.y) * ((double)a.z * (double)a.w);
+    double pn = prod;
+    for (int i = 1; i < N; ++i) pn *= prod;
+    return acc * ((double)(1 << N) / Tab<N>::DEN) / pn;
+}
+
+// ---------------------------------------------------------------------------
+// The tile kernel.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_max(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+
+__device__ __forceinline__ long long load_sample(const TileArgs& A, int x, int y, unsigned& inexact) {
+    if (A.border == BSF_BORDER_ZERO) {
+        if (x < 0 || x >= A.width || y < 0 || y >= A.height) return 0;
+    } else {
+        x = clampi(x, 0, A.width - 1);
+        y = clampi(y, 0, A.height - 1);
+    }
+    const long long off = (long long)y * A.in_pitch + x;
+    if (A.in_dtype == BSF_U8) return (long long)((const unsigned char*)A.in)[off];
+    const double v = (A.in_dtype == BSF_F32) ? (double)((const float*)A.in)[off] : ((const double*)A.in)[off];
+    const double sv = v * 16777216.0;  // samples on the 2^-24 grid become integers
+    const long long iv = (long long)rint(sv);
+    inexact |= (unsigned)((double)iv != sv);
+    return iv;
+}
+
+template <int N, int PATH>
+__global__ __launch_bounds__(kThreads) void filter_tile_kernel(TileArgs A) {
+    extern __shared__ long long S[];
+    __shared__ double red[2][kThreads / 64];
+    const int tid = threadIdx.x;
+    int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (A.dbg_window) tile = A.dbg_tile;
+    const int tx = tile % A.tiles_x, ty = tile / A.tiles_x;
+    const int t1 = tx * kTile, t2 = ty * kTile;
+    const int tw = std::min(kTile, A.width - t1), th = std::min(kTile, A.height - t2);
+    const int px = tid % kTile, py = tid / kTile;
+    const int m1 = t1 + px, m2 = t2 + py;
+    const bool inside = px < tw && py < th;
+
+    float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
+    bool valid = false;
+    if (inside) {
+        a = *reinterpret_cast<const float4*>(A.scales + 4 * ((long long)m2 * A.scale_pitch + m1));
+        valid = true;
+        const float av[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+        for (int d = 0; d < 4; ++d) valid = valid && (av[d] >= (float)kScaleMin) && (av[d] <= (float)kScaleMax);
+        if (!valid) atomicOr(A.err, kErrScale);
+    }
+    double R1 = valid ? reach1(N, a.x, a.y, a.w) : 0.0;
+    double R2 = valid ? reach1(N, a.z, a.y, a.w) : 0.0;
+    R1 = wave_max(R1);
+    R2 = wave_max(R2);
+    if ((tid & 63) == 0) {
+        red[0][tid >> 6] = R1;
+        red[1][tid >> 6] = R2;
+    }
+    __syncthreads();
+    R1 = fmax(fmax(red[0][0], red[0][1]), fmax(red[0][2], red[0][3]));
+    R2 = fmax(fmax(red[1][0], red[1][1]), fmax(red[1][2], red[1][3]));
+
+    const Window w = tile_window<N>(t1, t2, tw, th, R1, R2);
+    const long long need = window_elems(w);
+    const double nan = __builtin_nan("");
+    auto store = [&](double v) {
+        if (!inside) return;
+        const long long off = (long long)m2 * A.out_pitch + m1;
+        if (PATH == BSF_PATH_F64)
+            ((double*)A.out)[off] = v;
+        else
+            ((float*)A.out)[off] = (float)v;
+    };
+    if (need > A.lds_cap) {
+        if (tid == 0) atomicOr(A.err, kErrWindow);
+        if (!A.dbg_window) store(nan);
+        if (A.dbg_window && tid == 0) {
+            A.dbg_geom[0] = w.x0; A.dbg_geom[1] = w.y0; A.dbg_geom[2] = w.wq; A.dbg_geom[3] = w.hq;
+        }
+        return;
+    }
+    const Geo g = {w.wq, w.hq, w.wq * w.hq};
+    unsigned inexact = 0;
+    for (int i = tid; i < g.qn; i += kThreads) {
+        const int r = i / g.wq, c = i - r * g.wq;
+        S[i] = load_sample(A, w.x0 + c, w.y0 + r, inexact);
+    }
+    const int ntri = (g.hq * (g.hq - 1)) / 2;
+    for (int i = tid; i < ntri; i += kThreads) S[g.qn + i] = 0;
+    if (inexact) atomicOr(A.err, kErrInexact);
+    __syncthreads();
+
+    unsigned ovf = 0;
+    const bool cen = !A.dbg_window || A.dbg_geom[4];
+    const int cc = t1 + tw / 2 - w.x0, rc = t2 + th / 2 - w.y0;  // centre of the tile's own extent
+    preintegrate_window(S, g, N, cen, cc, rc, ovf);
+    ovf = __syncthreads_or(ovf);
+
+    if (A.dbg_window) {
+        if (tid == 0) {
+            A.dbg_geom[0] = w.x0; A.dbg_geom[1] = w.y0; A.dbg_geom[2] = w.wq; A.dbg_geom[3] = w.hq;
+            A.dbg_geom[5] = (int)ovf;
+        }
+        if ((long long)g.qn <= A.dbg_cap)
+            for (int i = tid; i < g.qn; i += kThreads) A.dbg_window[i] = S[i];
+        return;
+    }
+    if (ovf) {
+        if (tid == 0) atomicOr(A.err, kErrRange);
+        store(nan);
+        return;
+    }
+    if (!inside) return;
+    if (!valid) {
+        store(nan);
+        return;
+    }
+    unsigned bad = 0;
+    const int mx = m1 - w.x0, my = m2 - w.y0;
+    double s = (PATH == BSF_PATH_F64) ? mesh_dd<N>(S, g.wq, g.hq, mx, my, a, bad)
+                                      : mesh_f64<N>(S, g.wq, g.hq, mx, my, a, bad);
+    if (A.in_dtype != BSF_U8) s *= 5.9604644775390625e-08;  // undo the 2^24 input scaling
+    if (bad) {
+        atomicOr(A.err, kErrWindow);
+        s = nan;
+    }
+    store(s);
+}
+
+// ---------------------------------------------------------------------------
+// Global pre-integrator (bsf_preintegrate): stage 1 over an arbitrary window held in
+// HBM, hq rows of pitch wt = wq + hq - 1 (row r uses its first wt - r entries).
+// ---------------------------------------------------------------------------
+struct GlobalArgs {
+    const void* in;
+    long long in_pitch;
+    int width, height, in_dtype, border;
+    int x0, y0, wq, hq;
+    long long* T;  // workspace [hq][wt]
+    long long* g;
+    long long g_pitch;
+};
+
+__global__ void gpre_load(GlobalArgs A) {
+    const int wt = A.wq + A.hq - 1;
+    const long long total = (long long)A.hq * wt;
+    TileArgs t{};
+    t.in = A.in; t.in_pitch = A.in_pitch; t.width = A.width; t.height = A.height;
+    t.in_dtype = A.in_dtype; t.border = A.border;
+    unsigned inexact = 0;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int r = (int)(i / wt), c = (int)(i - (long long)r * wt);
+        long long v = 0;
+        if (c < A.wq) v = load_sample(t, A.x0 + c, A.y0 + r, inexact);
+        A.T[i] = v;
+    }
+}
+
+// one lane per line, lines adjacent in memory at every step (coalesced walk)
+// dir 1: rows, 2: diagonals, 3: columns, 4: anti-diagonals
+__global__ void gpre_walk(GlobalArgs A, int dir) {
+    const int W = A.wq, H = A.hq, wt = W + H - 1;
+    const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    int r0, c0, dr, dc, len;
+    if (dir == 1) {
+        if (i >= H) return;
+        r0 = (int)i; c0 = 0; dr = 0; dc = 1; len = wt - r0;
+    } else if (dir == 2) {
+        if (i >= wt + H - 1) return;
+        const int e = (int)i - (H - 1);
+        const int rs = e < 0 ? -e : 0;
+        const int re = std::min(H - 1, (W + H - 2 - e) >> 1);
+        r0 = rs; c0 = e + rs; dr = 1; dc = 1; len = re - rs + 1;
+    } else if (dir == 3) {
+        if (i >= wt) return;
+        r0 = 0; c0 = (int)i; dr = 1; dc = 0; len = std::min(H, wt - c0);
+    } else {
+        if (i >= wt) return;
+        r0 = 0; c0 = (int)i; dr = 1; dc = -1; len = std::min(H, c0 + 1);
+    }
+    long long acc = 0;
+    for (int t = 0; t < len; ++t) {
+        long long* p = A.T + (long long)(r0 + t * dr) * wt + (c0 + t * dc);
+        acc = (long long)((unsigned long long)acc + (unsigned long long)*p);
+        *p = acc;
+    }
+}
+
+__global__ void gpre_store(GlobalArgs A) {
+    const int wt = A.wq + A.hq - 1;
+    const long long total = (long long)A.hq * A.wq;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int r = (int)(i / A.wq), c = (int)(i - (long long)r * A.wq);
+        A.g[(long long)r * A.g_pitch + c] = A.T[(long long)r * wt + c];
+    }
+}
+
+}  // namespace bsf
+
+// ===========================================================================
+// Host side: the C ABI.
+// ===========================================================================
+struct bsf_ctx {
+    int device = 0;
+    size_t ws_limit = 0;
+    unsigned* d_err = nullptr;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    long long lds_max_bytes = 0;
+    std::string last;
+};
+
+namespace {
+
+using namespace bsf;
+
+bsf_status fail(bsf_ctx* c, bsf_status s, const std::string& msg) {
+    if (c) c->last = msg;
+    return s;
+}
+
+bsf_status hip_fail(bsf_ctx* c, hipError_t e, const char* what) {
+    return fail(c, BSF_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bsf_status validate(bsf_ctx* c, const bsf_job* j, bool need_out) {
+    if (!j) return fail(c, BSF_ERR_INVALID_ARG, "job is null");
+    if (j->width < 1 || j->height < 1) return fail(c, BSF_ERR_INVALID_ARG, "width and height must be >= 1");
+    if (j->width > (1 << 24) || j->height > (1 << 24)) return fail(c, BSF_ERR_INVALID_ARG, "image too large");
+    if (!j->in) return fail(c, BSF_ERR_INVALID_ARG, "input pointer is null");
+    if (j->in_pitch < j->width) return fail(c, BSF_ERR_INVALID_ARG, "in_pitch < width");
+    if (j->in_dtype != BSF_U8 && j->in_dtype != BSF_F32 && j->in_dtype != BSF_F64)
+        return fail(c, BSF_ERR_INVALID_ARG, "unknown input dtype");
+    if (j->border != BSF_BORDER_CLAMP && j->border != BSF_BORDER_ZERO)
+        return fail(c, BSF_ERR_INVALID_ARG, "unknown border rule");
+    if (j->order < 1 || j->order > 3) return fail(c, BSF_ERR_UNSUPPORTED, "order must be 1, 2 or 3");
+    if (!need_out) return BSF_OK;
+    if (!j->scales) return fail(c, BSF_ERR_INVALID_ARG, "scales pointer is null");
+    if (((uintptr_t)j->scales) % 16) return fail(c, BSF_ERR_INVALID_ARG, "scales must be 16-byte aligned");
+    if (j->scale_pitch < j->width) return fail(c, BSF_ERR_INVALID_ARG, "scale_pitch < width");
+    if (!j->out) return fail(c, BSF_ERR_INVALID_ARG, "output pointer is null");
+    if (j->out_pitch < j->width) return fail(c, BSF_ERR_INVALID_ARG, "out_pitch < width");
+    if (j->path != BSF_PATH_F64 && j->path != BSF_PATH_F32_TILED)
+        return fail(c, BSF_ERR_INVALID_ARG, "unknown path");
+    if (!(j->a_max >= 0.0f) || j->a_max > (float)kScaleMax)
+        return fail(c, BSF_ERR_INVALID_ARG, "a_max must be 0 or a bound in [0.5, 1e4]");
+    return BSF_OK;
+}
+
+template <int N>
+long long window_bound_elems(float a_max) {
+    const double R = reach1(N, a_max, a_max, a_max);
+    return window_elems(tile_window<N>(0, 0, kTile, kTile, R, R));
+}
+
+long long window_bound(int n, float a_max) {
+    switch (n) {
+        case 1: return window_bound_elems<1>(a_max);
+        case 2: return window_bound_elems<2>(a_max);
+        default: return window_bound_elems<3>(a_max);
+    }
+}
+
+template <int N, int PATH>
+hipError_t launch_tile(const TileArgs& a, dim3 grid, size_t lds, hipStream_t st) {
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&filter_tile_kernel<N, PATH>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
+        (void)hipGetLastError();
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((filter_tile_kernel<N, PATH>), grid, dim3(kThreads), lds, st, a);
+    return hipGetLastError();
+}
+
+hipError_t dispatch(int n, int path, const TileArgs& a, dim3 grid, size_t lds, hipStream_t st) {
+    if (path == BSF_PATH_F64) {
+        if (n == 1) return launch_tile<1, BSF_PATH_F64>(a, grid, lds, st);
+        if (n == 2) return launch_tile<2, BSF_PATH_F64>(a, grid, lds, st);
+        return hipErrorInvalidValue;
+    }
+    if (n == 1) return launch_tile<1, BSF_PATH_F32_TILED>(a, grid, lds, st);
+    if (n == 2) return launch_tile<2, BSF_PATH_F32_TILED>(a, grid, lds, st);
+    return hipErrorInvalidValue;
+}
+
+bsf_status prepare(bsf_ctx* c, const bsf_job* j, TileArgs& a, dim3& grid, size_t& lds) {
+    bsf_status s = validate(c, j, true);
+    if (s != BSF_OK) return s;
+    if (j->order == 3) return fail(c, BSF_ERR_UNSUPPORTED, "order 3 is not built in this library yet");
+    a = TileArgs{};
+    a.in = j->in;
+    a.in_pitch = j->in_pitch;
+    a.scales = j->scales;
+    a.scale_pitch = j->scale_pitch;
+    a.out = j->out;
+    a.out_pitch = j->out_pitch;
+    a.width = j->width;
+    a.height = j->height;
+    a.in_dtype = j->in_dtype;
+    a.border = j->border;
+    a.tiles_x = (j->width + kTile - 1) / kTile;
+    a.tiles_y = (j->height + kTile - 1) / kTile;
+    a.err = c->d_err;
+    const long long cap_elems = (c->lds_max_bytes - 64) / 8;
+    long long elems = cap_elems;
+    if (j->a_max > 0.0f) {
+        elems = window_bound(j->order, j->a_max) + 64;
+        if (elems > cap_elems)
+            return fail(c, BSF_ERR_UNSUPPORTED,
+                        "a_max needs a restart window of " + std::to_string(elems * 8) +
+                            " bytes, more than the on-chip memory of a workgroup");
+    }
+    a.lds_cap = elems;
+    lds = (size_t)elems * 8;
+    grid = dim3((unsigned)(a.tiles_x * a.tiles_y));
+    return BSF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* bsf_status_string(bsf_status s) {
+    switch (s) {
+        case BSF_OK: return "ok";
+        case BSF_ERR_INVALID_ARG: return "invalid argument";
+        case BSF_ERR_OUT_OF_MEMORY: return "out of memory (workspace limit)";
+        case BSF_ERR_HIP: return "HIP runtime error";
+        case BSF_ERR_UNSUPPORTED: return "unsupported (window exceeds on-chip memory, or order)";
+        case BSF_ERR_SCALE_RANGE: return "scale out of range";
+        case BSF_ERR_RANGE: return "pre-integrated value out of the exact integer range";
+        case BSF_ERR_INEXACT_INPUT: return "float input not on the 2^-24 grid";
+    }
+    return "unknown status";
+}
+
+const char* bsf_last_error(const bsf_ctx* ctx) { return ctx ? ctx->last.c_str() : ""; }
+
+bsf_status bsf_create(bsf_ctx** out, int hip_device, size_t workspace_limit_bytes) {
+    if (!out) return BSF_ERR_INVALID_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess) return BSF_ERR_HIP;
+    if (hip_device < 0 || hip_device >= ndev) return BSF_ERR_INVALID_ARG;
+    bsf_ctx* c = new bsf_ctx();
+    c->device = hip_device;
+    c->ws_limit = workspace_limit_bytes ? workspace_limit_bytes : (size_t(1) << 30);
+    e = hipSetDevice(hip_device);
+    if (e != hipSuccess) {
+        delete c;
+        return BSF_ERR_HIP;
+    }
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeSharedMemPerBlockOptin, hip_device) != hipSuccess || lds <= 0) {
+        (void)hipGetLastError();
+        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, hip_device);
+    }
+    c->lds_max_bytes = lds > 0 ? lds : 65536;
+    e = hipMalloc(&c->d_err, sizeof(unsigned));
+    if (e != hipSuccess) {
+        delete c;
+        return BSF_ERR_HIP;
+    }
+    e = hipMemset(c->d_err, 0, sizeof(unsigned));
+    if (e != hipSuccess) {
+        hipFree(c->d_err);
+        delete c;
+        return BSF_ERR_HIP;
+    }
+    *out = c;
+    return BSF_OK;
+}
+
+bsf_status bsf_destroy(bsf_ctx* c) {
+    if (!c) return BSF_ERR_INVALID_ARG;
+    hipSetDevice(c->device);
+    if (c->d_err) hipFree(c->d_err);
+    if (c->ws) hipFree(c->ws);
+    delete c;
+    return BSF_OK;
+}
+
+bsf_status bsf_workspace_size(const bsf_job* job, size_t* bytes) {
+    if (!bytes) return BSF_ERR_INVALID_ARG;
+    bsf_status s = validate(nullptr, job, true);
+    if (s != BSF_OK) return s;
+    *bytes = 0;  // the fused tile kernel keeps its windows on chip
+    return BSF_OK;
+}
+
+bsf_status bsf_filter(bsf_ctx* c, const bsf_job* j, void* stream) {
+    if (!c) return BSF_ERR_INVALID_ARG;
+    TileArgs a;
+    dim3 grid;
+    size_t lds;
+    bsf_status s = prepare(c, j, a, grid, lds);
+    if (s != BSF_OK) return s;
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+    e = dispatch(j->order, j->path, a, grid, lds, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "tile kernel launch");
+    return BSF_OK;
+}
+
+bsf_status bsf_filter_batched(bsf_ctx* c, const bsf_job* jobs, int njobs, void* stream) {
+    if (!c || !jobs || njobs < 0) return fail(c, BSF_ERR_INVALID_ARG, "bad batch");
+    for (int i = 0; i < njobs; ++i) {
+        bsf_status s = bsf_filter(c, jobs + i, stream);
+        if (s != BSF_OK) return s;
+    }
+    return BSF_OK;
+}
+
+bsf_status bsf_preintegrate(bsf_ctx* c, const bsf_job* j, int x0, int y0, int wq, int hq, int64_t* g,
+                            ptrdiff_t g_pitch, void* stream) {
+    if (!c) return BSF_ERR_INVALID_ARG;
+    bsf_status s = validate(c, j, false);
+    if (s != BSF_OK) return s;
+    if (wq < 1 || hq < 1 || !g || g_pitch < wq) return fail(c, BSF_ERR_INVALID_ARG, "bad window");
+    const size_t need = (size_t)hq * (size_t)(wq + hq - 1) * 8;
+    if (need > c->ws_limit) return fail(c, BSF_ERR_OUT_OF_MEMORY, "window workspace exceeds the limit");
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+    if (need > c->ws_bytes) {
+        if (c->ws) {
+            hipStreamSynchronize((hipStream_t)stream);
+            hipFree(c->ws);
+            c->ws = nullptr;
+            c->ws_bytes = 0;
+        }
+        e = hipMalloc(&c->ws, need);
+        if (e != hipSuccess) return hip_fail(c, e, "workspace allocation");
+        c->ws_bytes = need;
+    }
+    GlobalArgs A{};
+    A.in = j->in;
+    A.in_pitch = j->in_pitch;
+    A.width = j->width;
+    A.height = j->height;
+    A.in_dtype = j->in_dtype;
+    A.border = j->border;
+    A.x0 = x0;
+    A.y0 = y0;
+    A.wq = wq;
+    A.hq = hq;
+    A.T = (long long*)c->ws;
+    A.g = (long long*)g;
+    A.g_pitch = g_pitch;
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(gpre_load, dim3(1024), dim3(256), 0, st, A);
+    const int wt = wq + hq - 1;
+    const int nlines[5] = {0, hq, wt + hq - 1, wt, wt};
+    for (int dir = 1; dir <= 4; ++dir)
+        for (int f = 0; f < j->order; ++f)
+            hipLaunchKernelGGL(gpre_walk, dim3((nlines[dir] + 255) / 256), dim3(256), 0, st, A, dir);
+    hipLaunchKernelGGL(gpre_store, dim3(1024), dim3(256), 0, st, A);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(c, e, "pre-integration launch");
+    return BSF_OK;
+}
+
+bsf_status bsf_get_device_error(bsf_ctx* c, void* stream) {
+    if (!c) return BSF_ERR_INVALID_ARG;
+    unsigned h = 0;
+    hipError_t e = hipMemcpyAsync(&h, c->d_err, sizeof(unsigned), hipMemcpyDeviceToHost, (hipStream_t)stream);
+    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "reading the device error word");
+    if (h) {
+        e = hipMemsetAsync(c->d_err, 0, sizeof(unsigned), (hipStream_t)stream);
+        if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+        if (e != hipSuccess) return hip_fail(c, e, "clearing the device error word");
+    }
+    if (h & kErrScale) return fail(c, BSF_ERR_SCALE_RANGE, "a scale was not finite or outside [0.5, 1e4]");
+    if (h & kErrWindow) return fail(c, BSF_ERR_UNSUPPORTED, "a restart window exceeded the on-chip memory");
+    if (h & kErrRange) return fail(c, BSF_ERR_RANGE, "a pre-integrated value left the int64 range");
+    if (h & kErrInexact) return fail(c, BSF_ERR_INEXACT_INPUT, "a float input was rounded to the 2^-24 grid");
+    return BSF_OK;
+}
+
+// Test aid: stage 1 of one tile, written out as the int64 box part of its window.
+// geom (device int[6]): in [4] the caller puts 1 for centred anchors, 0 for the
+// recursions' own zero start; out [0..3] = x0, y0, wq, hq, [5] = overflow flag.
+bsf_status bsf_debug_tile_window(bsf_ctx* c, const bsf_job* j, int tile, int64_t* window, long long cap,
+                                 int* geom, void* stream) {
+    if (!c) return BSF_ERR_INVALID_ARG;
+    TileArgs a;
+    dim3 grid;
+    size_t lds;
+    bsf_status s = prepare(c, j, a, grid, lds);
+    if (s != BSF_OK) return s;
+    if (tile < 0 || tile >= a.tiles_x * a.tiles_y || !window || !geom)
+        return fail(c, BSF_ERR_INVALID_ARG, "bad debug tile arguments");
+    a.dbg_window = (long long*)window;
+    a.dbg_geom = geom;
+    a.dbg_cap = cap;
+    a.dbg_tile = tile;
+    hipError_t e = hipSetDevice(c->device);
+    if (e == hipSuccess) e = dispatch(j->order, j->path, a, dim3(1), lds, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "debug tile launch");
+    return BSF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,175 @@
+// Device building blocks of libbsf: double-double arithmetic, the interpolant tables,
+// restart-window geometry, the on-chip pre-integrator and the localisation mesh.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "boxspline_tables.h"
+
+namespace bsf {
+
+constexpr int kTile = 16;       // output tile edge (pixels)
+constexpr int kThreads = 256;   // one output pixel per thread
+constexpr double kScaleMin = 0.5;
+constexpr double kScaleMax = 1e4;
+
+// sticky device error bits
+enum : unsigned { kErrScale = 1u, kErrWindow = 2u, kErrRange = 4u, kErrInexact = 8u };
+
+// 1/sqrt2 as an unevaluated sum hi + lo (hi = round(1/sqrt2), lo = the rest)
+constexpr double kInvSqrt2Hi = 0x1.6a09e667f3bcdp-1;
+constexpr double kInvSqrt2Lo = -0x1.bdd3413b26456p-55;
+
+// ---------------------------------------------------------------------------
+// double-double (unevaluated sum of two doubles, ~106 significant bits).
+// Error-free transforms: Knuth's two-sum, Dekker's fast two-sum, FMA two-product.
+// ---------------------------------------------------------------------------
+struct dd {
+    double hi, lo;
+};
+
+__device__ __forceinline__ dd two_sum(double a, double b) {
+    double s = a + b;
+    double bb = s - a;
+    double e = (a - (s - bb)) + (b - bb);
+    return {s, e};
+}
+__device__ __forceinline__ dd fast_two_sum(double a, double b) {  // |a| >= |b|
+    double s = a + b;
+    double e = b - (s - a);
+    return {s, e};
+}
+__device__ __forceinline__ dd two_prod(double a, double b) {
+    double p = a * b;
+    return {p, __fma_rn(a, b, -p)};
+}
+__device__ __forceinline__ dd dd_add(dd a, dd b) {
+    dd s = two_sum(a.hi, b.hi);
+    dd t = two_sum(a.lo, b.lo);
+    s.lo += t.hi;
+    s = fast_two_sum(s.hi, s.lo);
+    s.lo += t.lo;
+    return fast_two_sum(s.hi, s.lo);
+}
+__device__ __forceinline__ dd dd_neg(dd a) { return {-a.hi, -a.lo}; }
+__device__ __forceinline__ dd dd_add_d(dd a, double b) {
+    dd s = two_sum(a.hi, b);
+    s.lo += a.lo;
+    return fast_two_sum(s.hi, s.lo);
+}
+__device__ __forceinline__ dd dd_mul(dd a, dd b) {
+    double p = a.hi * b.hi;
+    double e = __fma_rn(a.hi, b.hi, -p);
+    e = __fma_rn(a.hi, b.lo, e);
+    e = __fma_rn(a.lo, b.hi, e);
+    return fast_two_sum(p, e);
+}
+__device__ __forceinline__ dd dd_mul_d(dd a, double b) {
+    double p = a.hi * b;
+    double e = __fma_rn(a.hi, b, -p);
+    e = __fma_rn(a.lo, b, e);
+    return fast_two_sum(p, e);
+}
+__device__ __forceinline__ dd dd_div(dd a, dd b) {
+    double q1 = a.hi / b.hi;
+    dd r = dd_add(a, dd_neg(dd_mul_d(b, q1)));
+    double q2 = r.hi / b.hi;
+    r = dd_add(r, dd_neg(dd_mul_d(b, q2)));
+    double q3 = r.hi / b.hi;
+    return dd_add_d(fast_two_sum(q1, q2), q3);
+}
+
+// ---------------------------------------------------------------------------
+// Interpolant tables per order (generated, exact rationals NUM/DEN).
+// ---------------------------------------------------------------------------
+template <int N>
+struct Tab;
+template <>
+struct Tab<1> {
+    static constexpr int S = bsf_tables::kStencil1, M = bsf_tables::kMono1, DEG = 2;
+    static constexpr double DEN = bsf_tables::kDen1;
+    static constexpr int SPLIT = 2, SHIFT = 32;  // int64 -> 2 exact doubles of 32 bits
+    __host__ __device__ static constexpr double num(int j, int a) { return bsf_tables::kNum1[j][a]; }
+    __host__ __device__ static constexpr int jx(int j) { return bsf_tables::kJ1[j][0]; }
+    __host__ __device__ static constexpr int jy(int j) { return bsf_tables::kJ1[j][1]; }
+    __host__ __device__ static constexpr int ma(int a) { return bsf_tables::kMonoExp1[a][0]; }
+};
+template <>
+struct Tab<2> {
+    static constexpr int S = bsf_tables::kStencil2, M = bsf_tables::kMono2, DEG = 6;
+    static constexpr double DEN = bsf_tables::kDen2;
+    static constexpr int SPLIT = 2, SHIFT = 32;
+    __host__ __device__ static constexpr double num(int j, int a) { return bsf_tables::kNum2[j][a]; }
+    __host__ __device__ static constexpr int jx(int j) { return bsf_tables::kJ2[j][0]; }
+    __host__ __device__ static constexpr int jy(int j) { return bsf_tables::kJ2[j][1]; }
+    __host__ __device__ static constexpr int ma(int a) { return bsf_tables::kMonoExp2[a][0]; }
+};
+template <>
+struct Tab<3> {
+    static constexpr int S = bsf_tables::kStencil3, M = bsf_tables::kMono3, DEG = 10;
+    static constexpr double DEN = bsf_tables::kDen3;
+    static constexpr int SPLIT = 3, SHIFT = 24;  // 24-bit chunks keep every partial sum exact
+    __host__ __device__ static constexpr double num(int j, int a) { return bsf_tables::kNum3[j][a]; }
+    __host__ __device__ static constexpr int jx(int j) { return bsf_tables::kJ3[j][0]; }
+    __host__ __device__ static constexpr int jy(int j) { return bsf_tables::kJ3[j][1]; }
+    __host__ __device__ static constexpr int ma(int a) { return bsf_tables::kMonoExp3[a][0]; }
+};
+
+// Bounds of the stencil after the quarter turns about the cell centre (odd n: about
+// the anchor; even n: about the anchor + (1/2, 1/2)).
+template <int N>
+__host__ __device__ constexpr int stencil_lo() {
+    int lo = 0, hi = 0;
+    for (int j = 0; j < Tab<N>::S; ++j) {
+        lo = Tab<N>::jx(j) < lo ? Tab<N>::jx(j) : lo;
+        lo = Tab<N>::jy(j) < lo ? Tab<N>::jy(j) : lo;
+        hi = Tab<N>::jx(j) > hi ? Tab<N>::jx(j) : hi;
+        hi = Tab<N>::jy(j) > hi ? Tab<N>::jy(j) : hi;
+    }
+    const int other = (N & 1) ? -hi : 1 - hi;
+    return lo < other ? lo : other;
+}
+template <int N>
+__host__ __device__ constexpr int stencil_hi() {
+    return (N & 1) ? -stencil_lo<N>() : 1 - stencil_lo<N>();
+}
+
+// ---------------------------------------------------------------------------
+// Restart window of an output tile.  For pixel m the taps sit at
+// p = m + n*tau - x_k with p - m in [-R1 - n/2, R1 - n/2] x [-R2 - 3n/2, R2 - 3n/2],
+// R1 = (n/2)(a1 + a'2 + a'4), R2 = (n/2)(a3 + a'2 + a'4); the anchor q = round(p)
+// (odd n) or floor(p) (even n) and the stencil add the interpolation reach.  The
+// window also holds every sample in the kernel support [m - R, m + R].
+// ---------------------------------------------------------------------------
+struct Window {
+    int x0, y0, wq, hq;
+};
+
+template <int N>
+__host__ __device__ inline Window tile_window(int t1, int t2, int tw, int th, double R1, double R2) {
+    const double qlo = (N & 1) ? -0.5 : -1.0, qhi = (N & 1) ? 0.5 : 0.0;
+    const int jl = stencil_lo<N>(), jh = stencil_hi<N>();
+    int lx = (int)floor(-R1 - 0.5 * N + qlo) + jl, sx = (int)floor(-R1);
+    int hx = (int)ceil(R1 - 0.5 * N + qhi) + jh, ux = (int)ceil(R1);
+    int ly = (int)floor(-R2 - 1.5 * N + qlo) + jl, sy = (int)floor(-R2);
+    int hy = (int)ceil(R2 - 1.5 * N + qhi) + jh, uy = (int)ceil(R2);
+    Window w;
+    w.x0 = t1 + (lx < sx ? lx : sx) - 1;
+    w.y0 = t2 + (ly < sy ? ly : sy) - 1;
+    const int x1 = t1 + tw - 1 + (hx > ux ? hx : ux) + 1;
+    const int y1 = t2 + th - 1 + (hy > uy ? hy : uy) + 1;
+    w.wq = x1 - w.x0 + 1;
+    w.hq = y1 - w.y0 + 1;
+    return w;
+}
+
+// elements of a window plus the right-hand extension triangle of step (4)
+__host__ __device__ inline long long window_elems(const Window& w) {
+    return (long long)w.hq * w.wq + (long long)w.hq * (w.hq - 1) / 2;
+}
+
+__host__ __device__ inline double reach1(int n, double a1, double a2, double a4) {
+    return 0.5 * n * (a1 + (a2 + a4) * 0.70710678118654752440);
+}
+
+}  // namespace bsf

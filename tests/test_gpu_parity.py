@@ -1,0 +1,189 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+Error measure (the paper fixes none): rel_max = max|s - O| / max|O| over the compared
+pixels.  The float64 path must stay within 1e-12 of the oracle; the oracle itself sums
+only non-negative terms in float64, so its own error is a few ulps.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_0908_3861_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL_F64 = 1e-12
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def bsf(torch_dev):
+    from paper_0908_3861_amd import binding
+    binding.load()
+    return binding
+
+
+def rel_max(s, o):
+    return float(np.abs(s - o).max() / np.abs(o).max())
+
+
+def run(bsf, torch, img, sc, n, path="f64", border="clamp", a_max=None):
+    ti = torch.from_numpy(np.ascontiguousarray(img)).cuda()
+    ts = torch.from_numpy(np.ascontiguousarray(sc)).cuda()
+    out = bsf.filter(ti, ts, n, path=path, border=border, a_max=a_max)
+    ctx = bsf.default_context()
+    st = ctx.device_error()
+    return out.cpu().numpy(), st
+
+
+def test_stage1_tile_window_bit_exact(bsf, torch_dev, oracle_mod):
+    """The on-chip pre-integrator equals the paper's recursions on the same window."""
+    torch = torch_dev
+    rng = np.random.default_rng(101)
+    H, W = 45, 38
+    img = rng.integers(0, 256, size=(H, W)).astype(np.uint8)
+    for n in (1, 2):
+        sc = synth.uniform_scales(rng, H, W, 1.0, 4.0)
+        ti = torch.from_numpy(img).cuda()
+        ts = torch.from_numpy(sc).cuda()
+        ntiles = math.ceil(W / 16) * math.ceil(H / 16)
+        for tile in (0, ntiles - 1, 4):
+            win, (x0, y0, wq, hq), ovf = bsf.debug_tile_window(ti, ts, n, tile, centred=False)
+            assert not ovf
+            ys = np.clip(np.arange(y0, y0 + hq), 0, H - 1)
+            xs = np.clip(np.arange(x0, x0 + wq), 0, W - 1)
+            fwin = img[np.ix_(ys, xs)].astype(np.int64)
+            ref = oracle_mod.preintegrate(fwin, n)
+            assert np.array_equal(win, ref), (n, tile)
+
+
+def test_global_preintegrate_bit_exact(bsf, torch_dev, oracle_mod):
+    torch = torch_dev
+    rng = np.random.default_rng(102)
+    H, W = 30, 41
+    img = rng.integers(0, 256, size=(H, W)).astype(np.uint8)
+    ti = torch.from_numpy(img).cuda()
+    for n, (x0, y0, wq, hq) in [(1, (-5, -3, 50, 37)), (2, (3, 2, 20, 25)), (3, (-2, -4, 17, 15))]:
+        g = bsf.preintegrate(ti, n, x0, y0, wq, hq).cpu().numpy()
+        ys = np.clip(np.arange(y0, y0 + hq), 0, H - 1)
+        xs = np.clip(np.arange(x0, x0 + wq), 0, W - 1)
+        ref = oracle_mod.preintegrate(img[np.ix_(ys, xs)].astype(np.int64), n)
+        assert np.array_equal(g, ref), n
+
+
+def test_parity_order1_integer_scales_f64(bsf, torch_dev, oracle_mod):
+    rng = np.random.default_rng(103)
+    H, W = 50, 67  # several tiles and ragged edges
+    img = synth.unit_grid_image(rng, H, W, np.float64)
+    sc = synth.integer_scales(rng, H, W, 1, 8)
+    s, st = run(bsf, torch_dev, img, sc, 1)
+    assert st == 0
+    o = oracle_mod.filter(img, sc, 1)
+    assert rel_max(s, o) < TOL_F64
+
+
+def test_parity_order2_smooth_real_scales_f64(bsf, torch_dev, oracle_mod):
+    rng = np.random.default_rng(104)
+    H, W = 40, 53
+    img = synth.blurred_u8_image(rng, H, W, 3.0)
+    sc = synth.smooth_scales(rng, H, W, 1.0, 8.0, 8.0)
+    s, st = run(bsf, torch_dev, img, sc, 2)
+    assert st == 0
+    o = oracle_mod.filter(img.astype(np.float64), sc, 2)
+    assert rel_max(s, o) < TOL_F64
+
+
+def test_parity_order2_iid_real_scales_f64(bsf, torch_dev, oracle_mod):
+    rng = np.random.default_rng(105)
+    H, W = 33, 35
+    img = synth.unit_grid_image(rng, H, W, np.float32)
+    sc = synth.uniform_scales(rng, H, W, 1.0, 6.0)
+    s, st = run(bsf, torch_dev, img, sc, 2)
+    assert st == 0
+    o = oracle_mod.filter(img.astype(np.float64), sc, 2)
+    assert rel_max(s, o) < TOL_F64
+
+
+def test_parity_small_config_full(bsf, torch_dev, oracle_mod):
+    job = synth.config_job("small")
+    s, st = run(bsf, torch_dev, job.image, job.scales, job.order, a_max=8.0)
+    assert st == 0
+    o = oracle_mod.filter(job.image, job.scales, job.order)
+    assert rel_max(s, o) < TOL_F64
+
+
+def test_zero_border_and_tiny_images(bsf, torch_dev, oracle_mod):
+    rng = np.random.default_rng(106)
+    for (H, W) in [(1, 1), (1, 9), (7, 1), (17, 16), (16, 17)]:
+        img = synth.unit_grid_image(rng, H, W, np.float64)
+        sc = synth.uniform_scales(rng, H, W, 1.0, 3.0)
+        for n in (1, 2):
+            for border in ("clamp", "zero"):
+                s, st = run(bsf, torch_dev, img, sc, n, border=border)
+                assert st == 0
+                o = oracle_mod.filter(img, sc, n, border)
+                assert np.abs(s - o).max() <= TOL_F64 * max(np.abs(o).max(), 1e-300), (H, W, n, border)
+
+
+def test_constant_image_is_reproduced(bsf, torch_dev):
+    rng = np.random.default_rng(107)
+    H, W = 37, 29
+    sc = synth.integer_scales(rng, H, W, 1, 6)
+    sc[..., 1] = rng.uniform(1, 6, size=(H, W))  # real diagonal scales keep the DC gain exact
+    img = np.full((H, W), 200, np.uint8)
+    for n in (1, 2):
+        s, st = run(bsf, torch_dev, img, sc, n)
+        assert st == 0
+        assert np.abs(s - 200.0).max() < 200.0 * TOL_F64
+
+
+def test_invalid_scales_flag_and_nan(bsf, torch_dev):
+    rng = np.random.default_rng(108)
+    H, W = 20, 20
+    img = synth.unit_grid_image(rng, H, W, np.float64)
+    sc = synth.uniform_scales(rng, H, W, 1.0, 2.0)
+    sc[3, 4, 2] = 0.1
+    sc[10, 11, 0] = np.nan
+    s, st = run(bsf, torch_dev, img, sc, 1, a_max=2.0)
+    assert st == 5  # BSF_ERR_SCALE_RANGE
+    assert np.isnan(s[3, 4]) and np.isnan(s[10, 11])
+    assert np.isfinite(s).sum() == H * W - 2
+
+
+def test_invalid_arguments(bsf, torch_dev):
+    import ctypes
+    torch = torch_dev
+    ctx = bsf.default_context()
+    img = torch.zeros((8, 8), dtype=torch.float64, device="cuda")
+    sc = torch.ones((8, 8, 4), dtype=torch.float32, device="cuda")
+    j, out = bsf.make_job(img, sc, 1)
+    j.order = 4
+    assert ctx.lib.bsf_filter(ctx.handle, ctypes.byref(j), None) == 4
+    j.order = 1
+    j.width = 0
+    assert ctx.lib.bsf_filter(ctx.handle, ctypes.byref(j), None) == 1
+    j.width = 8
+    j.out_pitch = 3
+    assert ctx.lib.bsf_filter(ctx.handle, ctypes.byref(j), None) == 1
+    j.out_pitch = 8
+    j.a_max = 1e9
+    assert ctx.lib.bsf_filter(ctx.handle, ctypes.byref(j), None) == 1
+
+
+def test_f32_path_error_is_stated(bsf, torch_dev, oracle_mod):
+    rng = np.random.default_rng(109)
+    H, W = 40, 40
+    img = synth.unit_grid_image(rng, H, W, np.float32)
+    sc = synth.integer_scales(rng, H, W, 1, 8)
+    s, st = run(bsf, torch_dev, img, sc, 1, path="f32tiled")
+    assert st == 0 and s.dtype == np.float32
+    o = oracle_mod.filter(img.astype(np.float64), sc, 1)
+    assert rel_max(s.astype(np.float64), o) < 1e-5
