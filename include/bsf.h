@@ -26,6 +26,11 @@
  *   - Every pointer in a bsf_job is a device pointer owned by the caller.  Calls are
  *     asynchronous on the given stream (a hipStream_t passed as void*, NULL = default
  *     stream) and the caller keeps the buffers alive until the stream reaches them.
+ *   - Samples enter the pre-integrator as exact integers: each tile scales its window by the
+ *     power of two that makes every sample an integer of at most 53 bits (float samples
+ *     finer than 2^-53 of the window's largest magnitude are rounded to that grid).  When
+ *     the running sums of those integers would leave int64, the tile runs stage 1 and the
+ *     mesh on K base-2^B digits of the samples and adds the results (the filter is linear).
  *   - No call throws.  Argument errors are reported synchronously; errors found by the
  *     kernels (scale values out of range, a window larger than the chip's LDS, integer
  *     range) set sticky device flags returned by bsf_get_device_error, and the affected
@@ -51,7 +56,7 @@ typedef enum {
     BSF_ERR_UNSUPPORTED = 4,   /* a restart window does not fit the on-chip memory        */
     BSF_ERR_SCALE_RANGE = 5,   /* a scale is not finite or lies outside [0.5, 1e4]        */
     BSF_ERR_RANGE = 6,         /* a pre-integrated value left the exact integer range     */
-    BSF_ERR_INEXACT_INPUT = 7  /* a float input was not on the 2^-24 grid (it was rounded) */
+    BSF_ERR_INEXACT_INPUT = 7  /* reserved (not raised)                                     */
 } bsf_status;
 
 typedef enum { BSF_U8 = 0, BSF_F32 = 1, BSF_F64 = 2 } bsf_dtype;
@@ -115,8 +120,8 @@ bsf_status bsf_preintegrate(bsf_ctx* ctx, const bsf_job* job, int x0, int y0, in
                             int64_t* g, ptrdiff_t g_pitch, void* stream);
 
 /* Synchronise `stream`, return (and clear) the sticky device error of the context:
- * BSF_OK, BSF_ERR_SCALE_RANGE, BSF_ERR_UNSUPPORTED, BSF_ERR_RANGE or
- * BSF_ERR_INEXACT_INPUT (the first in this order that occurred). */
+ * BSF_OK, BSF_ERR_SCALE_RANGE, BSF_ERR_UNSUPPORTED or BSF_ERR_RANGE (the first in this
+ * order that occurred). */
 bsf_status bsf_get_device_error(bsf_ctx* ctx, void* stream);
 
 /* Test aid for the on-chip pre-integrator (stage 1 of Section 7, eq. RS): run only the

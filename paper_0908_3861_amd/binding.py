@@ -232,10 +232,10 @@ def debug_tile_window(img, scales, order: int, tile: int, centred: bool, path: s
     ctx = ctx or default_context(img.device.index)
     j, _ = make_job(img, scales, order, path, border, None, None)
     win = torch.zeros(cap, dtype=torch.int64, device=img.device)
-    geom = torch.zeros(6, dtype=torch.int32, device=img.device)
+    geom = torch.zeros(8, dtype=torch.int32, device=img.device)
     geom[4] = 1 if centred else 0
     ctx._check(ctx.lib.bsf_debug_tile_window(ctx.handle, ctypes.byref(j), int(tile), win.data_ptr(), cap,
                                              geom.data_ptr(), _stream_ptr()))
     torch.cuda.synchronize()
-    x0, y0, wq, hq, _, ovf = [int(v) for v in geom.cpu()]
+    x0, y0, wq, hq, _, ovf, sh, _ = [int(v) for v in geom.cpu()]
     return win[: wq * hq].view(hq, wq).cpu().numpy(), (x0, y0, wq, hq), bool(ovf)

@@ -205,68 +205,234 @@ __host__ __device__ constexpr int mono_index(int a, int b) {
     return a * (DEG + 1) - (a * (a - 1)) / 2 + b;
 }
 
-// sum_j g[q+j] beta(o + u - j) in double-double; G accumulated exactly in split form.
-template <int N>
-__device__ __forceinline__ dd interp_dd(const long long* S, const TapFrame<N>& fr, dd v1, dd v2) {
-    using T = Tab<N>;
-    constexpr int M = T::M, DEG = T::DEG;
-    static_assert(T::SPLIT == 2, "two-way split");
-    double Gh[M], Gl[M];
+// Exact integer -> PARTS doubles of SHIFT bits each (the top part keeps the sign), so
+// that every product with a table numerator and every partial sum stays exact.
+template <int PARTS, int SHIFT>
+__device__ __forceinline__ void split_int(long long x, double (&p)[PARTS]) {
+    if constexpr (PARTS == 1) {
+        p[0] = (double)x;
+    } else {
+        constexpr long long mask = (1ll << SHIFT) - 1;
 #pragma unroll
-    for (int a = 0; a < M; ++a) {
-        Gh[a] = 0.0;
-        Gl[a] = 0.0;
+        for (int i = 0; i + 1 < PARTS; ++i) p[i] = (double)((x >> (i * SHIFT)) & mask);
+        p[PARTS - 1] = (double)(x >> ((PARTS - 1) * SHIFT));
     }
+}
+
+template <int PARTS, int SHIFT>
+__device__ __forceinline__ cp join_parts(const double* g) {
+    if constexpr (PARTS == 1) {
+        return {g[0], 0.0};
+    } else if constexpr (PARTS == 2) {
+        const dd t = two_sum(g[1] * (double)(1ll << SHIFT), g[0]);
+        return {t.hi, t.lo};
+    } else {
+        const dd t = dd_add_d(two_sum(g[2] * (double)(1ll << (2 * SHIFT)), g[1] * (double)(1ll << SHIFT)), g[0]);
+        return {t.hi, t.lo};
+    }
+}
+
+// G_alpha = sum_j NUM[j][alpha] g[q + R j] for the monomials u1^a u2^b with ALO <= a <= AHI,
+// in PARTS exact partial sums.  Mirror pairs (j, j') enter once, as g + g' for even b
+// and g - g' for odd b.
+template <int N, int PARTS, int SHIFT, int ALO, int AHI>
+__device__ __forceinline__ void accumulate_chunk(const long long* S, const TapFrame<N>& fr,
+                                                 double (&G)[PARTS][mono_index<Tab<N>::DEG>(AHI, Tab<N>::DEG - AHI) -
+                                                                    mono_index<Tab<N>::DEG>(ALO, 0) + 1],
+                                                 unsigned& bad) {
+    using T = Tab<N>;
+    constexpr int DEG = T::DEG;
+    constexpr int M0 = mono_index<DEG>(ALO, 0);
+    constexpr int CM = mono_index<DEG>(AHI, DEG - AHI) - M0 + 1;
+#pragma unroll
+    for (int p = 0; p < PARTS; ++p)
+#pragma unroll
+        for (int c = 0; c < CM; ++c) G[p][c] = 0.0;
 #pragma unroll
     for (int j = 0; j < T::S; ++j) {
-        const long long g = S[fr.base + T::jx(j) * fr.s1 + T::jy(j) * fr.s2];
-        const double lo = (double)(unsigned)(g & 0xffffffffll);
-        const double hi = (double)(int)(g >> 32);
+        if (!is_rep<N>(j)) continue;
+        const int jm = mirror_of<N>(j);
+        const long long g1 = S[fr.base + T::jx(j) * fr.s1 + T::jy(j) * fr.s2];
+        if (jm == j) {
+            double x[PARTS];
+            split_int<PARTS, SHIFT>(g1, x);
 #pragma unroll
-        for (int a = 0; a < M; ++a) {
-            if (T::num(j, a) != 0.0) {
-                Gh[a] = __fma_rn(T::num(j, a), hi, Gh[a]);
-                Gl[a] = __fma_rn(T::num(j, a), lo, Gl[a]);
+            for (int c = 0; c < CM; ++c)
+                if (T::num(j, M0 + c) != 0.0)
+#pragma unroll
+                    for (int p = 0; p < PARTS; ++p) G[p][c] = __fma_rn(T::num(j, M0 + c), x[p], G[p][c]);
+        } else {
+            const long long g2 = S[fr.base + T::jx(jm) * fr.s1 + T::jy(jm) * fr.s2];
+            double xs[PARTS], xd[PARTS];
+            split_int<PARTS, SHIFT>(add_ovf(g1, g2, bad), xs);
+            split_int<PARTS, SHIFT>(sub_ovf(g1, g2, bad), xd);
+#pragma unroll
+            for (int c = 0; c < CM; ++c)
+                if (T::num(j, M0 + c) != 0.0) {
+                    const bool odd = T::mb(M0 + c) & 1;
+#pragma unroll
+                    for (int p = 0; p < PARTS; ++p)
+                        G[p][c] = __fma_rn(T::num(j, M0 + c), odd ? xd[p] : xs[p], G[p][c]);
+                }
+        }
+    }
+}
+
+// Order 3: the same accumulation with a runtime loop over the stencil (the table rows are
+// uniform across the wave and come from constant memory).  Fully unrolled, order 3 would
+// be tens of thousands of instructions per variant.
+struct MirrorTab3 {
+    int m[bsf_tables::kStencil3];
+    constexpr MirrorTab3() : m() {
+        for (int j = 0; j < bsf_tables::kStencil3; ++j) m[j] = mirror_of<3>(j);
+    }
+};
+__constant__ double c_num3[bsf_tables::kStencil3][bsf_tables::kMono3] = BSF_NUM3_INIT;
+__constant__ int c_j3[bsf_tables::kStencil3][2] = BSF_J3_INIT;
+__constant__ MirrorTab3 c_mirror3 = MirrorTab3();
+
+template <int PARTS, int SHIFT, int ALO, int AHI>
+__device__ __forceinline__ void accumulate_chunk3(const long long* S, const TapFrame<3>& fr,
+                                                  double (&G)[PARTS][mono_index<10>(AHI, 10 - AHI) -
+                                                                     mono_index<10>(ALO, 0) + 1],
+                                                  unsigned& bad) {
+    using T = Tab<3>;
+    constexpr int M0 = mono_index<10>(ALO, 0);
+    constexpr int CM = mono_index<10>(AHI, 10 - AHI) - M0 + 1;
+    asm volatile("" ::: "memory");  // keep each chunk's LDS reads local to the chunk
+#pragma unroll
+    for (int p = 0; p < PARTS; ++p)
+#pragma unroll
+        for (int c = 0; c < CM; ++c) G[p][c] = 0.0;
+#pragma unroll 1
+    for (int j = 0; j < T::S; ++j) {
+        const int jy = c_j3[j][1];
+        if (jy < 0) continue;  // odd order: representatives have jy >= 0
+        const int jx = c_j3[j][0];
+        const long long g1 = S[fr.base + jx * fr.s1 + jy * fr.s2];
+        if (jy == 0) {
+            double x[PARTS];
+            split_int<PARTS, SHIFT>(g1, x);
+#pragma unroll
+            for (int c = 0; c < CM; ++c) {
+                const double w = c_num3[j][M0 + c];
+#pragma unroll
+                for (int p = 0; p < PARTS; ++p) G[p][c] = __fma_rn(w, x[p], G[p][c]);
+            }
+        } else {
+            const long long g2 = S[fr.base + jx * fr.s1 - jy * fr.s2];
+            double xs[PARTS], xd[PARTS];
+            split_int<PARTS, SHIFT>(add_ovf(g1, g2, bad), xs);
+            split_int<PARTS, SHIFT>(sub_ovf(g1, g2, bad), xd);
+#pragma unroll
+            for (int c = 0; c < CM; ++c) {
+                const double w = c_num3[j][M0 + c];
+#pragma unroll
+                for (int p = 0; p < PARTS; ++p)
+                    G[p][c] = __fma_rn(w, (T::mb(M0 + c) & 1) ? xd[p] : xs[p], G[p][c]);
             }
         }
     }
-    dd P = {0.0, 0.0};
+}
+
+// Horner over the chunk's u1-powers AHI..ALO (compensated), continuing the running value P.
+template <int N, int PARTS, int SHIFT, int ALO, int AHI, bool FIRST>
+__device__ __forceinline__ void horner_chunk_dd(
+    const double (&G)[PARTS][mono_index<Tab<N>::DEG>(AHI, Tab<N>::DEG - AHI) - mono_index<Tab<N>::DEG>(ALO, 0) + 1],
+    dd v1, dd v2, cp& P) {
+    constexpr int DEG = Tab<N>::DEG;
+    constexpr int M0 = mono_index<DEG>(ALO, 0);
 #pragma unroll
-    for (int a = DEG; a >= 0; --a) {
-        constexpr double two32 = 4294967296.0;
-        dd q = two_sum(Gh[mono_index<DEG>(a, DEG - a)] * two32, Gl[mono_index<DEG>(a, DEG - a)]);
+    for (int a = AHI; a >= ALO; --a) {
+        double c[PARTS];
+#pragma unroll
+        for (int p = 0; p < PARTS; ++p) c[p] = G[p][mono_index<DEG>(a, DEG - a) - M0];
+        cp q = join_parts<PARTS, SHIFT>(c);
 #pragma unroll
         for (int b = DEG - a - 1; b >= 0; --b) {
-            const dd c = two_sum(Gh[mono_index<DEG>(a, b)] * two32, Gl[mono_index<DEG>(a, b)]);
-            q = dd_add(dd_mul(q, v2), c);
+#pragma unroll
+            for (int p = 0; p < PARTS; ++p) c[p] = G[p][mono_index<DEG>(a, b) - M0];
+            q = cp_horner(q, v2, join_parts<PARTS, SHIFT>(c));
         }
-        P = (a == DEG) ? q : dd_add(dd_mul(P, v1), q);
+        P = (FIRST && a == AHI) ? q : cp_horner(P, v1, q);
+    }
+}
+
+template <int N, int ALO, int AHI, bool FIRST>
+__device__ __forceinline__ void horner_chunk_f64(
+    const double (&G)[1][mono_index<Tab<N>::DEG>(AHI, Tab<N>::DEG - AHI) - mono_index<Tab<N>::DEG>(ALO, 0) + 1],
+    double v1, double v2, double& P) {
+    constexpr int DEG = Tab<N>::DEG;
+    constexpr int M0 = mono_index<DEG>(ALO, 0);
+#pragma unroll
+    for (int a = AHI; a >= ALO; --a) {
+        double q = G[0][mono_index<DEG>(a, DEG - a) - M0];
+#pragma unroll
+        for (int b = DEG - a - 1; b >= 0; --b) q = __fma_rn(q, v2, G[0][mono_index<DEG>(a, b) - M0]);
+        P = (FIRST && a == AHI) ? q : __fma_rn(P, v1, q);
+    }
+}
+
+template <int N, int ALO, int AHI, bool FIRST>
+__device__ __forceinline__ void interp_chunk_dd(const long long* S, const TapFrame<N>& fr, dd v1, dd v2, cp& P,
+                                                unsigned& bad) {
+    using T = Tab<N>;
+    double G[T::SPLIT][mono_index<T::DEG>(AHI, T::DEG - AHI) - mono_index<T::DEG>(ALO, 0) + 1];
+    if constexpr (N == 3)
+        accumulate_chunk3<T::SPLIT, T::SHIFT, ALO, AHI>(S, fr, G, bad);
+    else
+        accumulate_chunk<N, T::SPLIT, T::SHIFT, ALO, AHI>(S, fr, G, bad);
+    horner_chunk_dd<N, T::SPLIT, T::SHIFT, ALO, AHI, FIRST>(G, v1, v2, P);
+}
+
+template <int N, int ALO, int AHI, bool FIRST>
+__device__ __forceinline__ void interp_chunk_f64(const long long* S, const TapFrame<N>& fr, double v1, double v2,
+                                                 double& P, unsigned& bad) {
+    using T = Tab<N>;
+    double G[1][mono_index<T::DEG>(AHI, T::DEG - AHI) - mono_index<T::DEG>(ALO, 0) + 1];
+    if constexpr (N == 3)
+        accumulate_chunk3<1, 0, ALO, AHI>(S, fr, G, bad);
+    else
+        accumulate_chunk<N, 1, 0, ALO, AHI>(S, fr, G, bad);
+    horner_chunk_f64<N, ALO, AHI, FIRST>(G, v1, v2, P);
+}
+
+// sum_j g[q+j] beta(o + u - j) = (1/DEN) sum_alpha G_alpha v^alpha: double-double with the
+// coefficients accumulated exactly (order 3 in three u1-chunks to bound registers).
+template <int N>
+__device__ __forceinline__ cp interp_dd(const long long* S, const TapFrame<N>& fr, dd v1, dd v2, unsigned& bad) {
+    using T = Tab<N>;
+    cp P = {0.0, 0.0};
+    if constexpr (N < 3) {
+        double G[T::SPLIT][T::M];
+        accumulate_chunk<N, T::SPLIT, T::SHIFT, 0, T::DEG>(S, fr, G, bad);
+        horner_chunk_dd<N, T::SPLIT, T::SHIFT, 0, T::DEG, true>(G, v1, v2, P);
+    } else {
+        interp_chunk_dd<N, 7, 10, true>(S, fr, v1, v2, P, bad);
+        interp_chunk_dd<N, 5, 6, false>(S, fr, v1, v2, P, bad);
+        interp_chunk_dd<N, 3, 4, false>(S, fr, v1, v2, P, bad);
+        interp_chunk_dd<N, 2, 2, false>(S, fr, v1, v2, P, bad);
+        interp_chunk_dd<N, 0, 1, false>(S, fr, v1, v2, P, bad);
     }
     return P;
 }
 
 // the same in plain double
 template <int N>
-__device__ __forceinline__ double interp_f64(const long long* S, const TapFrame<N>& fr, double v1, double v2) {
+__device__ __forceinline__ double interp_f64(const long long* S, const TapFrame<N>& fr, double v1, double v2,
+                                             unsigned& bad) {
     using T = Tab<N>;
-    constexpr int M = T::M, DEG = T::DEG;
-    double G[M];
-#pragma unroll
-    for (int a = 0; a < M; ++a) G[a] = 0.0;
-#pragma unroll
-    for (int j = 0; j < T::S; ++j) {
-        const double g = (double)S[fr.base + T::jx(j) * fr.s1 + T::jy(j) * fr.s2];
-#pragma unroll
-        for (int a = 0; a < M; ++a)
-            if (T::num(j, a) != 0.0) G[a] = __fma_rn(T::num(j, a), g, G[a]);
-    }
     double P = 0.0;
-#pragma unroll
-    for (int a = DEG; a >= 0; --a) {
-        double q = G[mono_index<DEG>(a, DEG - a)];
-#pragma unroll
-        for (int b = DEG - a - 1; b >= 0; --b) q = __fma_rn(q, v2, G[mono_index<DEG>(a, b)]);
-        P = (a == DEG) ? q : __fma_rn(P, v1, q);
+    if constexpr (N < 3) {
+        double G[1][T::M];
+        accumulate_chunk<N, 1, 0, 0, T::DEG>(S, fr, G, bad);
+        horner_chunk_f64<N, 0, T::DEG, true>(G, v1, v2, P);
+    } else {
+        interp_chunk_f64<N, 7, 10, true>(S, fr, v1, v2, P, bad);
+        interp_chunk_f64<N, 5, 6, false>(S, fr, v1, v2, P, bad);
+        interp_chunk_f64<N, 3, 4, false>(S, fr, v1, v2, P, bad);
+        interp_chunk_f64<N, 2, 2, false>(S, fr, v1, v2, P, bad);
+        interp_chunk_f64<N, 0, 1, false>(S, fr, v1, v2, P, bad);
     }
     return P;
 }
@@ -290,7 +456,7 @@ __device__ __forceinline__ int cell_triangle(double u1, double u2) {
 // is the pixel relative to the window origin.  Returns s in units of the integer
 // samples (the caller applies the input quantum).
 template <int N>
-__device__ double mesh_dd(const long long* S, int wq, int hq, int mx, int my, float4 a, unsigned& bad) {
+__device__ dd mesh_dd(const long long* S, int wq, int hq, int mx, int my, float4 a, unsigned& bad) {
     const dd isq = {kInvSqrt2Hi, kInvSqrt2Lo};
     const double a1 = a.x, a3 = a.z;
     const dd A2 = dd_mul_d(isq, (double)a.y);  // a'_2 = a2/sqrt2 (lattice units along (1,1))
@@ -299,7 +465,7 @@ __device__ double mesh_dd(const long long* S, int wq, int hq, int mx, int my, fl
     // n*tau = (n/2)(a1 + a'2 - a'4 - 1, a'2 + a3 + a'4 - 3)
     const dd T1 = dd_mul_d(dd_add_d(dd_add(A2, dd_neg(A4)), a1 - 1.0), h);
     const dd T2 = dd_mul_d(dd_add_d(dd_add(A2, A4), a3 - 3.0), h);
-    dd acc = {0.0, 0.0};
+    cp acc = {0.0, 0.0};
     for (int k2 = 0; k2 <= N; ++k2) {
         for (int k4 = 0; k4 <= N; ++k4) {
             const dd D2 = dd_mul_d(A2, (double)k2), D4 = dd_mul_d(A4, (double)k4);
@@ -336,25 +502,31 @@ __device__ double mesh_dd(const long long* S, int wq, int hq, int mx, int my, fl
                         bad = 1;
                         continue;
                     }
-                    const dd P = interp_dd<N>(S, fr, v1, v2);
+                    const cp P = interp_dd<N>(S, fr, v1, v2, bad);
                     const int c = binom(N, k1) * binom(N, k2) * binom(N, k3) * binom(N, k4);
                     const double cs = ((k1 + k2 + k3 + k4) & 1) ? -(double)c : (double)c;
-                    acc = dd_add(acc, dd_mul_d(P, cs));
+                    acc = cp_axpy(acc, cs, P);
                 }
             }
         }
     }
-    // s = acc * 2^n / DEN / (a1 a2 a3 a4)^n
-    const dd prod = two_prod((double)a.x * (double)a.y, (double)a.z * (double)a.w);
+    return fast_two_sum(acc.s, acc.c);
+}
+
+// s = acc * 2^n / DEN / (a1 a2 a3 a4)^n  (the sqrt2 weights of the two diagonal running
+// sums, the table denominator and the finite-difference weights d^n_a of eq. FD)
+template <int N>
+__device__ double finalize_dd(dd acc, float4 a) {
+    const dd prod = two_prod((double)a.x * (double)a.y, (double)a.z * (double)a.w);  // exact
     dd pn = prod;
     for (int i = 1; i < N; ++i) pn = dd_mul(pn, prod);
     const dd den = {Tab<N>::DEN / (double)(1 << N), 0.0};
-    const dd s = dd_div(dd_div(acc, den), pn);
-    return s.hi + s.lo;
+    const dd r = dd_div(dd_div(acc, den), pn);
+    return r.hi + r.lo;
 }
 
 template <int N>
-__device__ double mesh_f64(const long long* S, int wq, int hq, int mx, int my, float4 a, unsigned& bad) {
+__device__ double mesh_f64(const long long* S, int wq, int hq, int mx, int my, float4 a, unsigned& bad) {  // raw sum
     const double a1 = a.x, a3 = a.z;
     const double A2 = (double)a.y * kInvSqrt2Hi, A4 = (double)a.w * kInvSqrt2Hi;
     constexpr double h = 0.5 * N;
@@ -386,13 +558,18 @@ __device__ double mesh_f64(const long long* S, int wq, int hq, int mx, int my, f
                         bad = 1;
                         continue;
                     }
-                    const double P = interp_f64<N>(S, fr, v1, v2);
+                    const double P = interp_f64<N>(S, fr, v1, v2, bad);
                     const int c = binom(N, k1) * binom(N, k2) * binom(N, k3) * binom(N, k4);
                     acc = __fma_rn(((k1 + k2 + k3 + k4) & 1) ? -(double)c : (double)c, P, acc);
                 }
             }
         }
     }
+    return acc;
+}
+
+template <int N>
+__device__ double finalize_f64(double acc, float4 a) {
     const double prod = ((double)a.x * (double)a.y) * ((double)a.z * (double)a.w);
     double pn = prod;
     for (int i = 1; i < N; ++i) pn *= prod;
@@ -407,26 +584,61 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
-__device__ __forceinline__ long long load_sample(const TileArgs& A, int x, int y, unsigned& inexact) {
+// One input sample under the boundary rule, as a double (exact for u8, f32 and f64).
+__device__ __forceinline__ double load_sample(const TileArgs& A, int x, int y) {
     if (A.border == BSF_BORDER_ZERO) {
-        if (x < 0 || x >= A.width || y < 0 || y >= A.height) return 0;
+        if (x < 0 || x >= A.width || y < 0 || y >= A.height) return 0.0;
     } else {
         x = clampi(x, 0, A.width - 1);
         y = clampi(y, 0, A.height - 1);
     }
     const long long off = (long long)y * A.in_pitch + x;
-    if (A.in_dtype == BSF_U8) return (long long)((const unsigned char*)A.in)[off];
-    const double v = (A.in_dtype == BSF_F32) ? (double)((const float*)A.in)[off] : ((const double*)A.in)[off];
-    const double sv = v * 16777216.0;  // samples on the 2^-24 grid become integers
-    const long long iv = (long long)rint(sv);
-    inexact |= (unsigned)((double)iv != sv);
-    return iv;
+    if (A.in_dtype == BSF_U8) return (double)((const unsigned char*)A.in)[off];
+    if (A.in_dtype == BSF_F32) return (double)((const float*)A.in)[off];
+    return ((const double*)A.in)[off];
+}
+
+// Integer grid of a sample: top = exponent e with |v| < 2^e, fine = number of fractional
+// bits v needs to become an integer (v = M 2^(e-53) with M a 53-bit integer).
+__device__ __forceinline__ void sample_grid(double v, int& top, int& fine) {
+    if (v == 0.0) {
+        top = -1100;
+        fine = 0;
+        return;
+    }
+    const unsigned long long bits = __double_as_longlong(v);
+    const int ex = (int)((bits >> 52) & 0x7ff);
+    unsigned long long man = bits & 0xfffffffffffffull;
+    int e;  // v = man' * 2^(e - 53), man' in [2^52, 2^53)
+    if (ex == 0) {  // subnormal
+        e = -1022 - 52 + (64 - __clzll(man)) ;
+        man <<= (53 - (64 - __clzll(man)));
+    } else {
+        man |= 1ull << 52;
+        e = ex - 1022;
+    }
+    top = e;
+    const int low = e - 53 + __ffsll((long long)man) - 1;  // exponent of the lowest set bit
+    fine = low < 0 ? -low : 0;
+}
+
+// digit k of K (B bits each; the top digit keeps the sign) of an exact integer
+__device__ __forceinline__ long long digit(long long v, int k, int K, int B) {
+    if (K == 1) return v;
+    if (k + 1 < K) return (v >> (k * B)) & ((1ll << B) - 1);
+    return v >> (k * B);
+}
+
+__device__ __forceinline__ int wave_max_i(int v) {
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return v;
 }
 
 template <int N, int PATH>
 __global__ __launch_bounds__(kThreads) void filter_tile_kernel(TileArgs A) {
     extern __shared__ long long S[];
     __shared__ double red[2][kThreads / 64];
+    __shared__ int redi[2][kThreads / 64];
     const int tid = threadIdx.x;
     int tile = xcd_tile(blockIdx.x, gridDim.x);
     if (A.dbg_window) tile = A.dbg_tile;
@@ -437,6 +649,7 @@ __global__ __launch_bounds__(kThreads) void filter_tile_kernel(TileArgs A) {
     const int m1 = t1 + px, m2 = t2 + py;
     const bool inside = px < tw && py < th;
 
+    // 1. the tile's scale vectors and its reach
     float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
     bool valid = false;
     if (inside) {
@@ -459,6 +672,7 @@ __global__ __launch_bounds__(kThreads) void filter_tile_kernel(TileArgs A) {
     R1 = fmax(fmax(red[0][0], red[0][1]), fmax(red[0][2], red[0][3]));
     R2 = fmax(fmax(red[1][0], red[1][1]), fmax(red[1][2], red[1][3]));
 
+    // 2. the restart window
     const Window w = tile_window<N>(t1, t2, tw, th, R1, R2);
     const long long need = window_elems(w);
     const double nan = __builtin_nan("");
@@ -479,32 +693,83 @@ __global__ __launch_bounds__(kThreads) void filter_tile_kernel(TileArgs A) {
         return;
     }
     const Geo g = {w.wq, w.hq, w.wq * w.hq};
-    unsigned inexact = 0;
+    const int ntri = (g.hq * (g.hq - 1)) / 2;
+
+    // 3. an exact integer grid for the window: samples become v * 2^sh with at most 53
+    //    significant bits (finer bits than 2^-53 of the window maximum are rounded)
+    int top = -1100, fine = 0;
     for (int i = tid; i < g.qn; i += kThreads) {
         const int r = i / g.wq, c = i - r * g.wq;
-        S[i] = load_sample(A, w.x0 + c, w.y0 + r, inexact);
+        int t_, f_;
+        sample_grid(load_sample(A, w.x0 + c, w.y0 + r), t_, f_);
+        top = max(top, t_);
+        fine = max(fine, f_);
     }
-    const int ntri = (g.hq * (g.hq - 1)) / 2;
-    for (int i = tid; i < ntri; i += kThreads) S[g.qn + i] = 0;
-    if (inexact) atomicOr(A.err, kErrInexact);
+    top = wave_max_i(top);
+    fine = wave_max_i(fine);
     __syncthreads();
+    if ((tid & 63) == 0) {
+        redi[0][tid >> 6] = top;
+        redi[1][tid >> 6] = fine;
+    }
+    __syncthreads();
+    top = max(max(redi[0][0], redi[0][1]), max(redi[0][2], redi[0][3]));
+    fine = max(max(redi[1][0], redi[1][1]), max(redi[1][2], redi[1][3]));
+    const int sh = (top + fine > 53) ? 53 - top : fine;
+    const int bits = max(top + sh, 1);
 
-    unsigned ovf = 0;
     const bool cen = !A.dbg_window || A.dbg_geom[4];
     const int cc = t1 + tw / 2 - w.x0, rc = t2 + th / 2 - w.y0;  // centre of the tile's own extent
-    preintegrate_window(S, g, N, cen, cc, rc, ovf);
-    ovf = __syncthreads_or(ovf);
+    const int mx = m1 - w.x0, my = m2 - w.y0;
 
-    if (A.dbg_window) {
-        if (tid == 0) {
-            A.dbg_geom[0] = w.x0; A.dbg_geom[1] = w.y0; A.dbg_geom[2] = w.wq; A.dbg_geom[3] = w.hq;
-            A.dbg_geom[5] = (int)ovf;
+    // 4. stage 1 + mesh, on K base-2^B digits of the samples when the running sums of
+    //    the whole samples would leave int64 (the filter is linear in the image)
+    dd acc_dd = {0.0, 0.0};
+    double acc_f = 0.0;
+    unsigned bad = 0;
+    bool done = false;
+    for (int K = 1; K <= 4 && !done; ++K) {
+        const int B = (bits + K - 1) / K;
+        acc_dd = {0.0, 0.0};
+        acc_f = 0.0;
+        bool overflowed = false;
+        for (int k = 0; k < K; ++k) {
+            __syncthreads();  // the previous digit's mesh has finished reading the window
+            for (int i = tid; i < g.qn; i += kThreads) {
+                const int r = i / g.wq, c = i - r * g.wq;
+                const long long iv = (long long)rint(ldexp(load_sample(A, w.x0 + c, w.y0 + r), sh));
+                S[i] = digit(iv, k, K, B);
+            }
+            for (int i = tid; i < ntri; i += kThreads) S[g.qn + i] = 0;
+            __syncthreads();
+            unsigned ovf = 0;
+            preintegrate_window(S, g, N, cen, cc, rc, ovf);
+            ovf = __syncthreads_or(ovf);
+            if (A.dbg_window) {
+                if (tid == 0) {
+                    A.dbg_geom[0] = w.x0; A.dbg_geom[1] = w.y0; A.dbg_geom[2] = w.wq; A.dbg_geom[3] = w.hq;
+                    A.dbg_geom[5] = (int)ovf;
+                    A.dbg_geom[6] = sh;
+                }
+                if ((long long)g.qn <= A.dbg_cap)
+                    for (int i = tid; i < g.qn; i += kThreads) A.dbg_window[i] = S[i];
+                return;
+            }
+            if (ovf) {
+                overflowed = true;
+                break;
+            }
+            if (inside && valid) {
+                const double wk = ldexp(1.0, k * B);
+                if (PATH == BSF_PATH_F64)
+                    acc_dd = dd_add(acc_dd, dd_mul_d(mesh_dd<N>(S, g.wq, g.hq, mx, my, a, bad), wk));
+                else
+                    acc_f = __fma_rn(mesh_f64<N>(S, g.wq, g.hq, mx, my, a, bad), wk, acc_f);
+            }
         }
-        if ((long long)g.qn <= A.dbg_cap)
-            for (int i = tid; i < g.qn; i += kThreads) A.dbg_window[i] = S[i];
-        return;
+        done = !overflowed;
     }
-    if (ovf) {
+    if (!done) {
         if (tid == 0) atomicOr(A.err, kErrRange);
         store(nan);
         return;
@@ -514,11 +779,8 @@ __global__ __launch_bounds__(kThreads) void filter_tile_kernel(TileArgs A) {
         store(nan);
         return;
     }
-    unsigned bad = 0;
-    const int mx = m1 - w.x0, my = m2 - w.y0;
-    double s = (PATH == BSF_PATH_F64) ? mesh_dd<N>(S, g.wq, g.hq, mx, my, a, bad)
-                                      : mesh_f64<N>(S, g.wq, g.hq, mx, my, a, bad);
-    if (A.in_dtype != BSF_U8) s *= 5.9604644775390625e-08;  // undo the 2^24 input scaling
+    double s = (PATH == BSF_PATH_F64) ? finalize_dd<N>(acc_dd, a) : finalize_f64<N>(acc_f, a);
+    s = ldexp(s, -sh);
     if (bad) {
         atomicOr(A.err, kErrWindow);
         s = nan;
@@ -546,12 +808,12 @@ __global__ void gpre_load(GlobalArgs A) {
     TileArgs t{};
     t.in = A.in; t.in_pitch = A.in_pitch; t.width = A.width; t.height = A.height;
     t.in_dtype = A.in_dtype; t.border = A.border;
-    unsigned inexact = 0;
+    const double scale = (A.in_dtype == BSF_U8) ? 1.0 : 16777216.0;  // float inputs on the 2^-24 grid
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
          i += (long long)gridDim.x * blockDim.x) {
         const int r = (int)(i / wt), c = (int)(i - (long long)r * wt);
         long long v = 0;
-        if (c < A.wq) v = load_sample(t, A.x0 + c, A.y0 + r, inexact);
+        if (c < A.wq) v = (long long)rint(load_sample(t, A.x0 + c, A.y0 + r) * scale);
         A.T[i] = v;
     }
 }
@@ -679,17 +941,16 @@ hipError_t dispatch(int n, int path, const TileArgs& a, dim3 grid, size_t lds, h
     if (path == BSF_PATH_F64) {
         if (n == 1) return launch_tile<1, BSF_PATH_F64>(a, grid, lds, st);
         if (n == 2) return launch_tile<2, BSF_PATH_F64>(a, grid, lds, st);
-        return hipErrorInvalidValue;
+        return launch_tile<3, BSF_PATH_F64>(a, grid, lds, st);
     }
     if (n == 1) return launch_tile<1, BSF_PATH_F32_TILED>(a, grid, lds, st);
     if (n == 2) return launch_tile<2, BSF_PATH_F32_TILED>(a, grid, lds, st);
-    return hipErrorInvalidValue;
+    return launch_tile<3, BSF_PATH_F32_TILED>(a, grid, lds, st);
 }
 
 bsf_status prepare(bsf_ctx* c, const bsf_job* j, TileArgs& a, dim3& grid, size_t& lds) {
     bsf_status s = validate(c, j, true);
     if (s != BSF_OK) return s;
-    if (j->order == 3) return fail(c, BSF_ERR_UNSUPPORTED, "order 3 is not built in this library yet");
     a = TileArgs{};
     a.in = j->in;
     a.in_pitch = j->in_pitch;
@@ -732,7 +993,7 @@ const char* bsf_status_string(bsf_status s) {
         case BSF_ERR_UNSUPPORTED: return "unsupported (window exceeds on-chip memory, or order)";
         case BSF_ERR_SCALE_RANGE: return "scale out of range";
         case BSF_ERR_RANGE: return "pre-integrated value out of the exact integer range";
-        case BSF_ERR_INEXACT_INPUT: return "float input not on the 2^-24 grid";
+        case BSF_ERR_INEXACT_INPUT: return "reserved";
     }
     return "unknown status";
 }
@@ -877,7 +1138,6 @@ bsf_status bsf_get_device_error(bsf_ctx* c, void* stream) {
     if (h & kErrScale) return fail(c, BSF_ERR_SCALE_RANGE, "a scale was not finite or outside [0.5, 1e4]");
     if (h & kErrWindow) return fail(c, BSF_ERR_UNSUPPORTED, "a restart window exceeded the on-chip memory");
     if (h & kErrRange) return fail(c, BSF_ERR_RANGE, "a pre-integrated value left the int64 range");
-    if (h & kErrInexact) return fail(c, BSF_ERR_INEXACT_INPUT, "a float input was rounded to the 2^-24 grid");
     return BSF_OK;
 }
 

@@ -79,6 +79,26 @@ __device__ __forceinline__ dd dd_div(dd a, dd b) {
     return dd_add_d(fast_two_sum(q1, q2), q3);
 }
 
+// Compensated pair s + c (c collects the rounding errors of s).  One Horner step
+// acc * x + coef costs an FMA two-product and a two-sum, and the pair keeps about twice
+// the working precision (compensated Horner scheme, Graillat-Langlois-Louvet).
+struct cp {
+    double s, c;
+};
+__device__ __forceinline__ cp cp_horner(cp acc, dd x, cp coef) {
+    const double p = acc.s * x.hi;
+    const double pi = __fma_rn(acc.s, x.hi, -p);
+    const dd t = two_sum(p, coef.s);
+    const double corr = ((pi + t.lo) + coef.c) + acc.s * x.lo;
+    return {t.hi, __fma_rn(acc.c, x.hi, corr)};
+}
+// acc + w * v for a small integer weight w (exact as a double)
+__device__ __forceinline__ cp cp_axpy(cp acc, double w, cp v) {
+    const dd h = two_prod(v.s, w);
+    const dd t = two_sum(acc.s, h.hi);
+    return {t.hi, acc.c + ((t.lo + h.lo) + v.c * w)};
+}
+
 // ---------------------------------------------------------------------------
 // Interpolant tables per order (generated, exact rationals NUM/DEN).
 // ---------------------------------------------------------------------------
@@ -93,6 +113,7 @@ struct Tab<1> {
     __host__ __device__ static constexpr int jx(int j) { return bsf_tables::kJ1[j][0]; }
     __host__ __device__ static constexpr int jy(int j) { return bsf_tables::kJ1[j][1]; }
     __host__ __device__ static constexpr int ma(int a) { return bsf_tables::kMonoExp1[a][0]; }
+    __host__ __device__ static constexpr int mb(int a) { return bsf_tables::kMonoExp1[a][1]; }
 };
 template <>
 struct Tab<2> {
@@ -103,17 +124,34 @@ struct Tab<2> {
     __host__ __device__ static constexpr int jx(int j) { return bsf_tables::kJ2[j][0]; }
     __host__ __device__ static constexpr int jy(int j) { return bsf_tables::kJ2[j][1]; }
     __host__ __device__ static constexpr int ma(int a) { return bsf_tables::kMonoExp2[a][0]; }
+    __host__ __device__ static constexpr int mb(int a) { return bsf_tables::kMonoExp2[a][1]; }
 };
 template <>
 struct Tab<3> {
     static constexpr int S = bsf_tables::kStencil3, M = bsf_tables::kMono3, DEG = 10;
     static constexpr double DEN = bsf_tables::kDen3;
-    static constexpr int SPLIT = 3, SHIFT = 24;  // 24-bit chunks keep every partial sum exact
+    static constexpr int SPLIT = 3, SHIFT = 21;  // 21-bit parts keep every partial sum exact
     __host__ __device__ static constexpr double num(int j, int a) { return bsf_tables::kNum3[j][a]; }
     __host__ __device__ static constexpr int jx(int j) { return bsf_tables::kJ3[j][0]; }
     __host__ __device__ static constexpr int jy(int j) { return bsf_tables::kJ3[j][1]; }
     __host__ __device__ static constexpr int ma(int a) { return bsf_tables::kMonoExp3[a][0]; }
+    __host__ __device__ static constexpr int mb(int a) { return bsf_tables::kMonoExp3[a][1]; }
 };
+
+// The reference triangle u1 >= |u2| is symmetric under u2 -> -u2 (about the cell
+// centre), so stencil point j and its mirror j' = (jx, e - jy) (e = 0 odd n, 1 even n)
+// carry the same polynomials up to the sign (-1)^b of the u2-power b.
+template <int N>
+__host__ __device__ constexpr int mirror_of(int j) {
+    const int e = (N & 1) ? 0 : 1;
+    for (int k = 0; k < Tab<N>::S; ++k)
+        if (Tab<N>::jx(k) == Tab<N>::jx(j) && Tab<N>::jy(k) == e - Tab<N>::jy(j)) return k;
+    return -1;
+}
+template <int N>
+__host__ __device__ constexpr bool is_rep(int j) {  // representative of its mirror pair
+    return 2 * Tab<N>::jy(j) >= ((N & 1) ? 0 : 1);
+}
 
 // Bounds of the stencil after the quarter turns about the cell centre (odd n: about
 // the anchor; even n: about the anchor + (1/2, 1/2)).

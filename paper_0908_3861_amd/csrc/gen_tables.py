@@ -296,11 +296,11 @@ def emit(all_tables, path):
         lines.append(f"constexpr int kStencil{n} = {len(stencil)};")
         lines.append(f"constexpr int kMono{n} = {len(mono)};")
         lines.append(f"constexpr double kDen{n} = {den}.0;")
-        lines.append(f"constexpr int kJ{n}[{len(stencil)}][2] = {{" +
-                     ", ".join(f"{{{j[0]}, {j[1]}}}" for j in stencil) + "};")
+        lines.append(f"#define BSF_J{n}_INIT {{" + ", ".join(f"{{{j[0]}, {j[1]}}}" for j in stencil) + "}")
+        lines.append(f"constexpr int kJ{n}[{len(stencil)}][2] = BSF_J{n}_INIT;")
         lines.append(f"constexpr int kMonoExp{n}[{len(mono)}][2] = {{" +
                      ", ".join(f"{{{a}, {b}}}" for a, b in mono) + "};")
-        lines.append(f"constexpr double kNum{n}[{len(stencil)}][{len(mono)}] = {{")
+        lines.append(f"#define BSF_NUM{n}_INIT {{ \\")
         maxabs = 0
         for j in stencil:
             row = []
@@ -309,8 +309,9 @@ def emit(all_tables, path):
                 assert v.denominator == 1
                 maxabs = max(maxabs, abs(v.numerator))
                 row.append(f"{v.numerator}.0")
-            lines.append("  {" + ", ".join(row) + "},")
-        lines.append("};")
+            lines.append("  {" + ", ".join(row) + "}, \\")
+        lines.append("}")
+        lines.append(f"constexpr double kNum{n}[{len(stencil)}][{len(mono)}] = BSF_NUM{n}_INIT;")
         lines.append(f"// max |numerator| = {maxabs}")
     lines.append("}  // namespace bsf_tables")
     with open(path, "w") as fh:

@@ -187,3 +187,52 @@ def test_f32_path_error_is_stated(bsf, torch_dev, oracle_mod):
     assert st == 0 and s.dtype == np.float32
     o = oracle_mod.filter(img.astype(np.float64), sc, 1)
     assert rel_max(s.astype(np.float64), o) < 1e-5
+
+
+def test_parity_order3_u8_and_float(bsf, torch_dev, oracle_mod):
+    rng = np.random.default_rng(110)
+    H, W = 19, 21
+    sc = synth.uniform_scales(rng, H, W, 1.0, 2.5)
+    img8 = rng.integers(0, 256, size=(H, W)).astype(np.uint8)
+    s, st = run(bsf, torch_dev, img8, sc, 3)
+    assert st == 0
+    o = oracle_mod.filter(img8.astype(np.float64), sc, 3)
+    assert rel_max(s, o) < TOL_F64
+    # float input on the 2^-24 grid: the running sums need two digits at order 3
+    imgf = synth.unit_grid_image(rng, H, W, np.float64)
+    s, st = run(bsf, torch_dev, imgf, sc, 3)
+    assert st == 0
+    o = oracle_mod.filter(imgf, sc, 3)
+    assert rel_max(s, o) < TOL_F64
+
+
+def test_arbitrary_float_inputs(bsf, torch_dev, oracle_mod):
+    """Inputs off any short grid (full 53-bit mantissas), negative and large values."""
+    rng = np.random.default_rng(111)
+    H, W = 26, 31
+    sc = synth.uniform_scales(rng, H, W, 1.0, 5.0)
+    for img in (rng.standard_normal((H, W)) * 1e3 + 17.0,
+                rng.random((H, W)) - 0.5,
+                np.exp(rng.uniform(-20, 20, size=(H, W)))):
+        for n in (1, 2):
+            s, st = run(bsf, torch_dev, img, sc, n)
+            assert st == 0
+            o = oracle_mod.filter(img, sc, n)
+            assert rel_max(s, o) < TOL_F64, n
+    s, st = run(bsf, torch_dev, img.astype(np.float32), sc, 2)
+    assert st == 0
+    o = oracle_mod.filter(img.astype(np.float32).astype(np.float64), sc, 2)
+    assert rel_max(s, o) < TOL_F64
+
+
+def test_large_windows_need_digits(bsf, torch_dev, oracle_mod):
+    """Scales up to 14 at order 2 with float input: windows past 100 px, two digits."""
+    rng = np.random.default_rng(112)
+    H, W = 24, 24
+    img = synth.unit_grid_image(rng, H, W, np.float64)
+    sc = synth.uniform_scales(rng, H, W, 1.0, 14.0)
+    s, st = run(bsf, torch_dev, img, sc, 2, a_max=14.0)
+    assert st == 0
+    pix = rng.choice(H * W, size=40, replace=False)
+    o = oracle_mod.filter(img, sc, 2, pixels=pix)
+    assert rel_max(s.reshape(-1)[pix], o) < TOL_F64
