@@ -16,13 +16,15 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "../../include/bsf.h"
 #include "bsf_device.h"
 
 namespace bsf {
 
-struct TileArgs {
+// One filter job (an image, its scale field, order, path and output).
+struct JobDesc {
     const void* in;
     long long in_pitch;
     const float* scales;
@@ -32,14 +34,22 @@ struct TileArgs {
     int width, height;
     int in_dtype;
     int border;
+    int order, path;
     int tiles_x, tiles_y;
-    long long lds_cap;  // int64 elements of dynamic LDS
-    unsigned* err;
-    // debug dump of one tile's pre-integrated window (nullptr in production)
+    long long item_base;  // first work item of this job in a batched launch
+};
+
+// Launch-wide parameters.
+struct Launch {
+    long long lds_cap;   // int64 elements of dynamic LDS
+    unsigned* err;       // sticky error bits
+    unsigned* counters;  // [0] overflow count, [1] overflow cursor, [2] work cursor
+    int2* overflow;      // (job, tile) whose window did not fit this launch's LDS
+    int overflow_cap;    // 0: no list, flag the error instead
+    // test aid: dump one tile's pre-integrated window instead of filtering
     long long* dbg_window;
     int* dbg_geom;
     long long dbg_cap;
-    int dbg_tile;
 };
 
 // XCD-aware order: consecutive workgroup ids are dealt round-robin to the 8 XCDs, so
@@ -585,7 +595,7 @@ __device__ __forceinline__ double wave_max(double v) {
 }
 
 // One input sample under the boundary rule, as a double (exact for u8, f32 and f64).
-__device__ __forceinline__ double load_sample(const TileArgs& A, int x, int y) {
+__device__ __forceinline__ double load_sample(const JobDesc A, int x, int y) {
     if (A.border == BSF_BORDER_ZERO) {
         if (x < 0 || x >= A.width || y < 0 || y >= A.height) return 0.0;
     } else {
@@ -634,14 +644,20 @@ __device__ __forceinline__ int wave_max_i(int v) {
     return v;
 }
 
+struct Shared {
+    double red[2][kThreads / 64];
+    int redi[2][kThreads / 64];
+    int item;
+};
+
+// Filter one 16x16 tile of job A (index `job`) with the window in S.
 template <int N, int PATH>
-__global__ __launch_bounds__(kThreads) void filter_tile_kernel(TileArgs A) {
-    extern __shared__ long long S[];
-    __shared__ double red[2][kThreads / 64];
-    __shared__ int redi[2][kThreads / 64];
+__device__ __forceinline__ void process_tile(const JobDesc A, int job, int tile, const Launch L, long long* S,
+                                             Shared& sh_) {
+    auto& red = sh_.red;
+    auto& redi = sh_.redi;
     const int tid = threadIdx.x;
-    int tile = xcd_tile(blockIdx.x, gridDim.x);
-    if (A.dbg_window) tile = A.dbg_tile;
+    __syncthreads();  // the previous item of this workgroup is done with S and the scratch
     const int tx = tile % A.tiles_x, ty = tile / A.tiles_x;
     const int t1 = tx * kTile, t2 = ty * kTile;
     const int tw = std::min(kTile, A.width - t1), th = std::min(kTile, A.height - t2);
@@ -658,7 +674,7 @@ __global__ __launch_bounds__(kThreads) void filter_tile_kernel(TileArgs A) {
         const float av[4] = {a.x, a.y, a.z, a.w};
 #pragma unroll
         for (int d = 0; d < 4; ++d) valid = valid && (av[d] >= (float)kScaleMin) && (av[d] <= (float)kScaleMax);
-        if (!valid) atomicOr(A.err, kErrScale);
+        if (!valid) atomicOr(L.err, kErrScale);
     }
     double R1 = valid ? reach1(N, a.x, a.y, a.w) : 0.0;
     double R2 = valid ? reach1(N, a.z, a.y, a.w) : 0.0;
@@ -684,12 +700,23 @@ __global__ __launch_bounds__(kThreads) void filter_tile_kernel(TileArgs A) {
         else
             ((float*)A.out)[off] = (float)v;
     };
-    if (need > A.lds_cap) {
-        if (tid == 0) atomicOr(A.err, kErrWindow);
-        if (!A.dbg_window) store(nan);
-        if (A.dbg_window && tid == 0) {
-            A.dbg_geom[0] = w.x0; A.dbg_geom[1] = w.y0; A.dbg_geom[2] = w.wq; A.dbg_geom[3] = w.hq;
+    if (need > L.lds_cap) {
+        if (L.dbg_window) {
+            if (tid == 0) {
+                L.dbg_geom[0] = w.x0; L.dbg_geom[1] = w.y0; L.dbg_geom[2] = w.wq; L.dbg_geom[3] = w.hq;
+            }
+            return;
         }
+        if (L.overflow_cap > 0) {  // a later launch with more LDS takes the tile
+            if (tid == 0) {
+                const unsigned k = atomicAdd(&L.counters[0], 1u);
+                if (k < (unsigned)L.overflow_cap) L.overflow[k] = make_int2(job, tile);
+                else atomicOr(L.err, kErrWindow);
+            }
+            return;
+        }
+        if (tid == 0) atomicOr(L.err, kErrWindow);
+        store(nan);
         return;
     }
     const Geo g = {w.wq, w.hq, w.wq * w.hq};
@@ -718,7 +745,7 @@ __global__ __launch_bounds__(kThreads) void filter_tile_kernel(TileArgs A) {
     const int sh = (top + fine > 53) ? 53 - top : fine;
     const int bits = max(top + sh, 1);
 
-    const bool cen = !A.dbg_window || A.dbg_geom[4];
+    const bool cen = !L.dbg_window || L.dbg_geom[4];
     const int cc = t1 + tw / 2 - w.x0, rc = t2 + th / 2 - w.y0;  // centre of the tile's own extent
     const int mx = m1 - w.x0, my = m2 - w.y0;
 
@@ -745,14 +772,14 @@ __global__ __launch_bounds__(kThreads) void filter_tile_kernel(TileArgs A) {
             unsigned ovf = 0;
             preintegrate_window(S, g, N, cen, cc, rc, ovf);
             ovf = __syncthreads_or(ovf);
-            if (A.dbg_window) {
+            if (L.dbg_window) {
                 if (tid == 0) {
-                    A.dbg_geom[0] = w.x0; A.dbg_geom[1] = w.y0; A.dbg_geom[2] = w.wq; A.dbg_geom[3] = w.hq;
-                    A.dbg_geom[5] = (int)ovf;
-                    A.dbg_geom[6] = sh;
+                    L.dbg_geom[0] = w.x0; L.dbg_geom[1] = w.y0; L.dbg_geom[2] = w.wq; L.dbg_geom[3] = w.hq;
+                    L.dbg_geom[5] = (int)ovf;
+                    L.dbg_geom[6] = sh;
                 }
-                if ((long long)g.qn <= A.dbg_cap)
-                    for (int i = tid; i < g.qn; i += kThreads) A.dbg_window[i] = S[i];
+                if ((long long)g.qn <= L.dbg_cap)
+                    for (int i = tid; i < g.qn; i += kThreads) L.dbg_window[i] = S[i];
                 return;
             }
             if (ovf) {
@@ -770,7 +797,7 @@ __global__ __launch_bounds__(kThreads) void filter_tile_kernel(TileArgs A) {
         done = !overflowed;
     }
     if (!done) {
-        if (tid == 0) atomicOr(A.err, kErrRange);
+        if (tid == 0) atomicOr(L.err, kErrRange);
         store(nan);
         return;
     }
@@ -782,10 +809,108 @@ __global__ __launch_bounds__(kThreads) void filter_tile_kernel(TileArgs A) {
     double s = (PATH == BSF_PATH_F64) ? finalize_dd<N>(acc_dd, a) : finalize_f64<N>(acc_f, a);
     s = ldexp(s, -sh);
     if (bad) {
-        atomicOr(A.err, kErrWindow);
+        atomicOr(L.err, kErrWindow);
         s = nan;
     }
     store(s);
+}
+
+// Runtime dispatch on (order, path) for launches that mix jobs; the window is addressed
+// through the kernel's dynamic LDS symbol.
+extern __shared__ long long g_lds[];
+
+__device__ __forceinline__ void process_any(const JobDesc A, int job, int tile, const Launch L, Shared& sh) {
+    const int v = (A.order - 1) * 2 + A.path;
+    switch (v) {
+        case 0: process_tile<1, BSF_PATH_F64>(A, job, tile, L, g_lds, sh); break;
+        case 1: process_tile<1, BSF_PATH_F32_TILED>(A, job, tile, L, g_lds, sh); break;
+        case 2: process_tile<2, BSF_PATH_F64>(A, job, tile, L, g_lds, sh); break;
+        case 3: process_tile<2, BSF_PATH_F32_TILED>(A, job, tile, L, g_lds, sh); break;
+        case 4: process_tile<3, BSF_PATH_F64>(A, job, tile, L, g_lds, sh); break;
+        default: process_tile<3, BSF_PATH_F32_TILED>(A, job, tile, L, g_lds, sh); break;
+    }
+}
+
+// Tier 1 of a single job: one workgroup per tile.
+template <int N, int PATH>
+__global__ __launch_bounds__(kThreads) void tile_kernel(JobDesc A, Launch L) {
+    extern __shared__ long long S[];
+    __shared__ Shared sh;
+    process_tile<N, PATH>(A, 0, xcd_tile(blockIdx.x, gridDim.x), L, S, sh);
+}
+
+// Test aid: stage 1 of one tile.
+template <int N, int PATH>
+__global__ __launch_bounds__(kThreads) void debug_tile_kernel(JobDesc A, Launch L, int tile) {
+    extern __shared__ long long S[];
+    __shared__ Shared sh;
+    process_tile<N, PATH>(A, 0, tile, L, S, sh);
+}
+
+// Persistent workgroups draining a work list through an atomic cursor; every
+// workgroup leaves once the cursor passes the end of the list.
+__device__ __forceinline__ int next_item(unsigned* cursor, Shared& sh) {
+    __syncthreads();
+    if (threadIdx.x == 0) sh.item = (int)atomicAdd(cursor, 1u);
+    __syncthreads();
+    return sh.item;
+}
+
+// Tier 2 of a single job: the tiles that did not fit tier 1's LDS.
+template <int N, int PATH>
+__global__ __launch_bounds__(kThreads) void overflow_kernel(JobDesc A, Launch L, const unsigned* count,
+                                                            const int2* list) {
+    extern __shared__ long long S[];
+    __shared__ Shared sh;
+    const int total = (int)min(*count, (unsigned)L.overflow_cap);
+    Launch L2 = L;
+    L2.overflow_cap = 0;
+    for (;;) {
+        const int i = next_item(&L.counters[1], sh);
+        if (i >= total) break;
+        process_tile<N, PATH>(A, 0, list[i].y, L2, S, sh);
+    }
+}
+
+// A batch of jobs: items are (job, tile) pairs numbered job by job (jobs sorted by cost
+// on the host, heaviest first); tier 1 pushes tiles that need more LDS to the list.
+__device__ __forceinline__ int find_job(const JobDesc* jobs, int njobs, long long item) {
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].item_base <= item) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 2))) void batch_kernel(const JobDesc* jobs, int njobs, long long total, Launch L) {
+    __shared__ Shared sh;
+    for (;;) {
+        const long long i = next_item(&L.counters[2], sh);
+        if (i >= total) break;
+        const int j = find_job(jobs, njobs, i);
+        const JobDesc A = jobs[j];
+        process_any(A, j, (int)(i - A.item_base), L, sh);
+    }
+}
+
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void batch_overflow_kernel(const JobDesc* jobs, Launch L, const unsigned* count,
+                                                                  const int2* list) {
+    __shared__ Shared sh;
+    const int total = (int)min(*count, (unsigned)L.overflow_cap);
+    Launch L2 = L;
+    L2.overflow_cap = 0;
+    for (;;) {
+        const int i = next_item(&L.counters[1], sh);
+        if (i >= total) break;
+        const int2 it = list[i];
+        process_any(jobs[it.x], it.x, it.y, L2, sh);
+    }
+}
+
+__global__ void reset_counters(unsigned* c) {
+    if (threadIdx.x < 4) c[threadIdx.x] = 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -805,7 +930,7 @@ struct GlobalArgs {
 __global__ void gpre_load(GlobalArgs A) {
     const int wt = A.wq + A.hq - 1;
     const long long total = (long long)A.hq * wt;
-    TileArgs t{};
+    JobDesc t{};
     t.in = A.in; t.in_pitch = A.in_pitch; t.width = A.width; t.height = A.height;
     t.in_dtype = A.in_dtype; t.border = A.border;
     const double scale = (A.in_dtype == BSF_U8) ? 1.0 : 16777216.0;  // float inputs on the 2^-24 grid
@@ -865,11 +990,18 @@ __global__ void gpre_store(GlobalArgs A) {
 // ===========================================================================
 struct bsf_ctx {
     int device = 0;
+    int cus = 256;
     size_t ws_limit = 0;
     unsigned* d_err = nullptr;
-    void* ws = nullptr;
+    void* ws = nullptr;  // stage-1 workspace of bsf_preintegrate
     size_t ws_bytes = 0;
-    long long lds_max_bytes = 0;
+    void* work = nullptr;  // counters, overflow list and job descriptors of the tile launches
+    size_t work_bytes = 0;
+    bsf::JobDesc* staging = nullptr;  // pinned host copy of a batch's descriptors
+    int staging_cap = 0;
+    hipEvent_t staging_done = nullptr;
+    long long lds_max_bytes = 0;   // LDS a workgroup may hold
+    long long lds_static = 1024;   // the largest static LDS of the tile kernels, plus a margin
     std::string last;
 };
 
@@ -924,34 +1056,66 @@ long long window_bound(int n, float a_max) {
     }
 }
 
+
+template <typename K>
+void allow_big_lds(K* kernel) {
+    // opt in to dynamic LDS beyond the default per-workgroup limit (once per kernel)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              163840 - 1024);
+    (void)hipGetLastError();
+}
+
 template <int N, int PATH>
-hipError_t launch_tile(const TileArgs& a, dim3 grid, size_t lds, hipStream_t st) {
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipFuncSetAttribute(reinterpret_cast<const void*>(&filter_tile_kernel<N, PATH>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
-        (void)hipGetLastError();
-        attr_set = true;
+hipError_t launch_single(const JobDesc& A, const Launch& L1, const Launch& L2, bool tier2, int tiles, int grid2,
+                         size_t lds1, size_t lds2, hipStream_t st) {
+    static bool once = false;
+    if (!once) {
+        allow_big_lds(&tile_kernel<N, PATH>);
+        allow_big_lds(&overflow_kernel<N, PATH>);
+        allow_big_lds(&debug_tile_kernel<N, PATH>);
+        once = true;
     }
-    hipLaunchKernelGGL((filter_tile_kernel<N, PATH>), grid, dim3(kThreads), lds, st, a);
+    hipLaunchKernelGGL((tile_kernel<N, PATH>), dim3(tiles), dim3(kThreads), lds1, st, A, L1);
+    if (tier2)
+        hipLaunchKernelGGL((overflow_kernel<N, PATH>), dim3(grid2), dim3(kThreads), lds2, st, A, L2, L1.counters,
+                           L1.overflow);
     return hipGetLastError();
 }
 
-hipError_t dispatch(int n, int path, const TileArgs& a, dim3 grid, size_t lds, hipStream_t st) {
+hipError_t dispatch_single(int n, int path, const JobDesc& A, const Launch& L1, const Launch& L2, bool tier2,
+                           int tiles, int grid2, size_t lds1, size_t lds2, hipStream_t st) {
+#define BSF_SINGLE(NN, PP) return launch_single<NN, PP>(A, L1, L2, tier2, tiles, grid2, lds1, lds2, st)
     if (path == BSF_PATH_F64) {
-        if (n == 1) return launch_tile<1, BSF_PATH_F64>(a, grid, lds, st);
-        if (n == 2) return launch_tile<2, BSF_PATH_F64>(a, grid, lds, st);
-        return launch_tile<3, BSF_PATH_F64>(a, grid, lds, st);
+        if (n == 1) BSF_SINGLE(1, BSF_PATH_F64);
+        if (n == 2) BSF_SINGLE(2, BSF_PATH_F64);
+        BSF_SINGLE(3, BSF_PATH_F64);
     }
-    if (n == 1) return launch_tile<1, BSF_PATH_F32_TILED>(a, grid, lds, st);
-    if (n == 2) return launch_tile<2, BSF_PATH_F32_TILED>(a, grid, lds, st);
-    return launch_tile<3, BSF_PATH_F32_TILED>(a, grid, lds, st);
+    if (n == 1) BSF_SINGLE(1, BSF_PATH_F32_TILED);
+    if (n == 2) BSF_SINGLE(2, BSF_PATH_F32_TILED);
+    BSF_SINGLE(3, BSF_PATH_F32_TILED);
+#undef BSF_SINGLE
 }
 
-bsf_status prepare(bsf_ctx* c, const bsf_job* j, TileArgs& a, dim3& grid, size_t& lds) {
-    bsf_status s = validate(c, j, true);
-    if (s != BSF_OK) return s;
-    a = TileArgs{};
+hipError_t dispatch_debug(int n, int path, const JobDesc& A, const Launch& L, int tile, size_t lds, hipStream_t st) {
+#define BSF_DBG(NN, PP)                                                                          \
+    do {                                                                                         \
+        allow_big_lds(&debug_tile_kernel<NN, PP>);                                               \
+        hipLaunchKernelGGL((debug_tile_kernel<NN, PP>), dim3(1), dim3(kThreads), lds, st, A, L, tile); \
+        return hipGetLastError();                                                                \
+    } while (0)
+    if (path == BSF_PATH_F64) {
+        if (n == 1) BSF_DBG(1, BSF_PATH_F64);
+        if (n == 2) BSF_DBG(2, BSF_PATH_F64);
+        BSF_DBG(3, BSF_PATH_F64);
+    }
+    if (n == 1) BSF_DBG(1, BSF_PATH_F32_TILED);
+    if (n == 2) BSF_DBG(2, BSF_PATH_F32_TILED);
+    BSF_DBG(3, BSF_PATH_F32_TILED);
+#undef BSF_DBG
+}
+
+JobDesc make_desc(const bsf_job* j) {
+    JobDesc a{};
     a.in = j->in;
     a.in_pitch = j->in_pitch;
     a.scales = j->scales;
@@ -962,22 +1126,91 @@ bsf_status prepare(bsf_ctx* c, const bsf_job* j, TileArgs& a, dim3& grid, size_t
     a.height = j->height;
     a.in_dtype = j->in_dtype;
     a.border = j->border;
+    a.order = j->order;
+    a.path = j->path;
     a.tiles_x = (j->width + kTile - 1) / kTile;
     a.tiles_y = (j->height + kTile - 1) / kTile;
-    a.err = c->d_err;
-    const long long cap_elems = (c->lds_max_bytes - 64) / 8;
-    long long elems = cap_elems;
-    if (j->a_max > 0.0f) {
-        elems = window_bound(j->order, j->a_max) + 64;
-        if (elems > cap_elems)
-            return fail(c, BSF_ERR_UNSUPPORTED,
-                        "a_max needs a restart window of " + std::to_string(elems * 8) +
-                            " bytes, more than the on-chip memory of a workgroup");
+    a.item_base = 0;
+    return a;
+}
+
+// LDS (int64 elements) a job's windows can need, from its a_max (0: the whole chip)
+long long job_window_need(const bsf_ctx* c, const bsf_job* j) {
+    const long long full = ((long long)c->lds_max_bytes - c->lds_static) / 8;
+    if (j->a_max > 0.0f) return window_bound(j->order, j->a_max) + 64;
+    return full;
+}
+
+// Tier sizes: tier 1 uses half the LDS (two workgroups per CU); tier 2 the rest.
+void tiers(const bsf_ctx* c, long long need, long long& t1, long long& t2, bool& two) {
+    const long long full = ((long long)c->lds_max_bytes - c->lds_static) / 8;
+    const long long half = ((long long)c->lds_max_bytes / 2 - c->lds_static) / 8;
+    if (need <= half) {
+        t1 = need;
+        t2 = 0;
+        two = false;
+    } else {
+        t1 = half;
+        t2 = std::min(need, full);
+        two = true;
     }
-    a.lds_cap = elems;
-    lds = (size_t)elems * 8;
-    grid = dim3((unsigned)(a.tiles_x * a.tiles_y));
+}
+
+// device buffers for counters, the overflow list and (batches) the job descriptors
+bsf_status ensure_work(bsf_ctx* c, size_t bytes, hipStream_t st) {
+    if (bytes <= c->work_bytes) return BSF_OK;
+    if (bytes > c->ws_limit) return fail(c, BSF_ERR_OUT_OF_MEMORY, "tile work list exceeds the workspace limit");
+    hipError_t e;
+    if (c->work) {
+        e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(c, e, "synchronising before growing the work list");
+        (void)hipFree(c->work);
+        c->work = nullptr;
+        c->work_bytes = 0;
+    }
+    const size_t cap = std::max(bytes, (size_t)1 << 20);
+    e = hipMalloc(&c->work, cap);
+    if (e != hipSuccess) return hip_fail(c, e, "work list allocation");
+    c->work_bytes = cap;
     return BSF_OK;
+}
+
+size_t work_bytes_for(long long items, int njobs) {
+    return 256 + (size_t)items * sizeof(int2) + (size_t)njobs * sizeof(JobDesc) + 256;
+}
+
+template <typename K>
+void static_lds(K* kernel, long long& mx) {
+    hipFuncAttributes fa{};
+    if (hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(kernel)) == hipSuccess)
+        mx = std::max(mx, (long long)fa.sharedSizeBytes);
+    (void)hipGetLastError();
+}
+
+// the largest static LDS any tile kernel declares (dynamic LDS + static must fit the chip)
+long long measure_static_lds() {
+    long long mx = 0;
+    static_lds(&tile_kernel<1, 0>, mx);
+    static_lds(&tile_kernel<2, 0>, mx);
+    static_lds(&tile_kernel<3, 0>, mx);
+    static_lds(&tile_kernel<1, 1>, mx);
+    static_lds(&tile_kernel<2, 1>, mx);
+    static_lds(&tile_kernel<3, 1>, mx);
+    static_lds(&overflow_kernel<1, 0>, mx);
+    static_lds(&overflow_kernel<2, 0>, mx);
+    static_lds(&overflow_kernel<3, 0>, mx);
+    static_lds(&overflow_kernel<1, 1>, mx);
+    static_lds(&overflow_kernel<2, 1>, mx);
+    static_lds(&overflow_kernel<3, 1>, mx);
+    static_lds(&debug_tile_kernel<1, 0>, mx);
+    static_lds(&debug_tile_kernel<2, 0>, mx);
+    static_lds(&debug_tile_kernel<3, 0>, mx);
+    static_lds(&debug_tile_kernel<1, 1>, mx);
+    static_lds(&debug_tile_kernel<2, 1>, mx);
+    static_lds(&debug_tile_kernel<3, 1>, mx);
+    static_lds(&batch_kernel, mx);
+    static_lds(&batch_overflow_kernel, mx);
+    return mx;
 }
 
 }  // namespace
@@ -1021,6 +1254,17 @@ bsf_status bsf_create(bsf_ctx** out, int hip_device, size_t workspace_limit_byte
         hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, hip_device);
     }
     c->lds_max_bytes = lds > 0 ? lds : 65536;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, hip_device) == hipSuccess && cus > 0)
+        c->cus = cus;
+    // static LDS of the kernels (rounded up, plus a margin); never below 1 KiB
+    c->lds_static = std::max(1024ll, ((measure_static_lds() + 255) / 256) * 256 + 256);
+    (void)hipGetLastError();
+    e = hipEventCreateWithFlags(&c->staging_done, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        delete c;
+        return BSF_ERR_HIP;
+    }
     e = hipMalloc(&c->d_err, sizeof(unsigned));
     if (e != hipSuccess) {
         delete c;
@@ -1039,8 +1283,11 @@ bsf_status bsf_create(bsf_ctx** out, int hip_device, size_t workspace_limit_byte
 bsf_status bsf_destroy(bsf_ctx* c) {
     if (!c) return BSF_ERR_INVALID_ARG;
     hipSetDevice(c->device);
-    if (c->d_err) hipFree(c->d_err);
-    if (c->ws) hipFree(c->ws);
+    if (c->d_err) (void)hipFree(c->d_err);
+    if (c->ws) (void)hipFree(c->ws);
+    if (c->work) (void)hipFree(c->work);
+    if (c->staging) (void)hipHostFree(c->staging);
+    if (c->staging_done) (void)hipEventDestroy(c->staging_done);
     delete c;
     return BSF_OK;
 }
@@ -1049,30 +1296,134 @@ bsf_status bsf_workspace_size(const bsf_job* job, size_t* bytes) {
     if (!bytes) return BSF_ERR_INVALID_ARG;
     bsf_status s = validate(nullptr, job, true);
     if (s != BSF_OK) return s;
-    *bytes = 0;  // the fused tile kernel keeps its windows on chip
+    // the windows live on chip; the only device memory is the work list of tiles that
+    // need the second, larger-LDS launch
+    const long long tiles = (long long)((job->width + kTile - 1) / kTile) * ((job->height + kTile - 1) / kTile);
+    *bytes = work_bytes_for(tiles, 0);
     return BSF_OK;
 }
 
 bsf_status bsf_filter(bsf_ctx* c, const bsf_job* j, void* stream) {
     if (!c) return BSF_ERR_INVALID_ARG;
-    TileArgs a;
-    dim3 grid;
-    size_t lds;
-    bsf_status s = prepare(c, j, a, grid, lds);
+    bsf_status s = validate(c, j, true);
     if (s != BSF_OK) return s;
+    const long long full = (c->lds_max_bytes - c->lds_static) / 8;
+    const long long need = job_window_need(c, j);
+    if (need > full)
+        return fail(c, BSF_ERR_UNSUPPORTED, "a_max needs a restart window of " + std::to_string(need * 8) +
+                                                " bytes, more than the on-chip memory of a workgroup");
+    long long t1, t2;
+    bool two;
+    tiers(c, need, t1, t2, two);
+    hipStream_t st = (hipStream_t)stream;
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
-    e = dispatch(j->order, j->path, a, grid, lds, (hipStream_t)stream);
+    const JobDesc A = make_desc(j);
+    const int tiles = A.tiles_x * A.tiles_y;
+    Launch L1{};
+    L1.lds_cap = t1;
+    L1.err = c->d_err;
+    Launch L2 = L1;
+    L2.lds_cap = t2;
+    int grid2 = 1;
+    if (two) {
+        s = ensure_work(c, work_bytes_for(tiles, 0), st);
+        if (s != BSF_OK) return s;
+        unsigned* counters = (unsigned*)c->work;
+        int2* list = (int2*)((char*)c->work + 256);
+        L1.counters = L2.counters = counters;
+        L1.overflow = L2.overflow = list;
+        L1.overflow_cap = L2.overflow_cap = tiles;
+        hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, st, counters);
+        const long long per_cu = std::max(1ll, c->lds_max_bytes / (t2 * 8 + c->lds_static));
+        grid2 = (int)std::min<long long>(tiles, c->cus * per_cu);
+    }
+    e = dispatch_single(j->order, j->path, A, L1, L2, two, tiles, grid2, (size_t)t1 * 8, (size_t)t2 * 8, st);
     if (e != hipSuccess) return hip_fail(c, e, "tile kernel launch");
     return BSF_OK;
 }
 
 bsf_status bsf_filter_batched(bsf_ctx* c, const bsf_job* jobs, int njobs, void* stream) {
-    if (!c || !jobs || njobs < 0) return fail(c, BSF_ERR_INVALID_ARG, "bad batch");
+    if (!c) return BSF_ERR_INVALID_ARG;
+    if (njobs < 0 || (njobs > 0 && !jobs)) return fail(c, BSF_ERR_INVALID_ARG, "bad batch");
+    if (njobs == 0) return BSF_OK;
+    const long long full = (c->lds_max_bytes - c->lds_static) / 8;
+    long long need = 0;
+    std::vector<int> order(njobs);
+    std::vector<double> cost(njobs);
     for (int i = 0; i < njobs; ++i) {
-        bsf_status s = bsf_filter(c, jobs + i, stream);
-        if (s != BSF_OK) return s;
+        bsf_status s = validate(c, jobs + i, true);
+        if (s != BSF_OK) return fail(c, s, "job " + std::to_string(i) + ": " + c->last);
+        need = std::max(need, job_window_need(c, jobs + i));
+        const int n = jobs[i].order;
+        // per-pixel mesh work ~ (n+1)^4 taps x 7n^2 interpolation weights
+        cost[i] = (double)jobs[i].width * jobs[i].height * std::pow(n + 1.0, 4) * 7.0 * n * n;
+        order[i] = i;
     }
+    if (need > full) return fail(c, BSF_ERR_UNSUPPORTED, "a job's a_max needs more LDS than a workgroup has");
+    // heaviest jobs first: their tiles are handed out first (longest-processing-time order)
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+    // the previous batch's descriptor upload must have left the staging buffer
+    e = hipEventSynchronize(c->staging_done);
+    if (e != hipSuccess) return hip_fail(c, e, "waiting for the staging buffer");
+    if (njobs > c->staging_cap) {
+        if (c->staging) (void)hipHostFree(c->staging);
+        c->staging = nullptr;
+        c->staging_cap = 0;
+        e = hipHostMalloc((void**)&c->staging, sizeof(JobDesc) * (size_t)njobs);
+        if (e != hipSuccess) return hip_fail(c, e, "pinned staging allocation");
+        c->staging_cap = njobs;
+    }
+    long long total = 0;
+    for (int k = 0; k < njobs; ++k) {
+        JobDesc d = make_desc(jobs + order[k]);
+        d.item_base = total;
+        total += (long long)d.tiles_x * d.tiles_y;
+        c->staging[k] = d;
+    }
+    if (total >= (1ll << 31)) return fail(c, BSF_ERR_INVALID_ARG, "batch has too many tiles");
+    bsf_status s = ensure_work(c, work_bytes_for(total, njobs), st);
+    if (s != BSF_OK) return s;
+    unsigned* counters = (unsigned*)c->work;
+    int2* list = (int2*)((char*)c->work + 256);
+    JobDesc* djobs = (JobDesc*)((char*)c->work + 256 + (size_t)total * sizeof(int2));
+    djobs = (JobDesc*)(((uintptr_t)djobs + 63) & ~(uintptr_t)63);
+    e = hipMemcpyAsync(djobs, c->staging, sizeof(JobDesc) * (size_t)njobs, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipEventRecord(c->staging_done, st);
+    if (e != hipSuccess) return hip_fail(c, e, "uploading the batch descriptors");
+    long long t1, t2;
+    bool two;
+    tiers(c, need, t1, t2, two);
+    Launch L{};
+    L.err = c->d_err;
+    L.counters = counters;
+    L.overflow = list;
+    L.overflow_cap = two ? (int)total : 0;
+    L.lds_cap = t1;
+    static bool once = false;
+    if (!once) {
+        allow_big_lds(&batch_kernel);
+        allow_big_lds(&batch_overflow_kernel);
+        once = true;
+    }
+    hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, st, counters);
+    const long long per_cu1 = std::max(1ll, c->lds_max_bytes / (t1 * 8 + c->lds_static));
+    const int grid1 = (int)std::min<long long>(total, c->cus * std::min(per_cu1, 8ll));
+    hipLaunchKernelGGL(batch_kernel, dim3(grid1), dim3(kThreads), (size_t)t1 * 8, st, (const JobDesc*)djobs, njobs,
+                       total, L);
+    if (two) {
+        Launch L2 = L;
+        L2.lds_cap = t2;
+        const long long per_cu2 = std::max(1ll, c->lds_max_bytes / (t2 * 8 + c->lds_static));
+        const int grid2 = (int)std::min<long long>(total, c->cus * per_cu2);
+        hipLaunchKernelGGL(batch_overflow_kernel, dim3(grid2), dim3(kThreads), (size_t)t2 * 8, st,
+                           (const JobDesc*)djobs, L2, (const unsigned*)counters, (const int2*)list);
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(c, e, "batch kernel launch");
     return BSF_OK;
 }
 
@@ -1147,19 +1498,20 @@ bsf_status bsf_get_device_error(bsf_ctx* c, void* stream) {
 bsf_status bsf_debug_tile_window(bsf_ctx* c, const bsf_job* j, int tile, int64_t* window, long long cap,
                                  int* geom, void* stream) {
     if (!c) return BSF_ERR_INVALID_ARG;
-    TileArgs a;
-    dim3 grid;
-    size_t lds;
-    bsf_status s = prepare(c, j, a, grid, lds);
+    bsf_status s = validate(c, j, true);
     if (s != BSF_OK) return s;
-    if (tile < 0 || tile >= a.tiles_x * a.tiles_y || !window || !geom)
+    const JobDesc A = make_desc(j);
+    if (tile < 0 || tile >= A.tiles_x * A.tiles_y || !window || !geom)
         return fail(c, BSF_ERR_INVALID_ARG, "bad debug tile arguments");
-    a.dbg_window = (long long*)window;
-    a.dbg_geom = geom;
-    a.dbg_cap = cap;
-    a.dbg_tile = tile;
+    const long long full = (c->lds_max_bytes - c->lds_static) / 8;
+    Launch L{};
+    L.lds_cap = std::min(job_window_need(c, j), full);
+    L.err = c->d_err;
+    L.dbg_window = (long long*)window;
+    L.dbg_geom = geom;
+    L.dbg_cap = cap;
     hipError_t e = hipSetDevice(c->device);
-    if (e == hipSuccess) e = dispatch(j->order, j->path, a, dim3(1), lds, (hipStream_t)stream);
+    if (e == hipSuccess) e = dispatch_debug(j->order, j->path, A, L, tile, (size_t)L.lds_cap * 8, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(c, e, "debug tile launch");
     return BSF_OK;
 }

@@ -236,3 +236,38 @@ def test_large_windows_need_digits(bsf, torch_dev, oracle_mod):
     pix = rng.choice(H * W, size=40, replace=False)
     o = oracle_mod.filter(img, sc, 2, pixels=pix)
     assert rel_max(s.reshape(-1)[pix], o) < TOL_F64
+
+
+def test_batched_bitwise_equals_single(bsf, torch_dev):
+    """One persistent launch over a mixed batch writes exactly what single calls write."""
+    torch = torch_dev
+    rng = np.random.default_rng(113)
+    specs = [(37, 50, 1, "f64", np.float64), (64, 48, 2, "f32tiled", np.float32), (23, 17, 3, "f64", np.uint8),
+             (80, 96, 2, "f64", np.uint8), (16, 16, 1, "f32tiled", np.float64), (45, 31, 3, "f32tiled", np.float32)]
+    items, singles = [], []
+    for (H, W, n, path, dt) in specs:
+        img = (rng.integers(0, 256, size=(H, W)).astype(np.uint8) if dt == np.uint8
+               else synth.unit_grid_image(rng, H, W, dt))
+        sc = synth.uniform_scales(rng, H, W, 1.0, 3.0 if n == 3 else 7.0)
+        ti, ts = torch.from_numpy(img).cuda(), torch.from_numpy(sc).cuda()
+        items.append(dict(img=ti, scales=ts, order=n, path=path, a_max=0.0))
+        singles.append(bsf.filter(ti, ts, n, path=path, a_max=0.0).cpu().numpy())
+    outs = bsf.filter_batched(items)
+    assert bsf.default_context().device_error() == 0
+    for o, s1 in zip(outs, singles):
+        o = o.cpu().numpy()
+        assert o.dtype == s1.dtype and np.array_equal(o.view(np.uint8), s1.view(np.uint8))
+
+
+def test_tier2_tiles_match_oracle(bsf, torch_dev, oracle_mod):
+    """Large reach: windows exceed the first launch's LDS share and go to the second."""
+    rng = np.random.default_rng(114)
+    H, W = 40, 44
+    img = synth.blurred_u8_image(rng, H, W, 2.0)
+    sc = synth.uniform_scales(rng, H, W, 1.0, 3.0)
+    sc[:16, :16] = rng.uniform(10.0, 16.0, size=(16, 16, 4)).astype(np.float32)  # one tile with a big window
+    s, st = run(bsf, torch_dev, img, sc, 2, a_max=0.0)
+    assert st == 0
+    pix = np.concatenate([rng.choice(H * W, 40, replace=False), np.arange(0, 16 * W, W + 1)[:10]])
+    o = oracle_mod.filter(img.astype(np.float64), sc, 2, pixels=pix)
+    assert rel_max(s.reshape(-1)[pix], o) < TOL_F64
