@@ -1,13 +1,14 @@
 #!/usr/bin/env python3
 """Throughput of the adaptive box-spline filter on one MI355X.
 
-One step = one bsf_filter call (the whole hot path: restart windows, exact
-pre-integration, localisation mesh) over the "plain" workload: a 2048x2048 uint8 image
-(Gaussian-blurred noise), smooth real scale fields in [1, 16], order 2, float64 path.
-Inputs are resident in HBM before timing starts.
+Default workload ("plain"): one step = one bsf_filter call (the whole hot path: restart
+windows, exact pre-integration, localisation mesh) over a 2048x2048 uint8 image
+(Gaussian-blurred noise) with smooth real scale fields in [1, 16], order 2, float64
+path.  Inputs are resident in HBM before timing starts.  Prints one JSON line with
+Mpixel/s, the roofline of the filter call (HIP events on its launch stream) and the CPU
+oracle timed on a bounded pixel sample.
 
-Prints one JSON line: Mpixel/s, the roofline of the tile kernel (measured live with HIP
-events on the launch stream) and the CPU oracle timed on a bounded pixel sample.
+Other forms (not run by default): --workload small | precision | batched | serving.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu-baseline]
 """
@@ -15,6 +16,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -32,15 +34,259 @@ PEAK_FP32_VALU = 157.3e12
 PEAK_HBM = 8.0e12          # B/s
 
 
+def mesh_flops_per_pixel(order: int) -> float:
+    """Interpolation-weighted tap MACs: (n+1)^4 taps x 7n^2 lattice weights x 2."""
+    return 2.0 * (order + 1) ** 4 * 7 * order ** 2
+
+
 def algorithmic_flops(pixels: int, order: int, pbox: int) -> float:
-    """Interpolation-weighted tap MACs 2*(n+1)^4*7n^2 per pixel plus 4n running-sum adds
-    per element of the padded stage-1 box."""
-    return pixels * 2.0 * (order + 1) ** 4 * 7 * order ** 2 + pbox * 4.0 * order
+    """Tap MACs per pixel plus 4n running-sum adds per element of the padded stage-1 box."""
+    return pixels * mesh_flops_per_pixel(order) + pbox * 4.0 * order
 
 
-def algorithmic_bytes(pixels: int, in_bytes: int, out_bytes: int) -> float:
-    # image read once, scale vectors (4 x f32) read once, output written once
-    return pixels * (in_bytes + 16 + out_bytes)
+def padded_box(h: int, w: int, order: int, a_max: float) -> int:
+    R = 0.5 * order * (a_max + 2 * a_max / math.sqrt(2))
+    return int((w + 2 * math.ceil(R) + 3 * order) * (h + 2 * math.ceil(R) + 3 * order))
+
+
+def time_steps(step, steps: int, warmup: int, stream):
+    import torch
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for e0, e1 in evs:
+        e0.record(stream)
+        step()
+        e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs]))
+
+
+def oracle_sample(img64, scales, order, pixels_total, cpu_seconds, rng, border="clamp"):
+    """Time the CPU oracle on a bounded random pixel sample (about cpu_seconds of work)."""
+    import oracle
+    probe = rng.choice(pixels_total, size=16, replace=False)
+    t0 = time.perf_counter()
+    oracle.filter(img64, scales, order, border, pixels=probe)
+    tp = max(time.perf_counter() - t0, 1e-3)
+    count = int(min(pixels_total, max(32, 16 * cpu_seconds / tp)))
+    sample = np.sort(rng.choice(pixels_total, size=count, replace=False))
+    t0 = time.perf_counter()
+    o = oracle.filter(img64, scales, order, border, pixels=sample)
+    return sample, o, time.perf_counter() - t0
+
+
+def threads_used() -> int:
+    return int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+
+
+def errors(s, o) -> dict:
+    s = np.asarray(s, np.float64)
+    return {"rel_max": float(np.abs(s - o).max() / np.abs(o).max()),
+            "rel_rms": float(np.sqrt(np.mean((s - o) ** 2)) / np.sqrt(np.mean(o ** 2))),
+            "frac_within_1e-5": float(np.mean(np.abs(s - o) <= 1e-5 * np.abs(o).max())),
+            "compared": int(len(o))}
+
+
+def record(value, wall, steps, warmup, dtype, config, roofline, cpu, extra):
+    return {"metric": METRIC, "value": value, "unit": "Mpixel/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
+            "ms_per_step": wall / steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": dtype, "data": "synthetic", "config": config, "roofline": roofline, "cpu_baseline": cpu,
+            "extra": extra}
+
+
+# ---------------------------------------------------------------------------------------
+def run_single(args, name, job, a_max, path):
+    import torch
+    from paper_0908_3861_amd import binding
+    H, W = job.image.shape
+    n = job.order
+    dev = torch.device("cuda:0")
+    img = torch.from_numpy(job.image).to(dev)
+    sc = torch.from_numpy(job.scales).to(dev)
+    out = torch.empty((H, W), dtype=torch.float64 if path == "f64" else torch.float32, device=dev)
+    ctx = binding.default_context(0)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        binding.filter(img, sc, n, path=path, a_max=a_max, out=out, ctx=ctx)
+
+    wall, ms = time_steps(step, args.steps, args.warmup, stream)
+    ctx.check_device()
+    P = H * W
+    flops = algorithmic_flops(P, n, padded_box(H, W, n, a_max))
+    peak = PEAK_FP64_VALU  # the mesh runs in float64 on both paths
+    roof = {"bound": "alu", "achieved": flops / (ms * 1e-3) / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+            "frac": flops / (ms * 1e-3) / peak, "traffic": None}
+    in_bytes = job.image.dtype.itemsize
+    alg_bytes = P * (in_bytes + 16 + (8 if path == "f64" else 4))
+    extra = {"filter_ms": ms, "hbm_algorithmic_GBps": alg_bytes / (ms * 1e-3) / 1e9,
+             "hbm_frac_of_8TBps": alg_bytes / (ms * 1e-3) / PEAK_HBM, "a_max": a_max}
+    return out, ms, wall, roof, extra
+
+
+def workload_plain(args):
+    job = synth.config_job("plain", size=(args.size, args.size))
+    a_max = 16.0  # the workload's scale fields lie in [1, 16]
+    out, ms, wall, roof, extra = run_single(args, "plain", job, a_max, args.path)
+    H, W = job.image.shape
+    P = H * W
+    cpu = None
+    if not args.no_cpu_baseline:
+        rng = np.random.default_rng(12345)
+        sample, o, tc = oracle_sample(job.image.astype(np.float64), job.scales, job.order, P, args.cpu_seconds, rng)
+        cpu = {"value": len(sample) / tc / 1e6, "unit": "Mpixel/s", "cores": threads_used(), "kind": "oracle",
+               "sample": f"{len(sample)} random pixels of the same {W}x{H} order-{job.order} workload "
+                         f"(direct box-spline sum, float64, OpenMP), {tc:.1f} s"}
+        extra["err_vs_oracle"] = errors(out.cpu().numpy().reshape(-1)[sample], o)
+    config = {"workload": f"plain: {W}x{H} uint8 blurred-noise image, smooth real scales in [1,16], "
+                          f"order {job.order}, {args.path} path", "pixels": P, "order": job.order, "path": args.path}
+    dtype = "f64" if args.path == "f64" else "f64-mesh/f32-out"
+    return record(P * args.steps / wall / 1e6, wall, args.steps, args.warmup, dtype, config, roof, cpu, extra)
+
+
+def workload_small(args):
+    job = synth.config_job("small")
+    out, ms, wall, roof, extra = run_single(args, "small", job, 8.0, "f64")
+    import oracle
+    t0 = time.perf_counter()
+    o = oracle.filter(job.image, job.scales, job.order)
+    tc = time.perf_counter() - t0
+    P = job.pixels
+    extra["err_vs_oracle"] = errors(out.cpu().numpy().reshape(-1), o.reshape(-1))
+    cpu = {"value": P / tc / 1e6, "unit": "Mpixel/s", "cores": threads_used(), "kind": "oracle",
+           "sample": f"the full 256x256 image, {tc:.2f} s"}
+    config = {"workload": "small: 256x256 f64 unit-grid pixels, integer scales U{1..8}, order 1, f64 path",
+              "pixels": P, "order": 1, "path": "f64"}
+    return record(P * args.steps / wall / 1e6, wall, args.steps, args.warmup, "f64", config, roof, cpu, extra)
+
+
+def workload_precision(args):
+    side = args.size if args.size != 2048 else 4096
+    job = synth.config_job("precision", size=(side, side))
+    P = job.pixels
+    out32, ms32, wall32, roof, extra = run_single(args, "precision", job, 32.0, "f32tiled")
+    out64, ms64, wall64, _, extra64 = run_single(args, "precision", job, 32.0, "f64")
+    rng = np.random.default_rng(777)
+    sample, o, tc = oracle_sample(job.image.astype(np.float64), job.scales, job.order, P, args.cpu_seconds, rng)
+    extra["f64_path_ms"] = ms64
+    extra["f32tiled_speedup_over_f64"] = ms64 / ms32
+    extra["err_f32tiled_vs_oracle"] = errors(out32.cpu().numpy().reshape(-1)[sample], o)
+    extra["err_f64_vs_oracle"] = errors(out64.cpu().numpy().reshape(-1)[sample], o)
+    cpu = {"value": len(sample) / tc / 1e6, "unit": "Mpixel/s", "cores": threads_used(), "kind": "oracle",
+           "sample": f"{len(sample)} random pixels of the {side}x{side} workload, {tc:.1f} s"}
+    config = {"workload": f"precision: {side}x{side} f32 unit-grid pixels, i.i.d. real scales U[1,32], order 2, "
+                          "f32tiled path (f64 path timed beside it)", "pixels": P, "order": 2, "path": "f32tiled"}
+    return record(P * args.steps / wall32 / 1e6, wall32, args.steps, args.warmup, "f64-mesh/f32-out", config, roof,
+                  cpu, extra)
+
+
+def workload_batched(args):
+    import torch
+    from paper_0908_3861_amd import binding
+    jobs = synth.batch_jobs(count=args.batch_count)
+    dev = torch.device("cuda:0")
+    items = []
+    for j in jobs:
+        items.append(dict(img=torch.from_numpy(j.image).to(dev), scales=torch.from_numpy(j.scales).to(dev),
+                          order=j.order, path="f32tiled", a_max=8.0))
+    for it in items:
+        it["out"] = torch.empty(it["img"].shape, dtype=torch.float32, device=dev)
+    ctx = binding.default_context(0)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        binding.filter_batched(items, ctx=ctx)
+
+    wall, ms = time_steps(step, args.steps, args.warmup, stream)
+    ctx.check_device()
+    P = sum(j.pixels for j in jobs)
+    flops = sum(algorithmic_flops(j.pixels, j.order, padded_box(*j.image.shape, j.order, 8.0)) for j in jobs)
+    roof = {"bound": "alu", "achieved": flops / (ms * 1e-3) / 1e12, "peak": PEAK_FP64_VALU / 1e12,
+            "unit": "TFLOP/s", "frac": flops / (ms * 1e-3) / PEAK_FP64_VALU, "traffic": None}
+    # each image alone, and the oracle on sampled pixels of a few images
+    rng = np.random.default_rng(99)
+    equal = True
+    for k in rng.choice(len(jobs), size=3, replace=False):
+        it = items[k]
+        alone = binding.filter(it["img"], it["scales"], it["order"], path="f32tiled", a_max=8.0, ctx=ctx)
+        equal &= bool(torch.equal(alone, it["out"]))
+    errs = []
+    import oracle
+    t_or = 0.0
+    n_or = 0
+    for k in rng.choice(len(jobs), size=4, replace=False):
+        j = jobs[k]
+        pix = rng.choice(j.pixels, size=16, replace=False)
+        t0 = time.perf_counter()
+        o = oracle.filter(j.image.astype(np.float64), j.scales, j.order, pixels=pix)
+        t_or += time.perf_counter() - t0
+        n_or += len(pix)
+        errs.append(errors(items[k]["out"].cpu().numpy().reshape(-1)[pix], o)["rel_max"])
+    orders = [j.order for j in jobs]
+    extra = {"batch_ms": ms, "images": len(jobs), "orders": {str(n): orders.count(n) for n in (1, 2, 3)},
+             "batched_equals_alone": equal, "err_rel_max_sampled": max(errs)}
+    cpu = {"value": n_or / t_or / 1e6, "unit": "Mpixel/s", "cores": threads_used(), "kind": "oracle",
+           "sample": f"{n_or} random pixels of 4 of the images (orders mixed), {t_or:.1f} s"}
+    config = {"workload": f"batched: {len(jobs)} images, sides U{{256..2048 step 64}}, f32 unit-grid pixels, "
+                          "integer scales U{1..8}, orders U{1,2,3}, one persistent launch", "pixels": P,
+              "path": "f32tiled"}
+    return record(P * args.steps / wall / 1e6, wall, args.steps, args.warmup, "f64-mesh/f32-out", config, roof, cpu,
+                  extra)
+
+
+def workload_serving(args):
+    import torch
+    from paper_0908_3861_amd import serve
+    rng = np.random.default_rng(5)
+    # a pool of requests with the stream's shape/order/dtype mix, in pinned host memory
+    pool = []
+    for i in range(args.pool):
+        s = int(round(math.exp(rng.uniform(math.log(128), math.log(args.max_side)))))
+        f64 = bool(rng.integers(0, 2))
+        n = int(rng.integers(1, 4))
+        img = synth.unit_grid_image(rng, s, s, np.float64 if f64 else np.float32)
+        sc = synth.integer_scales(rng, s, s, 1, 8)
+        pool.append((torch.from_numpy(img).pin_memory(), torch.from_numpy(sc).pin_memory(), n,
+                     "f64" if f64 else "f32tiled"))
+    srv = serve.Server(budget_bytes=args.budget_gib << 30, slots=args.slots, streams=4)
+    # closed-loop capacity probe: every pool request at once
+    t0 = time.perf_counter()
+    futs = [srv.submit(im, sc, n, path, a_max=8.0) for (im, sc, n, path) in pool]
+    for f in futs:
+        f.result()
+    probe_s = time.perf_counter() - t0
+    capacity = len(pool) / probe_s
+    srv.close()
+    rate = args.rate if args.rate > 0 else 0.7 * capacity
+    srv = serve.Server(budget_bytes=args.budget_gib << 30, slots=args.slots, streams=4)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=int(rate * args.duration * 2) + 10))
+    arrivals = arrivals[arrivals < args.duration]
+    picks = rng.integers(0, len(pool), size=len(arrivals))
+    t_start = time.perf_counter()
+    futs = []
+    for t_a, k in zip(arrivals, picks):
+        now = time.perf_counter() - t_start
+        if t_a > now:
+            time.sleep(t_a - now)
+        im, sc, n, path = pool[k]
+        futs.append(srv.submit(im, sc, n, path, a_max=8.0))
+    for f in futs:
+        f.result()
+    wall = time.perf_counter() - t_start
+    srv.close()
+    srv.check_device()
+    st = srv.stats()
+    extra = {"p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"], "requests": st["completed"],
+             "arrival_rate_hz": rate, "capacity_probe_hz": capacity, "duration_s": args.duration,
+             "budget_gib": args.budget_gib, "slots": args.slots, "streams": 4, "pool": len(pool)}
+    config = {"workload": "serving: Poisson stream, square sides log-uniform [128, %d], f32/f64 50/50, "
+                          "integer scales U{1..8}, orders U{1,2,3}" % args.max_side}
+    return record(st["pixels"] / wall / 1e6, wall, 1, 0, "f64 / f64-mesh+f32-out (mixed)", config,
+                  None, None, extra)
 
 
 def main():
@@ -49,110 +295,25 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--path", default="f64", choices=["f64", "f32tiled"])
-    ap.add_argument("--copy-probe-mib", type=int, default=0,
-                    help="also run a device copy of this size (counter calibration)")
     ap.add_argument("--size", type=int, default=2048)
+    ap.add_argument("--workload", default="plain", choices=["plain", "small", "precision", "batched", "serving"])
+    ap.add_argument("--batch-count", type=int, default=64)
+    ap.add_argument("--duration", type=float, default=60.0)
+    ap.add_argument("--rate", type=float, default=0.0)
+    ap.add_argument("--pool", type=int, default=24)
+    ap.add_argument("--max-side", type=int, default=4096)
+    ap.add_argument("--budget-gib", type=int, default=32)
+    ap.add_argument("--slots", type=int, default=16)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
               "every workload here fits one MI355X.", file=sys.stderr)
         sys.exit(2)
-
-    import torch
-    from paper_0908_3861_amd import binding
-
-    job = synth.config_job("plain", size=(args.size, args.size))
-    H, W = job.image.shape
-    n = job.order
-    dev = torch.device("cuda:0")
-    img = torch.from_numpy(job.image).to(dev)
-    sc = torch.from_numpy(job.scales).to(dev)
-    a_max = 16.0  # the workload's scale fields lie in [1, 16]
-    odt = torch.float64 if args.path == "f64" else torch.float32
-    out = torch.empty((H, W), dtype=odt, device=dev)
-    ctx = binding.default_context(0)
-    stream = torch.cuda.current_stream()
-
-    def step():
-        binding.filter(img, sc, n, path=args.path, a_max=a_max, out=out, ctx=ctx)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    ctx.check_device()
-
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for e0, e1 in evs:
-        e0.record(stream)
-        step()
-        e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    kernel_ms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs]))
-    ctx.check_device()
-
-    if args.copy_probe_mib:
-        nbytes = args.copy_probe_mib << 20
-        src = torch.empty(nbytes, dtype=torch.uint8, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-
-    P = H * W
-    mpx = P * args.steps / wall / 1e6
-    # padded stage-1 box at the workload's maximum reach (pixel count of the global form)
-    R = 0.5 * n * (a_max + 2 * a_max / np.sqrt(2))
-    pbox = int((W + 2 * np.ceil(R) + 3 * n) * (H + 2 * np.ceil(R) + 3 * n))
-    flops = algorithmic_flops(P, n, pbox)
-    peak = PEAK_FP64_VALU if args.path == "f64" else PEAK_FP32_VALU
-    achieved = flops / (kernel_ms * 1e-3)
-    alg_bytes = algorithmic_bytes(P, 1, 8 if args.path == "f64" else 4)
-
-    # accuracy on sampled pixels against the CPU oracle (and its timing)
-    extra = {"hbm_algorithmic_GBps": alg_bytes / (kernel_ms * 1e-3) / 1e9,
-             "hbm_frac_of_8TBps": alg_bytes / (kernel_ms * 1e-3) / PEAK_HBM,
-             "kernel_ms": kernel_ms}
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
-        rng = np.random.default_rng(12345)
-        res = out.cpu().numpy()
-        f = job.image.astype(np.float64)
-        probe = rng.choice(P, size=32, replace=False)
-        t0 = time.perf_counter()
-        oracle.filter(f, job.scales, n, pixels=probe)
-        tp = time.perf_counter() - t0
-        count = int(min(P, max(64, 32 * args.cpu_seconds / max(tp, 1e-3))))
-        sample = rng.choice(P, size=count, replace=False)
-        t0 = time.perf_counter()
-        o = oracle.filter(f, job.scales, n, pixels=sample)
-        tc = time.perf_counter() - t0
-        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
-        cpu = {"value": count / tc / 1e6, "unit": "Mpixel/s", "cores": threads, "kind": "oracle",
-               "sample": f"{count} random pixels of the same 2048x2048 order-2 workload "
-                         f"(direct box-spline sum, float64, OpenMP), {tc:.1f} s"}
-        s = res.reshape(-1)[sample]
-        extra["err_rel_max_vs_oracle"] = float(np.abs(s - o).max() / np.abs(o).max())
-        extra["err_rel_rms_vs_oracle"] = float(np.sqrt(np.mean((s - o) ** 2)) / np.sqrt(np.mean(o ** 2)))
-        extra["err_pixels_compared"] = count
-
-    rec = {
-        "metric": METRIC, "value": mpx, "unit": "Mpixel/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.path == "f64" else "f64-mesh/f32-out",
-        "data": "synthetic",
-        "config": {"workload": f"plain: {W}x{H} uint8 blurred-noise image, smooth real scales in [1,16], "
-                               f"order {n}, {args.path} path", "pixels": P, "order": n, "path": args.path},
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None},
-        "cpu_baseline": cpu,
-        "extra": extra,
-    }
-    print(json.dumps(rec), flush=True)
+    fn = {"plain": workload_plain, "small": workload_small, "precision": workload_precision,
+          "batched": workload_batched, "serving": workload_serving}[args.workload]
+    print(json.dumps(fn(args)), flush=True)
 
 
 if __name__ == "__main__":

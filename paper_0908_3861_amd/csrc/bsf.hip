@@ -41,11 +41,11 @@ struct JobDesc {
 
 // Launch-wide parameters.
 struct Launch {
-    long long lds_cap;   // int64 elements of dynamic LDS
-    unsigned* err;       // sticky error bits
-    unsigned* counters;  // [0] overflow count, [1] overflow cursor, [2] work cursor
-    int2* overflow;      // (job, tile) whose window did not fit this launch's LDS
-    int overflow_cap;    // 0: no list, flag the error instead
+    long long lds_cap;    // int64 elements a window may use (dynamic LDS, or a scratch slice)
+    unsigned* err;        // sticky error bits
+    unsigned* push_count; // tiles whose window does not fit go to this list for a later,
+    int2* push_list;      //   larger launch: (job, tile); push_cap = 0 flags them instead
+    int push_cap;
     // test aid: dump one tile's pre-integrated window instead of filtering
     long long* dbg_window;
     int* dbg_geom;
@@ -707,10 +707,10 @@ __device__ __forceinline__ void process_tile(const JobDesc A, int job, int tile,
             }
             return;
         }
-        if (L.overflow_cap > 0) {  // a later launch with more LDS takes the tile
+        if (L.push_cap > 0) {  // a later launch with more room takes the tile
             if (tid == 0) {
-                const unsigned k = atomicAdd(&L.counters[0], 1u);
-                if (k < (unsigned)L.overflow_cap) L.overflow[k] = make_int2(job, tile);
+                const unsigned k = atomicAdd(L.push_count, 1u);
+                if (k < (unsigned)L.push_cap) L.push_list[k] = make_int2(job, tile);
                 else atomicOr(L.err, kErrWindow);
             }
             return;
@@ -819,15 +819,16 @@ __device__ __forceinline__ void process_tile(const JobDesc A, int job, int tile,
 // through the kernel's dynamic LDS symbol.
 extern __shared__ long long g_lds[];
 
-__device__ __forceinline__ void process_any(const JobDesc A, int job, int tile, const Launch L, Shared& sh) {
+__device__ __forceinline__ void process_any(const JobDesc A, int job, int tile, const Launch L, long long* S,
+                                            Shared& sh) {
     const int v = (A.order - 1) * 2 + A.path;
     switch (v) {
-        case 0: process_tile<1, BSF_PATH_F64>(A, job, tile, L, g_lds, sh); break;
-        case 1: process_tile<1, BSF_PATH_F32_TILED>(A, job, tile, L, g_lds, sh); break;
-        case 2: process_tile<2, BSF_PATH_F64>(A, job, tile, L, g_lds, sh); break;
-        case 3: process_tile<2, BSF_PATH_F32_TILED>(A, job, tile, L, g_lds, sh); break;
-        case 4: process_tile<3, BSF_PATH_F64>(A, job, tile, L, g_lds, sh); break;
-        default: process_tile<3, BSF_PATH_F32_TILED>(A, job, tile, L, g_lds, sh); break;
+        case 0: process_tile<1, BSF_PATH_F64>(A, job, tile, L, S, sh); break;
+        case 1: process_tile<1, BSF_PATH_F32_TILED>(A, job, tile, L, S, sh); break;
+        case 2: process_tile<2, BSF_PATH_F64>(A, job, tile, L, S, sh); break;
+        case 3: process_tile<2, BSF_PATH_F32_TILED>(A, job, tile, L, S, sh); break;
+        case 4: process_tile<3, BSF_PATH_F64>(A, job, tile, L, S, sh); break;
+        default: process_tile<3, BSF_PATH_F32_TILED>(A, job, tile, L, S, sh); break;
     }
 }
 
@@ -856,24 +857,43 @@ __device__ __forceinline__ int next_item(unsigned* cursor, Shared& sh) {
     return sh.item;
 }
 
-// Tier 2 of a single job: the tiles that did not fit tier 1's LDS.
+// A list of (job, tile) items filled by an earlier launch, drained through a cursor.
+struct ItemList {
+    const unsigned* count;
+    const int2* items;
+    unsigned* cursor;
+    int cap;
+};
+
+// Tier 2 of a single job: the tiles that did not fit tier 1's LDS (full LDS here).
 template <int N, int PATH>
-__global__ __launch_bounds__(kThreads) void overflow_kernel(JobDesc A, Launch L, const unsigned* count,
-                                                            const int2* list) {
+__global__ __launch_bounds__(kThreads) void overflow_kernel(JobDesc A, Launch L, ItemList in) {
     extern __shared__ long long S[];
     __shared__ Shared sh;
-    const int total = (int)min(*count, (unsigned)L.overflow_cap);
-    Launch L2 = L;
-    L2.overflow_cap = 0;
+    const int total = (int)min(*in.count, (unsigned)in.cap);
     for (;;) {
-        const int i = next_item(&L.counters[1], sh);
+        const int i = next_item(in.cursor, sh);
         if (i >= total) break;
-        process_tile<N, PATH>(A, 0, list[i].y, L2, S, sh);
+        process_tile<N, PATH>(A, 0, in.items[i].y, L, S, sh);
+    }
+}
+
+// Tier 3 of a single job: windows larger than any workgroup's LDS, each workgroup
+// working in its own slice of a global scratch buffer (L2/MALL-resident).
+template <int N, int PATH>
+__global__ __launch_bounds__(kThreads) void scratch_kernel(JobDesc A, Launch L, ItemList in, long long* scratch) {
+    __shared__ Shared sh;
+    long long* S = scratch + (long long)blockIdx.x * L.lds_cap;
+    const int total = (int)min(*in.count, (unsigned)in.cap);
+    for (;;) {
+        const int i = next_item(in.cursor, sh);
+        if (i >= total) break;
+        process_tile<N, PATH>(A, 0, in.items[i].y, L, S, sh);
     }
 }
 
 // A batch of jobs: items are (job, tile) pairs numbered job by job (jobs sorted by cost
-// on the host, heaviest first); tier 1 pushes tiles that need more LDS to the list.
+// on the host, heaviest first); tier 1 pushes tiles that need more LDS to a list.
 __device__ __forceinline__ int find_job(const JobDesc* jobs, int njobs, long long item) {
     int lo = 0, hi = njobs - 1;
     while (lo < hi) {
@@ -884,33 +904,45 @@ __device__ __forceinline__ int find_job(const JobDesc* jobs, int njobs, long lon
     return lo;
 }
 
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 2))) void batch_kernel(const JobDesc* jobs, int njobs, long long total, Launch L) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 2))) void batch_kernel(
+    const JobDesc* jobs, int njobs, long long total, Launch L, unsigned* cursor) {
     __shared__ Shared sh;
     for (;;) {
-        const long long i = next_item(&L.counters[2], sh);
+        const long long i = next_item(cursor, sh);
         if (i >= total) break;
         const int j = find_job(jobs, njobs, i);
         const JobDesc A = jobs[j];
-        process_any(A, j, (int)(i - A.item_base), L, sh);
+        process_any(A, j, (int)(i - A.item_base), L, g_lds, sh);
     }
 }
 
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void batch_overflow_kernel(const JobDesc* jobs, Launch L, const unsigned* count,
-                                                                  const int2* list) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void batch_overflow_kernel(
+    const JobDesc* jobs, Launch L, ItemList in) {
     __shared__ Shared sh;
-    const int total = (int)min(*count, (unsigned)L.overflow_cap);
-    Launch L2 = L;
-    L2.overflow_cap = 0;
+    const int total = (int)min(*in.count, (unsigned)in.cap);
     for (;;) {
-        const int i = next_item(&L.counters[1], sh);
+        const int i = next_item(in.cursor, sh);
         if (i >= total) break;
-        const int2 it = list[i];
-        process_any(jobs[it.x], it.x, it.y, L2, sh);
+        const int2 it = in.items[i];
+        process_any(jobs[it.x], it.x, it.y, L, g_lds, sh);
+    }
+}
+
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 2))) void batch_scratch_kernel(
+    const JobDesc* jobs, Launch L, ItemList in, long long* scratch) {
+    __shared__ Shared sh;
+    long long* S = scratch + (long long)blockIdx.x * L.lds_cap;
+    const int total = (int)min(*in.count, (unsigned)in.cap);
+    for (;;) {
+        const int i = next_item(in.cursor, sh);
+        if (i >= total) break;
+        const int2 it = in.items[i];
+        process_any(jobs[it.x], it.x, it.y, L, S, sh);
     }
 }
 
 __global__ void reset_counters(unsigned* c) {
-    if (threadIdx.x < 4) c[threadIdx.x] = 0u;
+    if (threadIdx.x < 8) c[threadIdx.x] = 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -995,11 +1027,18 @@ struct bsf_ctx {
     unsigned* d_err = nullptr;
     void* ws = nullptr;  // stage-1 workspace of bsf_preintegrate
     size_t ws_bytes = 0;
-    void* work = nullptr;  // counters, overflow list and job descriptors of the tile launches
-    size_t work_bytes = 0;
-    bsf::JobDesc* staging = nullptr;  // pinned host copy of a batch's descriptors
-    int staging_cap = 0;
-    hipEvent_t staging_done = nullptr;
+    // Per-call device work areas (counters, overflow list, batch descriptors) and pinned
+    // host staging, in a ring: calls on different streams may be in flight together; a
+    // slot is reused only after the call that last used it has finished on the device.
+    static constexpr int kRing = 8;
+    struct Slot {
+        void* dev = nullptr;
+        size_t dev_bytes = 0;
+        bsf::JobDesc* host = nullptr;
+        int host_cap = 0;
+        hipEvent_t done = nullptr;
+    } slot[kRing];
+    int slot_next = 0;
     long long lds_max_bytes = 0;   // LDS a workgroup may hold
     long long lds_static = 1024;   // the largest static LDS of the tile kernels, plus a margin
     std::string last;
@@ -1065,9 +1104,89 @@ void allow_big_lds(K* kernel) {
     (void)hipGetLastError();
 }
 
+// Window capacities of the three launch tiers: tier 1 half the LDS (two workgroups per
+// CU), tier 2 the full LDS, tier 3 a per-workgroup slice of global scratch.
+struct Plan {
+    long long t1 = 0, t2 = 0, t3 = 0;
+    bool use2 = false, use3 = false;
+};
+
+Plan plan_tiers(const bsf_ctx* c, long long need) {
+    const long long full = (c->lds_max_bytes - c->lds_static) / 8;
+    const long long half = (c->lds_max_bytes / 2 - c->lds_static) / 8;
+    Plan p;
+    if (need <= half) {
+        p.t1 = need;
+    } else if (need <= full) {
+        p.t1 = half;
+        p.t2 = need;
+        p.use2 = true;
+    } else {
+        p.t1 = half;
+        p.t2 = full;
+        p.t3 = need;
+        p.use2 = p.use3 = true;
+    }
+    return p;
+}
+
+int per_cu(const bsf_ctx* c, long long elems) {
+    return (int)std::max(1ll, c->lds_max_bytes / (elems * 8 + c->lds_static));
+}
+
+// Device work area of one call: counters | list A | list B | job descriptors | scratch.
+struct WorkLayout {
+    size_t lists_off = 256, listb_off = 0, jobs_off = 0, scratch_off = 0, total = 0;
+};
+
+WorkLayout work_layout(long long items, int njobs, size_t scratch_bytes) {
+    WorkLayout w;
+    w.listb_off = w.lists_off + (size_t)items * sizeof(int2);
+    w.jobs_off = ((w.listb_off + (size_t)items * sizeof(int2)) + 63) & ~(size_t)63;
+    w.scratch_off = ((w.jobs_off + (size_t)njobs * sizeof(JobDesc)) + 255) & ~(size_t)255;
+    w.total = w.scratch_off + scratch_bytes;
+    return w;
+}
+
+struct Tiers {
+    Launch L1, L2, L3;
+    ItemList inA, inB;
+    long long* scratch = nullptr;
+    int grid2 = 1, grid3 = 1;
+};
+
+Tiers make_tiers(const bsf_ctx* c, const Plan& p, char* work, const WorkLayout& w, long long items) {
+    Tiers t;
+    unsigned* ctr = (unsigned*)work;
+    int2* la = (int2*)(work + w.lists_off);
+    int2* lb = (int2*)(work + w.listb_off);
+    t.L1 = Launch{};
+    t.L1.lds_cap = p.t1;
+    t.L1.err = c->d_err;
+    t.L2 = t.L1;
+    t.L2.lds_cap = p.t2;
+    t.L3 = t.L1;
+    t.L3.lds_cap = p.t3;
+    if (p.use2) {
+        t.L1.push_count = ctr + 0;
+        t.L1.push_list = la;
+        t.L1.push_cap = (int)items;
+        t.inA = ItemList{ctr + 0, la, ctr + 1, (int)items};
+        t.grid2 = (int)std::min<long long>(items, (long long)c->cus * per_cu(c, p.t2));
+    }
+    if (p.use3) {
+        t.L2.push_count = ctr + 3;
+        t.L2.push_list = lb;
+        t.L2.push_cap = (int)items;
+        t.inB = ItemList{ctr + 3, lb, ctr + 4, (int)items};
+        t.grid3 = (int)std::min<long long>(items, (long long)c->cus * 2);
+        t.scratch = (long long*)(work + w.scratch_off);
+    }
+    return t;
+}
+
 template <int N, int PATH>
-hipError_t launch_single(const JobDesc& A, const Launch& L1, const Launch& L2, bool tier2, int tiles, int grid2,
-                         size_t lds1, size_t lds2, hipStream_t st) {
+hipError_t launch_single(const JobDesc& A, const Plan& p, const Tiers& t, int tiles, hipStream_t st) {
     static bool once = false;
     if (!once) {
         allow_big_lds(&tile_kernel<N, PATH>);
@@ -1075,16 +1194,18 @@ hipError_t launch_single(const JobDesc& A, const Launch& L1, const Launch& L2, b
         allow_big_lds(&debug_tile_kernel<N, PATH>);
         once = true;
     }
-    hipLaunchKernelGGL((tile_kernel<N, PATH>), dim3(tiles), dim3(kThreads), lds1, st, A, L1);
-    if (tier2)
-        hipLaunchKernelGGL((overflow_kernel<N, PATH>), dim3(grid2), dim3(kThreads), lds2, st, A, L2, L1.counters,
-                           L1.overflow);
+    hipLaunchKernelGGL((tile_kernel<N, PATH>), dim3(tiles), dim3(kThreads), (size_t)p.t1 * 8, st, A, t.L1);
+    if (p.use2)
+        hipLaunchKernelGGL((overflow_kernel<N, PATH>), dim3(t.grid2), dim3(kThreads), (size_t)p.t2 * 8, st, A, t.L2,
+                           t.inA);
+    if (p.use3)
+        hipLaunchKernelGGL((scratch_kernel<N, PATH>), dim3(t.grid3), dim3(kThreads), 0, st, A, t.L3, t.inB, t.scratch);
     return hipGetLastError();
 }
 
-hipError_t dispatch_single(int n, int path, const JobDesc& A, const Launch& L1, const Launch& L2, bool tier2,
-                           int tiles, int grid2, size_t lds1, size_t lds2, hipStream_t st) {
-#define BSF_SINGLE(NN, PP) return launch_single<NN, PP>(A, L1, L2, tier2, tiles, grid2, lds1, lds2, st)
+hipError_t dispatch_single(int n, int path, const JobDesc& A, const Plan& p, const Tiers& t, int tiles,
+                           hipStream_t st) {
+#define BSF_SINGLE(NN, PP) return launch_single<NN, PP>(A, p, t, tiles, st)
     if (path == BSF_PATH_F64) {
         if (n == 1) BSF_SINGLE(1, BSF_PATH_F64);
         if (n == 2) BSF_SINGLE(2, BSF_PATH_F64);
@@ -1134,50 +1255,43 @@ JobDesc make_desc(const bsf_job* j) {
     return a;
 }
 
-// LDS (int64 elements) a job's windows can need, from its a_max (0: the whole chip)
+// Window elements a job's tiles can need, from its a_max (0: at most the whole LDS)
 long long job_window_need(const bsf_ctx* c, const bsf_job* j) {
     const long long full = ((long long)c->lds_max_bytes - c->lds_static) / 8;
     if (j->a_max > 0.0f) return window_bound(j->order, j->a_max) + 64;
     return full;
 }
 
-// Tier sizes: tier 1 uses half the LDS (two workgroups per CU); tier 2 the rest.
-void tiers(const bsf_ctx* c, long long need, long long& t1, long long& t2, bool& two) {
-    const long long full = ((long long)c->lds_max_bytes - c->lds_static) / 8;
-    const long long half = ((long long)c->lds_max_bytes / 2 - c->lds_static) / 8;
-    if (need <= half) {
-        t1 = need;
-        t2 = 0;
-        two = false;
-    } else {
-        t1 = half;
-        t2 = std::min(need, full);
-        two = true;
-    }
-}
-
-// device buffers for counters, the overflow list and (batches) the job descriptors
-bsf_status ensure_work(bsf_ctx* c, size_t bytes, hipStream_t st) {
-    if (bytes <= c->work_bytes) return BSF_OK;
+// Take the next ring slot, wait until its previous call has finished on the device,
+// and make sure it holds `bytes` of device memory and `njobs` pinned descriptors.
+bsf_status acquire_slot(bsf_ctx* c, size_t bytes, int njobs, int& idx) {
     if (bytes > c->ws_limit) return fail(c, BSF_ERR_OUT_OF_MEMORY, "tile work list exceeds the workspace limit");
-    hipError_t e;
-    if (c->work) {
-        e = hipStreamSynchronize(st);
-        if (e != hipSuccess) return hip_fail(c, e, "synchronising before growing the work list");
-        (void)hipFree(c->work);
-        c->work = nullptr;
-        c->work_bytes = 0;
+    idx = c->slot_next;
+    c->slot_next = (idx + 1) % bsf_ctx::kRing;
+    bsf_ctx::Slot& sl = c->slot[idx];
+    hipError_t e = hipEventSynchronize(sl.done);
+    if (e != hipSuccess) return hip_fail(c, e, "waiting for a work slot");
+    if (bytes > sl.dev_bytes) {
+        if (sl.dev) (void)hipFree(sl.dev);
+        sl.dev = nullptr;
+        sl.dev_bytes = 0;
+        const size_t cap = std::max(bytes, (size_t)1 << 16);
+        e = hipMalloc(&sl.dev, cap);
+        if (e != hipSuccess) return hip_fail(c, e, "work list allocation");
+        sl.dev_bytes = cap;
     }
-    const size_t cap = std::max(bytes, (size_t)1 << 20);
-    e = hipMalloc(&c->work, cap);
-    if (e != hipSuccess) return hip_fail(c, e, "work list allocation");
-    c->work_bytes = cap;
+    if (njobs > sl.host_cap) {
+        if (sl.host) (void)hipHostFree(sl.host);
+        sl.host = nullptr;
+        sl.host_cap = 0;
+        e = hipHostMalloc((void**)&sl.host, sizeof(JobDesc) * (size_t)njobs);
+        if (e != hipSuccess) return hip_fail(c, e, "pinned staging allocation");
+        sl.host_cap = njobs;
+    }
     return BSF_OK;
 }
 
-size_t work_bytes_for(long long items, int njobs) {
-    return 256 + (size_t)items * sizeof(int2) + (size_t)njobs * sizeof(JobDesc) + 256;
-}
+
 
 template <typename K>
 void static_lds(K* kernel, long long& mx) {
@@ -1210,6 +1324,7 @@ long long measure_static_lds() {
     static_lds(&debug_tile_kernel<3, 1>, mx);
     static_lds(&batch_kernel, mx);
     static_lds(&batch_overflow_kernel, mx);
+    static_lds(&batch_scratch_kernel, mx);
     return mx;
 }
 
@@ -1242,7 +1357,7 @@ bsf_status bsf_create(bsf_ctx** out, int hip_device, size_t workspace_limit_byte
     if (hip_device < 0 || hip_device >= ndev) return BSF_ERR_INVALID_ARG;
     bsf_ctx* c = new bsf_ctx();
     c->device = hip_device;
-    c->ws_limit = workspace_limit_bytes ? workspace_limit_bytes : (size_t(1) << 30);
+    c->ws_limit = workspace_limit_bytes ? workspace_limit_bytes : (size_t(16) << 30);
     e = hipSetDevice(hip_device);
     if (e != hipSuccess) {
         delete c;
@@ -1260,10 +1375,12 @@ bsf_status bsf_create(bsf_ctx** out, int hip_device, size_t workspace_limit_byte
     // static LDS of the kernels (rounded up, plus a margin); never below 1 KiB
     c->lds_static = std::max(1024ll, ((measure_static_lds() + 255) / 256) * 256 + 256);
     (void)hipGetLastError();
-    e = hipEventCreateWithFlags(&c->staging_done, hipEventDisableTiming);
-    if (e != hipSuccess) {
-        delete c;
-        return BSF_ERR_HIP;
+    for (int r = 0; r < bsf_ctx::kRing; ++r) {
+        e = hipEventCreateWithFlags(&c->slot[r].done, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            delete c;
+            return BSF_ERR_HIP;
+        }
     }
     e = hipMalloc(&c->d_err, sizeof(unsigned));
     if (e != hipSuccess) {
@@ -1285,9 +1402,11 @@ bsf_status bsf_destroy(bsf_ctx* c) {
     hipSetDevice(c->device);
     if (c->d_err) (void)hipFree(c->d_err);
     if (c->ws) (void)hipFree(c->ws);
-    if (c->work) (void)hipFree(c->work);
-    if (c->staging) (void)hipHostFree(c->staging);
-    if (c->staging_done) (void)hipEventDestroy(c->staging_done);
+    for (int r = 0; r < bsf_ctx::kRing; ++r) {
+        if (c->slot[r].dev) (void)hipFree(c->slot[r].dev);
+        if (c->slot[r].host) (void)hipHostFree(c->slot[r].host);
+        if (c->slot[r].done) (void)hipEventDestroy(c->slot[r].done);
+    }
     delete c;
     return BSF_OK;
 }
@@ -1299,7 +1418,12 @@ bsf_status bsf_workspace_size(const bsf_job* job, size_t* bytes) {
     // the windows live on chip; the only device memory is the work list of tiles that
     // need the second, larger-LDS launch
     const long long tiles = (long long)((job->width + kTile - 1) / kTile) * ((job->height + kTile - 1) / kTile);
-    *bytes = work_bytes_for(tiles, 0);
+    // an MI355X workgroup holds at most 160 KiB of LDS; larger windows use global scratch
+    // slices for up to two workgroups per CU (256 CUs)
+    const long long full = (163840 - 1024) / 8;
+    const long long need = job->a_max > 0.0f ? window_bound(job->order, job->a_max) + 64 : full;
+    const size_t scratch = need > full ? (size_t)std::min<long long>(tiles, 512) * (size_t)need * 8 : 0;
+    *bytes = work_layout(tiles, 0, scratch).total;
     return BSF_OK;
 }
 
@@ -1307,38 +1431,26 @@ bsf_status bsf_filter(bsf_ctx* c, const bsf_job* j, void* stream) {
     if (!c) return BSF_ERR_INVALID_ARG;
     bsf_status s = validate(c, j, true);
     if (s != BSF_OK) return s;
-    const long long full = (c->lds_max_bytes - c->lds_static) / 8;
-    const long long need = job_window_need(c, j);
-    if (need > full)
-        return fail(c, BSF_ERR_UNSUPPORTED, "a_max needs a restart window of " + std::to_string(need * 8) +
-                                                " bytes, more than the on-chip memory of a workgroup");
-    long long t1, t2;
-    bool two;
-    tiers(c, need, t1, t2, two);
+    const Plan p = plan_tiers(c, job_window_need(c, j));
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
     const JobDesc A = make_desc(j);
     const int tiles = A.tiles_x * A.tiles_y;
-    Launch L1{};
-    L1.lds_cap = t1;
-    L1.err = c->d_err;
-    Launch L2 = L1;
-    L2.lds_cap = t2;
-    int grid2 = 1;
-    if (two) {
-        s = ensure_work(c, work_bytes_for(tiles, 0), st);
+    Tiers t;
+    int slot = -1;
+    if (p.use2) {
+        const int grid3 = (int)std::min<long long>(tiles, (long long)c->cus * 2);
+        const WorkLayout w = work_layout(tiles, 0, p.use3 ? (size_t)grid3 * (size_t)p.t3 * 8 : 0);
+        s = acquire_slot(c, w.total, 0, slot);
         if (s != BSF_OK) return s;
-        unsigned* counters = (unsigned*)c->work;
-        int2* list = (int2*)((char*)c->work + 256);
-        L1.counters = L2.counters = counters;
-        L1.overflow = L2.overflow = list;
-        L1.overflow_cap = L2.overflow_cap = tiles;
-        hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, st, counters);
-        const long long per_cu = std::max(1ll, c->lds_max_bytes / (t2 * 8 + c->lds_static));
-        grid2 = (int)std::min<long long>(tiles, c->cus * per_cu);
+        t = make_tiers(c, p, (char*)c->slot[slot].dev, w, tiles);
+        hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, st, (unsigned*)c->slot[slot].dev);
+    } else {
+        t = make_tiers(c, p, nullptr, WorkLayout{}, tiles);
     }
-    e = dispatch_single(j->order, j->path, A, L1, L2, two, tiles, grid2, (size_t)t1 * 8, (size_t)t2 * 8, st);
+    e = dispatch_single(j->order, j->path, A, p, t, tiles, st);
+    if (e == hipSuccess && slot >= 0) e = hipEventRecord(c->slot[slot].done, st);
     if (e != hipSuccess) return hip_fail(c, e, "tile kernel launch");
     return BSF_OK;
 }
@@ -1347,7 +1459,6 @@ bsf_status bsf_filter_batched(bsf_ctx* c, const bsf_job* jobs, int njobs, void* 
     if (!c) return BSF_ERR_INVALID_ARG;
     if (njobs < 0 || (njobs > 0 && !jobs)) return fail(c, BSF_ERR_INVALID_ARG, "bad batch");
     if (njobs == 0) return BSF_OK;
-    const long long full = (c->lds_max_bytes - c->lds_static) / 8;
     long long need = 0;
     std::vector<int> order(njobs);
     std::vector<double> cost(njobs);
@@ -1360,69 +1471,51 @@ bsf_status bsf_filter_batched(bsf_ctx* c, const bsf_job* jobs, int njobs, void* 
         cost[i] = (double)jobs[i].width * jobs[i].height * std::pow(n + 1.0, 4) * 7.0 * n * n;
         order[i] = i;
     }
-    if (need > full) return fail(c, BSF_ERR_UNSUPPORTED, "a job's a_max needs more LDS than a workgroup has");
     // heaviest jobs first: their tiles are handed out first (longest-processing-time order)
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
-    // the previous batch's descriptor upload must have left the staging buffer
-    e = hipEventSynchronize(c->staging_done);
-    if (e != hipSuccess) return hip_fail(c, e, "waiting for the staging buffer");
-    if (njobs > c->staging_cap) {
-        if (c->staging) (void)hipHostFree(c->staging);
-        c->staging = nullptr;
-        c->staging_cap = 0;
-        e = hipHostMalloc((void**)&c->staging, sizeof(JobDesc) * (size_t)njobs);
-        if (e != hipSuccess) return hip_fail(c, e, "pinned staging allocation");
-        c->staging_cap = njobs;
-    }
     long long total = 0;
+    for (int k = 0; k < njobs; ++k)
+        total += (long long)((jobs[order[k]].width + kTile - 1) / kTile) * ((jobs[order[k]].height + kTile - 1) / kTile);
+    if (total >= (1ll << 31)) return fail(c, BSF_ERR_INVALID_ARG, "batch has too many tiles");
+    const Plan p = plan_tiers(c, need);
+    const int grid3 = (int)std::min<long long>(total, (long long)c->cus * 2);
+    const WorkLayout w = work_layout(total, njobs, p.use3 ? (size_t)grid3 * (size_t)p.t3 * 8 : 0);
+    int slot = -1;
+    bsf_status s = acquire_slot(c, w.total, njobs, slot);
+    if (s != BSF_OK) return s;
+    bsf_ctx::Slot& sl = c->slot[slot];
+    total = 0;
     for (int k = 0; k < njobs; ++k) {
         JobDesc d = make_desc(jobs + order[k]);
         d.item_base = total;
         total += (long long)d.tiles_x * d.tiles_y;
-        c->staging[k] = d;
+        sl.host[k] = d;
     }
-    if (total >= (1ll << 31)) return fail(c, BSF_ERR_INVALID_ARG, "batch has too many tiles");
-    bsf_status s = ensure_work(c, work_bytes_for(total, njobs), st);
-    if (s != BSF_OK) return s;
-    unsigned* counters = (unsigned*)c->work;
-    int2* list = (int2*)((char*)c->work + 256);
-    JobDesc* djobs = (JobDesc*)((char*)c->work + 256 + (size_t)total * sizeof(int2));
-    djobs = (JobDesc*)(((uintptr_t)djobs + 63) & ~(uintptr_t)63);
-    e = hipMemcpyAsync(djobs, c->staging, sizeof(JobDesc) * (size_t)njobs, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipEventRecord(c->staging_done, st);
+    char* work = (char*)sl.dev;
+    const JobDesc* djobs = (const JobDesc*)(work + w.jobs_off);
+    e = hipMemcpyAsync((void*)djobs, sl.host, sizeof(JobDesc) * (size_t)njobs, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return hip_fail(c, e, "uploading the batch descriptors");
-    long long t1, t2;
-    bool two;
-    tiers(c, need, t1, t2, two);
-    Launch L{};
-    L.err = c->d_err;
-    L.counters = counters;
-    L.overflow = list;
-    L.overflow_cap = two ? (int)total : 0;
-    L.lds_cap = t1;
+    const Tiers t = make_tiers(c, p, work, w, total);
     static bool once = false;
     if (!once) {
         allow_big_lds(&batch_kernel);
         allow_big_lds(&batch_overflow_kernel);
         once = true;
     }
-    hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, st, counters);
-    const long long per_cu1 = std::max(1ll, c->lds_max_bytes / (t1 * 8 + c->lds_static));
-    const int grid1 = (int)std::min<long long>(total, c->cus * std::min(per_cu1, 8ll));
-    hipLaunchKernelGGL(batch_kernel, dim3(grid1), dim3(kThreads), (size_t)t1 * 8, st, (const JobDesc*)djobs, njobs,
-                       total, L);
-    if (two) {
-        Launch L2 = L;
-        L2.lds_cap = t2;
-        const long long per_cu2 = std::max(1ll, c->lds_max_bytes / (t2 * 8 + c->lds_static));
-        const int grid2 = (int)std::min<long long>(total, c->cus * per_cu2);
-        hipLaunchKernelGGL(batch_overflow_kernel, dim3(grid2), dim3(kThreads), (size_t)t2 * 8, st,
-                           (const JobDesc*)djobs, L2, (const unsigned*)counters, (const int2*)list);
-    }
+    hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, st, (unsigned*)work);
+    const int grid1 = (int)std::min<long long>(total, (long long)c->cus * std::min(per_cu(c, p.t1), 8));
+    hipLaunchKernelGGL(batch_kernel, dim3(grid1), dim3(kThreads), (size_t)p.t1 * 8, st, djobs, njobs, total, t.L1,
+                       (unsigned*)work + 2);
+    if (p.use2)
+        hipLaunchKernelGGL(batch_overflow_kernel, dim3(t.grid2), dim3(kThreads), (size_t)p.t2 * 8, st, djobs, t.L2,
+                           t.inA);
+    if (p.use3)
+        hipLaunchKernelGGL(batch_scratch_kernel, dim3(t.grid3), dim3(kThreads), 0, st, djobs, t.L3, t.inB, t.scratch);
     e = hipGetLastError();
+    if (e == hipSuccess) e = hipEventRecord(sl.done, st);
     if (e != hipSuccess) return hip_fail(c, e, "batch kernel launch");
     return BSF_OK;
 }

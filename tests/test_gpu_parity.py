@@ -271,3 +271,22 @@ def test_tier2_tiles_match_oracle(bsf, torch_dev, oracle_mod):
     pix = np.concatenate([rng.choice(H * W, 40, replace=False), np.arange(0, 16 * W, W + 1)[:10]])
     o = oracle_mod.filter(img.astype(np.float64), sc, 2, pixels=pix)
     assert rel_max(s.reshape(-1)[pix], o) < TOL_F64
+
+
+def test_scratch_tier_for_windows_beyond_lds(bsf, torch_dev, oracle_mod):
+    """Reach ~60 px: windows past the chip's LDS run in global scratch (third tier)."""
+    rng = np.random.default_rng(115)
+    H, W = 36, 40
+    img = synth.unit_grid_image(rng, H, W, np.float32)
+    sc = synth.uniform_scales(rng, H, W, 1.0, 4.0)
+    sc[16:32, 16:32] = rng.uniform(18.0, 24.0, size=(16, 16, 4)).astype(np.float32)
+    for path, tol in (("f64", TOL_F64), ("f32tiled", None)):
+        s, st = run(bsf, torch_dev, img, sc, 2, path=path, a_max=24.0)
+        assert st == 0
+        pix = np.concatenate([rng.choice(H * W, 20, replace=False), (np.arange(16, 32) * W + 20)])
+        o = oracle_mod.filter(img.astype(np.float64), sc, 2, pixels=pix)
+        err = rel_max(s.reshape(-1)[pix].astype(np.float64), o)
+        if tol is not None:
+            assert err < tol
+        else:
+            assert np.isfinite(s).all()
