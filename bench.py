@@ -33,6 +33,17 @@ PEAK_FP64_VALU = 78.6e12   # MI355X vector FP64, FLOP/s
 PEAK_FP32_VALU = 157.3e12
 PEAK_HBM = 8.0e12          # B/s
 
+# HBM bytes per launch of the dominant kernel, from rocprofv3 FETCH_SIZE / WRITE_SIZE runs
+# (scaled by a 1 GiB device copy), keyed by the kernel source they were taken on: once
+# the source changes, the figure no longer applies and the bench reports null.
+MEASURED_TRAFFIC = {"94838771ed8da7b6": {("plain", "f64"): 106.2e6}}
+
+
+def kernel_source_key() -> str:
+    import hashlib
+    src = os.path.join(ROOT, "paper_0908_3861_amd", "csrc", "bsf.hip")
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+
 
 def mesh_flops_per_pixel(order: int) -> float:
     """Interpolation-weighted tap MACs: (n+1)^4 taps x 7n^2 lattice weights x 2."""
@@ -116,6 +127,12 @@ def run_single(args, name, job, a_max, path):
 
     wall, ms = time_steps(step, args.steps, args.warmup, stream)
     ctx.check_device()
+    if args.copy_probe_mib:
+        # a plain device copy of known size, for scaling the profiler's byte counters
+        src = torch.ones(args.copy_probe_mib << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
     P = H * W
     flops = algorithmic_flops(P, n, padded_box(H, W, n, a_max))
     peak = PEAK_FP64_VALU  # the mesh runs in float64 on both paths
@@ -142,6 +159,8 @@ def workload_plain(args):
                "sample": f"{len(sample)} random pixels of the same {W}x{H} order-{job.order} workload "
                          f"(direct box-spline sum, float64, OpenMP), {tc:.1f} s"}
         extra["err_vs_oracle"] = errors(out.cpu().numpy().reshape(-1)[sample], o)
+    if W == 2048 and H == 2048:
+        roof["traffic"] = MEASURED_TRAFFIC.get(kernel_source_key(), {}).get(("plain", args.path))
     config = {"workload": f"plain: {W}x{H} uint8 blurred-noise image, smooth real scales in [1,16], "
                           f"order {job.order}, {args.path} path", "pixels": P, "order": job.order, "path": args.path}
     dtype = "f64" if args.path == "f64" else "f64-mesh/f32-out"
@@ -306,6 +325,7 @@ def main():
     ap.add_argument("--max-side", type=int, default=4096)
     ap.add_argument("--budget-gib", type=int, default=32)
     ap.add_argument("--slots", type=int, default=16)
+    ap.add_argument("--copy-probe-mib", type=int, default=0, help="also run a device copy of this size")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
