@@ -145,6 +145,44 @@ def run_single(args, name, job, a_max, path):
     return out, ms, wall, roof, extra
 
 
+def stage1_alone(job, halo: int, steps: int, warmup: int) -> dict:
+    """The paper's global pre-integrator (bsf_preintegrate) over the image's whole padded box.
+
+    Four passes (rows fused with the sample load; diagonals; columns; anti-diagonals
+    writing g), each reading and writing every element of its domain once: the
+    algorithmic bytes are Pbox*(in + 8) for the end points plus 48 B per element of the
+    extended domain D1 (box + extension triangle) for the three int64 hand-overs."""
+    import torch
+    from paper_0908_3861_amd import binding
+    H, W = job.image.shape
+    n = job.order
+    wq, hq = W + 2 * halo, H + 2 * halo
+    dev = torch.device("cuda:0")
+    img = torch.from_numpy(job.image).to(dev)
+    g = torch.empty((hq, wq), dtype=torch.int64, device=dev)
+    ctx = binding.default_context(0)
+    lib = ctx.lib
+    j = binding.Job()
+    j.width, j.height = W, H
+    j.in_dtype = binding._dtype_code(img)
+    j.in_ = img.data_ptr()
+    j.in_pitch = img.stride(0)
+    j.order = n
+    stream = torch.cuda.current_stream()
+
+    def step():
+        ctx._check(lib.bsf_preintegrate(ctx.handle, binding.ctypes.byref(j), -halo, -halo, wq, hq, g.data_ptr(),
+                                        g.stride(0), binding._stream_ptr(stream)))
+
+    wall, ms = time_steps(step, steps, warmup, stream)
+    box = wq * hq
+    d1 = box + hq * (hq - 1) // 2
+    alg = box * (job.image.dtype.itemsize + 8) + 48 * d1
+    return {"window": [wq, hq], "order": n, "ms": ms, "algorithmic_bytes": alg,
+            "GBps": alg / (ms * 1e-3) / 1e9, "hbm_frac": alg / (ms * 1e-3) / PEAK_HBM,
+            "Mpixel_per_s": H * W / (ms * 1e-3) / 1e6}
+
+
 def workload_plain(args):
     job = synth.config_job("plain", size=(args.size, args.size))
     a_max = 16.0  # the workload's scale fields lie in [1, 16]
@@ -159,6 +197,9 @@ def workload_plain(args):
                "sample": f"{len(sample)} random pixels of the same {W}x{H} order-{job.order} workload "
                          f"(direct box-spline sum, float64, OpenMP), {tc:.1f} s"}
         extra["err_vs_oracle"] = errors(out.cpu().numpy().reshape(-1)[sample], o)
+    # the global (paper's literal) stage 1 alone over the same image, padded by the
+    # halo of the largest scale: R = (n/2)(a + 2a/sqrt2) + 3n, about 42 at n = 2, a = 16
+    extra["stage1_global_alone"] = stage1_alone(job, 42, max(3, args.steps // 2), 2)
     if W == 2048 and H == 2048:
         roof["traffic"] = MEASURED_TRAFFIC.get(kernel_source_key(), {}).get(("plain", args.path))
     config = {"workload": f"plain: {W}x{H} uint8 blurred-noise image, smooth real scales in [1,16], "
@@ -308,6 +349,20 @@ def workload_serving(args):
                   None, None, extra)
 
 
+def workload_stage1(args):
+    """Stage 1 alone, as the paper's global pre-integrator, on the plain workload's image."""
+    job = synth.config_job("plain", size=(args.size, args.size))
+    r = stage1_alone(job, 42, args.steps, args.warmup)
+    H, W = job.image.shape
+    roof = {"bound": "hbm", "achieved": r["GBps"], "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": r["hbm_frac"],
+            "traffic": None}
+    config = {"workload": f"stage1: global n-fold running sums (4 directions, order {job.order}) over the "
+                          f"{r['window'][0]}x{r['window'][1]} padded box of the {W}x{H} uint8 plain image",
+              "pixels": H * W, "order": job.order}
+    wall = r["ms"] * 1e-3 * args.steps
+    return record(r["Mpixel_per_s"], wall, args.steps, args.warmup, "int64", config, roof, None, r)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -317,7 +372,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--path", default="f64", choices=["f64", "f32tiled"])
     ap.add_argument("--size", type=int, default=2048)
-    ap.add_argument("--workload", default="plain", choices=["plain", "small", "precision", "batched", "serving"])
+    ap.add_argument("--workload", default="plain",
+                    choices=["plain", "small", "precision", "batched", "serving", "stage1"])
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--duration", type=float, default=60.0)
     ap.add_argument("--rate", type=float, default=0.0)
@@ -332,7 +388,7 @@ def main():
               "every workload here fits one MI355X.", file=sys.stderr)
         sys.exit(2)
     fn = {"plain": workload_plain, "small": workload_small, "precision": workload_precision,
-          "batched": workload_batched, "serving": workload_serving}[args.workload]
+          "batched": workload_batched, "serving": workload_serving, "stage1": workload_stage1}[args.workload]
     print(json.dumps(fn(args)), flush=True)
 
 

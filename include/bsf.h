@@ -64,7 +64,8 @@ typedef enum { BSF_U8 = 0, BSF_F32 = 1, BSF_F64 = 2 } bsf_dtype;
 /* BSF_PATH_F64: output float64; mesh interpolation and accumulation in double-double,
  *   so the result matches the exact filter to a few float64 ulps.
  * BSF_PATH_F32_TILED: output float32; the same exact pre-integration, mesh in plain
- *   float64 (error grows with the cancellation the mesh performs). */
+ *   float64.  Its error grows with the cancellation the mesh performs, about 1e-7 of the
+ *   output's magnitude for order 2 at scales up to 32 (float32 rounding dominates). */
 typedef enum { BSF_PATH_F64 = 0, BSF_PATH_F32_TILED = 1 } bsf_path;
 
 /* Boundary rule for samples outside the image (the paper leaves it open): clamp to
@@ -88,7 +89,7 @@ typedef struct {
 } bsf_job;
 
 /* Create a context on HIP device `hip_device`.  `workspace_limit_bytes` caps the device
- * memory the context may allocate for its own workspace (0 = 1 GiB).  The context owns
+ * memory the context may allocate for its own workspace (0 = 16 GiB).  The context owns
  * its workspace and a small sticky error word; it is used by one host thread at a time. */
 bsf_status bsf_create(bsf_ctx** ctx, int hip_device, size_t workspace_limit_bytes);
 
@@ -114,8 +115,9 @@ bsf_status bsf_filter_batched(bsf_ctx* ctx, const bsf_job* jobs, int njobs, void
  * recursions start from zero at the window's lower-left edges and run on the window
  * extended to the right by a triangle of zeros, which step (4) needs.  Float inputs are
  * taken on the 2^-24 grid (multiplied by 2^24).  Multiply by 2^n for the sqrt2 weights of
- * the two diagonal steps.  Values wrap modulo 2^64 if they exceed int64.  Workspace:
- * 8*hq*(wq+hq) bytes. */
+ * the two diagonal steps.  Values wrap modulo 2^64 if they exceed int64 (exact wherever
+ * the true value fits).  Workspace: 8*hq*tp bytes, tp = wq+hq-1 rounded up to a
+ * multiple of 4. */
 bsf_status bsf_preintegrate(bsf_ctx* ctx, const bsf_job* job, int x0, int y0, int wq, int hq,
                             int64_t* g, ptrdiff_t g_pitch, void* stream);
 
@@ -128,10 +130,11 @@ bsf_status bsf_get_device_error(bsf_ctx* ctx, void* stream);
  * stage-1 part of the tile kernel for output tile `tile` (row-major tile index, 16x16
  * tiles) of `job` and write the box part of its restart window, int64 row-major
  * [hq][wq], to the device buffer `window` (capacity `cap` elements).  `geom` is a device
- * int[6]: the caller sets geom[4] = 1 to anchor every running sum at the tile centre
+ * int[8]: the caller sets geom[4] = 1 to anchor every running sum at the tile centre
  * (what bsf_filter does) or 0 for the recursions' zero start at the window's lower-left
  * edges; the call writes geom[0..3] = x0, y0, wq, hq of the window and geom[5] = 1 if a
- * value left the int64 range.  Asynchronous on `stream`. */
+ * value left the int64 range and geom[6] = the power of two sh the samples were scaled by
+ * (the window holds the digit-free running sums of f_ext * 2^sh).  Asynchronous on `stream`. */
 bsf_status bsf_debug_tile_window(bsf_ctx* ctx, const bsf_job* job, int tile, int64_t* window,
                                  long long cap, int* geom, void* stream);
 

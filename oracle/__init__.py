@@ -88,15 +88,19 @@ def filter(img: np.ndarray, scales: np.ndarray, n: int, border: str = "clamp",
     return out
 
 
-def preintegrate(window: np.ndarray, n: int) -> np.ndarray:
-    """Unit-weight n-fold pre-integration of an integer window ([Hq, Wq], row 0 = smallest k2)."""
+def preintegrate(window: np.ndarray, n: int, wrap: bool = False) -> np.ndarray:
+    """Unit-weight n-fold pre-integration of an integer window ([Hq, Wq], row 0 = smallest k2).
+
+    The recursions run in 128-bit integers.  With ``wrap=False`` a value outside int64 raises
+    OverflowError; with ``wrap=True`` the low 64 bits of every exact value are returned (the
+    result modulo 2^64, as two's-complement int64)."""
     lib = _load()
     w = np.ascontiguousarray(window, dtype=np.int64)
     Hq, Wq = w.shape
     g = np.empty_like(w)
     rc = lib.bsf_oracle_preintegrate(w.ctypes.data, Hq, Wq, int(n), g.ctypes.data)
-    if rc == -2:
+    if rc == -2 and not wrap:
         raise OverflowError("pre-integrated value exceeds int64")
-    if rc != 0:
+    if rc not in (0, -2):
         raise ValueError("bad arguments")
     return g

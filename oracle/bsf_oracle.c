@@ -281,7 +281,7 @@ int bsf_oracle_preintegrate(const int64_t* win, int Hq, int Wq, int n, int64_t* 
         for (int c = 0; c < Wq; ++c) {
             __int128 v = AT(r, c);
             if (v >= lim || v < -lim) rc = -2;
-            g[(size_t)r * Wq + c] = (int64_t)v;
+            g[(size_t)r * Wq + c] = (int64_t)(uint64_t)v; /* low 64 bits */
         }
 #undef AT
 #undef LEN

@@ -946,73 +946,263 @@ __global__ void reset_counters(unsigned* c) {
 }
 
 // ---------------------------------------------------------------------------
-// Global pre-integrator (bsf_preintegrate): stage 1 over an arbitrary window held in
-// HBM, hq rows of pitch wt = wq + hq - 1 (row r uses its first wt - r entries).
+// Global pre-integrator (bsf_preintegrate): stage 1 (eq. RS, n folds per direction)
+// over an arbitrary window held in HBM.  The workspace T has hq rows of pitch tp >= wt,
+// wt = wq + hq - 1; row r holds wt - r entries (the box, then the extension triangle
+// that step (4) reads).  Four passes, each reading and writing every element once:
+//   rows : f -> T, one workgroup per row, the n folds fused (chunked block scan);
+//   diag : T -> T along (1,1);  cols: T -> T along (0,1);  anti: T -> g along (-1,1).
+// The three upward passes give each wave a strip of kStrip adjacent lines (see
+// gpre_lines).  Arithmetic is modulo 2^64 (unsigned), exact wherever the true value
+// fits int64.
 // ---------------------------------------------------------------------------
 struct GlobalArgs {
     const void* in;
     long long in_pitch;
     int width, height, in_dtype, border;
     int x0, y0, wq, hq;
-    long long* T;  // workspace [hq][wt]
+    long long* T;  // workspace [hq][tp]
+    long long tp;  // workspace pitch: wt rounded up to a multiple of 4 (32-byte rows)
     long long* g;
     long long g_pitch;
 };
 
-__global__ void gpre_load(GlobalArgs A) {
-    const int wt = A.wq + A.hq - 1;
-    const long long total = (long long)A.hq * wt;
-    JobDesc t{};
-    t.in = A.in; t.in_pitch = A.in_pitch; t.width = A.width; t.height = A.height;
-    t.in_dtype = A.in_dtype; t.border = A.border;
-    const double scale = (A.in_dtype == BSF_U8) ? 1.0 : 16777216.0;  // float inputs on the 2^-24 grid
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
-         i += (long long)gridDim.x * blockDim.x) {
-        const int r = (int)(i / wt), c = (int)(i - (long long)r * wt);
-        long long v = 0;
-        if (c < A.wq) v = (long long)rint(load_sample(t, A.x0 + c, A.y0 + r) * scale);
-        A.T[i] = v;
-    }
-}
+constexpr int kStrip = 4;  // lines per wave in the upward passes
 
-// one lane per line, lines adjacent in memory at every step (coalesced walk)
-// dir 1: rows, 2: diagonals, 3: columns, 4: anti-diagonals
-__global__ void gpre_walk(GlobalArgs A, int dir) {
-    const int W = A.wq, H = A.hq, wt = W + H - 1;
-    const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    int r0, c0, dr, dc, len;
-    if (dir == 1) {
-        if (i >= H) return;
-        r0 = (int)i; c0 = 0; dr = 0; dc = 1; len = wt - r0;
-    } else if (dir == 2) {
-        if (i >= wt + H - 1) return;
-        const int e = (int)i - (H - 1);
-        const int rs = e < 0 ? -e : 0;
-        const int re = std::min(H - 1, (W + H - 2 - e) >> 1);
-        r0 = rs; c0 = e + rs; dr = 1; dc = 1; len = re - rs + 1;
-    } else if (dir == 3) {
-        if (i >= wt) return;
-        r0 = 0; c0 = (int)i; dr = 1; dc = 0; len = std::min(H, wt - c0);
+using u64 = unsigned long long;
+
+
+// Lines of the upward passes, by their column c0 at row 0:
+//   DIR 2 (1,1):  c(r) = c0 + r, c0 in [-(hq-1), wt-1], rows max(0,-c0) .. (wt-1-c0)/2
+//   DIR 3 (0,1):  c(r) = c0,     c0 in [0, wt-1],      rows 0 .. min(hq, wt-c0)-1
+//   DIR 4 (-1,1): c(r) = c0 - r, c0 in [0, wt-1],      rows 0 .. min(hq-1, c0)
+template <int DIR>
+__device__ __forceinline__ void line_rows(int c0, int hq, int wt, int& rs, int& re) {
+    if (DIR == 2) {
+        rs = c0 < 0 ? -c0 : 0;
+        re = min(hq, (wt - 1 - c0) / 2 + 1);
+    } else if (DIR == 3) {
+        rs = 0;
+        re = min(hq, wt - c0);
     } else {
-        if (i >= wt) return;
-        r0 = 0; c0 = (int)i; dr = 1; dc = -1; len = std::min(H, c0 + 1);
-    }
-    long long acc = 0;
-    for (int t = 0; t < len; ++t) {
-        long long* p = A.T + (long long)(r0 + t * dr) * wt + (c0 + t * dc);
-        acc = (long long)((unsigned long long)acc + (unsigned long long)*p);
-        *p = acc;
+        rs = 0;
+        re = min(hq, c0 + 1);
     }
 }
 
-__global__ void gpre_store(GlobalArgs A) {
-    const int wt = A.wq + A.hq - 1;
-    const long long total = (long long)A.hq * A.wq;
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
-         i += (long long)gridDim.x * blockDim.x) {
-        const int r = (int)(i / A.wq), c = (int)(i - (long long)r * A.wq);
-        A.g[(long long)r * A.g_pitch + c] = A.T[(long long)r * wt + c];
+// Carry state of the n-fold running sum of one line: s_f = the last value of fold f.
+// Feeding m zeros into a line with state c gives the state L^m c with
+//   (L^m c)_f = sum_{i <= f} c_i * binom(m - 1 + f - i, f - i).
+template <int N>
+__device__ __forceinline__ void propagate(const u64* c, u64 m, u64* out) {
+    const u64 b1 = m, b2 = (m * (m + 1)) >> 1;  // binom(m-1+k, k), k = 1, 2
+#pragma unroll
+    for (int f = 0; f < N; ++f) {
+        u64 v = c[f];
+        if (f >= 1) v += c[f - 1] * b1;
+        if (f >= 2) v += c[f - 2] * b2;
+        out[f] = v;
     }
+}
+
+// Every pass is a set of independent lines, each scanned n times.  A wave owns W
+// adjacent lines (W = 1 for the row pass, kStrip for the others) and walks them in
+// batches of NB * kRun positions: lane (i, j), i < W, j < NB = 64 / W, owns positions
+// j*kRun .. j*kRun + kRun-1 of line i.  A lane scans its positions in registers from a
+// zero state, a Kogge-Stone scan over j combines the blocks' end states with the carry
+// maps L, and each lane adds the closed-form contribution of its incoming state.
+// Loads run kAhead batches ahead of the scan.
+constexpr int kRun = 16;
+constexpr int kAhead = 2;
+
+template <int N, int W>
+__device__ __forceinline__ void scan_batch(u64 (&cur)[kRun], u64 (&carry)[N], int i, int j) {
+    constexpr int NB = 64 / W;
+    u64 agg[N];
+#pragma unroll
+    for (int f = 0; f < N; ++f) {
+#pragma unroll
+        for (int t = 1; t < kRun; ++t) cur[t] += cur[t - 1];
+        agg[f] = cur[kRun - 1];
+    }
+#pragma unroll
+    for (int d = 1; d < NB; d <<= 1) {
+        u64 prev[N], moved[N];
+#pragma unroll
+        for (int f = 0; f < N; ++f) prev[f] = __shfl_up(agg[f], d * W);
+        propagate<N>(prev, (u64)(d * kRun), moved);
+        if (j >= d) {
+#pragma unroll
+            for (int f = 0; f < N; ++f) agg[f] += moved[f];
+        }
+    }
+    u64 inc[N], before[N], ex[N], last[N], through[N];
+#pragma unroll
+    for (int f = 0; f < N; ++f) {
+        ex[f] = __shfl_up(agg[f], W);
+        last[f] = __shfl(agg[f], (NB - 1) * W + i);
+    }
+    propagate<N>(carry, (u64)(j * kRun), before);
+    propagate<N>(carry, (u64)(NB * kRun), through);
+#pragma unroll
+    for (int f = 0; f < N; ++f) {
+        inc[f] = before[f] + (j > 0 ? ex[f] : 0ull);
+        carry[f] = through[f] + last[f];
+    }
+#pragma unroll
+    for (int t = 0; t < kRun; ++t) {
+#pragma unroll
+        for (int f = 1; f < N; ++f) inc[f] += inc[f - 1];
+        cur[t] += inc[N - 1];
+    }
+}
+
+// Exact integer of an input sample: uint8 as is, float samples on the 2^-24 grid x 2^24.
+template <typename TIN>
+__device__ __forceinline__ u64 sample_int(TIN v) {
+    if constexpr (sizeof(TIN) == 1) return (u64)v;
+    else return (u64)(long long)rint((double)v * 16777216.0);
+}
+
+// Workspace tail behind the hq x tp array: 8 zero words that positions outside a line
+// read.  Selecting the address instead of the loaded value keeps every load
+// unconditional straight-line code (a load under a branch would be waited for at once),
+// so the loads of the next kAhead batches stay in flight while a batch is scanned.
+constexpr int kZeros = 8;
+
+__global__ void gpre_zero(GlobalArgs A) {
+    u64* z = (u64*)A.T + (long long)A.hq * A.tp;
+    if (threadIdx.x < kZeros) z[threadIdx.x] = 0ull;
+}
+
+// DIR 1: rows (f -> T), one wave per row.  DIR 2..4: strips of kStrip lines.
+template <int N, int DIR, typename TIN>
+__global__ __launch_bounds__(64) void gpre_pass(GlobalArgs A, int nwaves) {
+    constexpr int W = (DIR == 1) ? 1 : kStrip;
+    constexpr int NB = 64 / W;
+    constexpr int span = NB * kRun;
+    const int wt = A.wq + A.hq - 1, hq = A.hq;
+    const long long tp = A.tp;
+    const int lane = threadIdx.x, i = lane % W, j = lane / W;
+    const int w = xcd_tile(blockIdx.x, gridDim.x);
+    if (w >= nwaves) return;
+    u64* T = (u64*)A.T;
+    const u64* zeros = T + (long long)hq * tp;
+    // positions along the lines: [ps, pe) for this lane's line, [sps, spe) for the wave
+    int ps, pe, sps, spe, c0 = 0, r = 0;
+    if (DIR == 1) {
+        r = w;
+        ps = sps = 0;
+        pe = spe = wt - r;
+    } else {
+        const int first = (DIR == 2) ? -(hq - 1) : 0;
+        const int s0 = first + w * kStrip;
+        c0 = s0 + i;
+        line_rows<DIR>(c0, hq, wt, ps, pe);
+        if (c0 > wt - 1) { ps = 0; pe = 0; }
+        int a, b, a2, b2;  // the strip's extent: the union over its lines
+        line_rows<DIR>(min(s0 + kStrip - 1, wt - 1), hq, wt, a, b);
+        line_rows<DIR>(s0, hq, wt, a2, b2);
+        sps = min(a, a2);
+        spe = max(b, b2);
+    }
+    constexpr int dc = (DIR == 2) ? 1 : (DIR == 3 ? 0 : -1);
+    const long long stride = tp + dc;  // elements between consecutive positions of a line
+    // positions whose values are stored: the anti-diagonal pass writes only the box
+    const int qs = (DIR == 4) ? max(ps, c0 - A.wq + 1) : ps;
+    // row pass: the image row and whether it lies inside the image
+    const int yr = (DIR == 1) ? A.y0 + r : 0;
+    const bool row_in = yr >= 0 && yr < A.height;
+    const TIN* img_row = (const TIN*)A.in + (long long)clampi(yr, 0, A.height - 1) * A.in_pitch;
+    const bool zero_border = A.border == BSF_BORDER_ZERO;
+    auto load_batch = [&](u64 (&x)[kRun], int p0) {
+        const int q0 = p0 + j * kRun;
+        if (DIR == 1) {
+#pragma unroll
+            for (int t = 0; t < kRun; ++t) {
+                const int p = q0 + t;
+                const int xi = A.x0 + p;
+                const bool in = p < A.wq && (!zero_border || (row_in && xi >= 0 && xi < A.width));
+                const TIN* src = in ? img_row + clampi(xi, 0, A.width - 1) : (const TIN*)zeros;
+                x[t] = sample_int<TIN>(*src);
+            }
+        } else {
+            const long long base = (long long)q0 * stride + c0;
+#pragma unroll
+            for (int t = 0; t < kRun; ++t) {
+                const int p = q0 + t;
+                const bool in = p >= ps && p < pe;
+                x[t] = *(in ? T + base + t * stride : zeros);
+            }
+        }
+    };
+    auto store_batch = [&](const u64 (&x)[kRun], int p0) {
+        const int q0 = p0 + j * kRun;
+        if (DIR == 1) {
+            u64* row = T + (long long)r * tp;
+            if (q0 + kRun <= pe) {  // rows are 32-byte aligned (tp % 4 == 0), q0 % 16 == 0
+                ulonglong2* v = (ulonglong2*)(row + q0);
+#pragma unroll
+                for (int t = 0; t < kRun / 2; ++t) v[t] = make_ulonglong2(x[2 * t], x[2 * t + 1]);
+            } else {
+#pragma unroll
+                for (int t = 0; t < kRun; ++t)
+                    if (q0 + t < pe) row[q0 + t] = x[t];
+            }
+        } else {
+            u64* dst;
+            long long dstride;
+            if (DIR == 4) {  // g[p][c0 - p]
+                dst = (u64*)A.g + (long long)q0 * A.g_pitch + (c0 - q0);
+                dstride = A.g_pitch - 1;
+            } else {
+                dst = T + (long long)q0 * stride + c0;
+                dstride = stride;
+            }
+#pragma unroll
+            for (int t = 0; t < kRun; ++t) {
+                const int p = q0 + t;
+                if (p >= qs && p < pe) dst[t * dstride] = x[t];
+            }
+        }
+    };
+    u64 carry[N];
+#pragma unroll
+    for (int f = 0; f < N; ++f) carry[f] = 0;
+    u64 b0[kRun], b1[kRun], b2[kRun];
+    static_assert(kAhead == 2, "three rotating batch buffers");
+    load_batch(b0, sps);
+    load_batch(b1, sps + span);
+    // each step scans one batch while the loads of the next two are in flight
+    auto step = [&](u64 (&proc)[kRun], u64 (&fill)[kRun], int p0) {
+        load_batch(fill, p0 + kAhead * span);
+        scan_batch<N, W>(proc, carry, i, j);
+        store_batch(proc, p0);
+    };
+    for (int p0 = sps; p0 < spe; p0 += 3 * span) {
+        step(b0, b2, p0);
+        if (p0 + span >= spe) break;
+        step(b1, b0, p0 + span);
+        if (p0 + 2 * span >= spe) break;
+        step(b2, b1, p0 + 2 * span);
+    }
+}
+
+template <int N>
+void launch_global(const GlobalArgs& A, hipStream_t st) {
+    const int wt = A.wq + A.hq - 1;
+    const int nd = (wt + A.hq - 1 + kStrip - 1) / kStrip;
+    const int nc = (wt + kStrip - 1) / kStrip;
+    hipLaunchKernelGGL(gpre_zero, dim3(1), dim3(64), 0, st, A);
+    if (A.in_dtype == BSF_U8)
+        hipLaunchKernelGGL((gpre_pass<N, 1, unsigned char>), dim3(A.hq), dim3(64), 0, st, A, A.hq);
+    else if (A.in_dtype == BSF_F32)
+        hipLaunchKernelGGL((gpre_pass<N, 1, float>), dim3(A.hq), dim3(64), 0, st, A, A.hq);
+    else
+        hipLaunchKernelGGL((gpre_pass<N, 1, double>), dim3(A.hq), dim3(64), 0, st, A, A.hq);
+    hipLaunchKernelGGL((gpre_pass<N, 2, unsigned char>), dim3(nd), dim3(64), 0, st, A, nd);
+    hipLaunchKernelGGL((gpre_pass<N, 3, unsigned char>), dim3(nc), dim3(64), 0, st, A, nc);
+    hipLaunchKernelGGL((gpre_pass<N, 4, unsigned char>), dim3(nc), dim3(64), 0, st, A, nc);
 }
 
 }  // namespace bsf
@@ -1526,7 +1716,8 @@ bsf_status bsf_preintegrate(bsf_ctx* c, const bsf_job* j, int x0, int y0, int wq
     bsf_status s = validate(c, j, false);
     if (s != BSF_OK) return s;
     if (wq < 1 || hq < 1 || !g || g_pitch < wq) return fail(c, BSF_ERR_INVALID_ARG, "bad window");
-    const size_t need = (size_t)hq * (size_t)(wq + hq - 1) * 8;
+    const size_t tp = ((size_t)(wq + hq - 1) + 3) & ~(size_t)3;
+    const size_t need = (size_t)hq * tp * 8 + bsf::kZeros * 8;  // + the zero words
     if (need > c->ws_limit) return fail(c, BSF_ERR_OUT_OF_MEMORY, "window workspace exceeds the limit");
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
@@ -1553,16 +1744,13 @@ bsf_status bsf_preintegrate(bsf_ctx* c, const bsf_job* j, int x0, int y0, int wq
     A.wq = wq;
     A.hq = hq;
     A.T = (long long*)c->ws;
+    A.tp = (long long)tp;
     A.g = (long long*)g;
     A.g_pitch = g_pitch;
     hipStream_t st = (hipStream_t)stream;
-    hipLaunchKernelGGL(gpre_load, dim3(1024), dim3(256), 0, st, A);
-    const int wt = wq + hq - 1;
-    const int nlines[5] = {0, hq, wt + hq - 1, wt, wt};
-    for (int dir = 1; dir <= 4; ++dir)
-        for (int f = 0; f < j->order; ++f)
-            hipLaunchKernelGGL(gpre_walk, dim3((nlines[dir] + 255) / 256), dim3(256), 0, st, A, dir);
-    hipLaunchKernelGGL(gpre_store, dim3(1024), dim3(256), 0, st, A);
+    if (j->order == 1) bsf::launch_global<1>(A, st);
+    else if (j->order == 2) bsf::launch_global<2>(A, st);
+    else bsf::launch_global<3>(A, st);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(c, e, "pre-integration launch");
     return BSF_OK;

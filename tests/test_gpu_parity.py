@@ -79,6 +79,45 @@ def test_global_preintegrate_bit_exact(bsf, torch_dev, oracle_mod):
         assert np.array_equal(g, ref), n
 
 
+@pytest.mark.parametrize("n,x0,y0,wq,hq,dtype", [
+    (1, -7, -3, 1300, 20, np.uint8),     # rows longer than one 1024-element chunk
+    (2, -3, -9, 37, 260, np.float32),    # tall window, float samples on the 2^-24 grid
+    (3, 5, 1, 150, 140, np.uint8),       # values beyond int64: compared modulo 2^64
+    (2, -42, -42, 700, 700, np.uint8),
+    (1, 0, 0, 1, 1, np.uint8),
+])
+def test_global_preintegrate_large_windows(bsf, torch_dev, oracle_mod, n, x0, y0, wq, hq, dtype):
+    torch = torch_dev
+    rng = np.random.default_rng(103 + n)
+    H, W = 600, 610
+    if dtype == np.uint8:
+        img = rng.integers(0, 256, size=(H, W)).astype(np.uint8)
+        scale = 1
+    else:
+        img = (rng.integers(0, 1 << 24, size=(H, W)) / float(1 << 24)).astype(np.float32)
+        scale = 1 << 24
+    g = bsf.preintegrate(torch.from_numpy(img).cuda(), n, x0, y0, wq, hq).cpu().numpy()
+    ys = np.clip(np.arange(y0, y0 + hq), 0, H - 1)
+    xs = np.clip(np.arange(x0, x0 + wq), 0, W - 1)
+    win = np.rint(img[np.ix_(ys, xs)].astype(np.float64) * scale).astype(np.int64)
+    ref = oracle_mod.preintegrate(win, n, wrap=True)
+    assert np.array_equal(g, ref), (n, x0, y0, wq, hq)
+
+
+def test_global_preintegrate_plain_workload_full_size(bsf, torch_dev, oracle_mod):
+    """The paper's global stage 1 over the whole padded box of the 2048x2048 order-2 workload."""
+    torch = torch_dev
+    job = synth.config_job("plain")
+    x0 = y0 = -42
+    wq = hq = job.image.shape[0] + 84
+    g = bsf.preintegrate(torch.from_numpy(job.image).cuda(), 2, x0, y0, wq, hq).cpu().numpy()
+    H, W = job.image.shape
+    ys = np.clip(np.arange(y0, y0 + hq), 0, H - 1)
+    xs = np.clip(np.arange(x0, x0 + wq), 0, W - 1)
+    ref = oracle_mod.preintegrate(job.image[np.ix_(ys, xs)].astype(np.int64), 2, wrap=True)
+    assert np.array_equal(g, ref)
+
+
 def test_parity_order1_integer_scales_f64(bsf, torch_dev, oracle_mod):
     rng = np.random.default_rng(103)
     H, W = 50, 67  # several tiles and ragged edges

@@ -269,3 +269,17 @@ def test_preintegrate_extension_matches_large_zero_padding(oracle_mod):
     big[:, :Wq] = win
     gb = oracle_mod.preintegrate(big, 2)
     assert np.array_equal(oracle_mod.preintegrate(win, 2), gb[:, :Wq])
+
+
+def test_preintegrate_wrap_is_exact_modulo_2_64(oracle_mod):
+    """Stage 1 is linear and homogeneous: scaling the input by 2^s scales every exact value by
+    2^s, so the wrapped result of 2^s x must be (exact result of x) * 2^s modulo 2^64."""
+    rng = np.random.default_rng(43)
+    Hq, Wq, n, s = 40, 45, 3, 30
+    win = rng.integers(0, 256, size=(Hq, Wq))
+    exact = oracle_mod.preintegrate(win, n)  # fits int64
+    with pytest.raises(OverflowError):
+        oracle_mod.preintegrate(win << s, n)
+    wrapped = oracle_mod.preintegrate(win << s, n, wrap=True)
+    expect = (exact.astype(np.uint64) << np.uint64(s)).view(np.int64)
+    assert np.array_equal(wrapped, expect)
