@@ -242,10 +242,15 @@ __device__ __forceinline__ cp join_parts(const double* g) {
     }
 }
 
+// Window values as the mesh reads them.  SRC_INT: int64 running sums, split into PARTS
+// exact doubles of SHIFT bits.  SRC_DBL: the tile's values were all below
+// 2^exact_bits<N>() and were converted in place to doubles; one exact part suffices.
+constexpr int SRC_INT = 0, SRC_DBL = 1;
+
 // G_alpha = sum_j NUM[j][alpha] g[q + R j] for the monomials u1^a u2^b with ALO <= a <= AHI,
 // in PARTS exact partial sums.  Mirror pairs (j, j') enter once, as g + g' for even b
 // and g - g' for odd b.
-template <int N, int PARTS, int SHIFT, int ALO, int AHI>
+template <int N, int SRC, int PARTS, int SHIFT, int ALO, int AHI>
 __device__ __forceinline__ void accumulate_chunk(const long long* S, const TapFrame<N>& fr,
                                                  double (&G)[PARTS][mono_index<Tab<N>::DEG>(AHI, Tab<N>::DEG - AHI) -
                                                                     mono_index<Tab<N>::DEG>(ALO, 0) + 1],
@@ -254,6 +259,7 @@ __device__ __forceinline__ void accumulate_chunk(const long long* S, const TapFr
     constexpr int DEG = T::DEG;
     constexpr int M0 = mono_index<DEG>(ALO, 0);
     constexpr int CM = mono_index<DEG>(AHI, DEG - AHI) - M0 + 1;
+    const double* Sd = reinterpret_cast<const double*>(S);
 #pragma unroll
     for (int p = 0; p < PARTS; ++p)
 #pragma unroll
@@ -262,29 +268,36 @@ __device__ __forceinline__ void accumulate_chunk(const long long* S, const TapFr
     for (int j = 0; j < T::S; ++j) {
         if (!is_rep<N>(j)) continue;
         const int jm = mirror_of<N>(j);
-        const long long g1 = S[fr.base + T::jx(j) * fr.s1 + T::jy(j) * fr.s2];
-        if (jm == j) {
-            double x[PARTS];
-            split_int<PARTS, SHIFT>(g1, x);
-#pragma unroll
-            for (int c = 0; c < CM; ++c)
-                if (T::num(j, M0 + c) != 0.0)
-#pragma unroll
-                    for (int p = 0; p < PARTS; ++p) G[p][c] = __fma_rn(T::num(j, M0 + c), x[p], G[p][c]);
+        const int o1 = fr.base + T::jx(j) * fr.s1 + T::jy(j) * fr.s2;
+        const int o2 = fr.base + T::jx(jm) * fr.s1 + T::jy(jm) * fr.s2;
+        double x[PARTS], xs[PARTS], xd[PARTS];
+        if constexpr (SRC == SRC_DBL) {
+            const double g1 = Sd[o1];
+            if (jm == j) {
+                x[0] = g1;
+            } else {
+                const double g2 = Sd[o2];
+                xs[0] = g1 + g2;  // exact: |g| < 2^exact_bits <= 2^50
+                xd[0] = g1 - g2;
+            }
         } else {
-            const long long g2 = S[fr.base + T::jx(jm) * fr.s1 + T::jy(jm) * fr.s2];
-            double xs[PARTS], xd[PARTS];
-            split_int<PARTS, SHIFT>(add_ovf(g1, g2, bad), xs);
-            split_int<PARTS, SHIFT>(sub_ovf(g1, g2, bad), xd);
-#pragma unroll
-            for (int c = 0; c < CM; ++c)
-                if (T::num(j, M0 + c) != 0.0) {
-                    const bool odd = T::mb(M0 + c) & 1;
-#pragma unroll
-                    for (int p = 0; p < PARTS; ++p)
-                        G[p][c] = __fma_rn(T::num(j, M0 + c), odd ? xd[p] : xs[p], G[p][c]);
-                }
+            const long long g1 = S[o1];
+            if (jm == j) {
+                split_int<PARTS, SHIFT>(g1, x);
+            } else {
+                const long long g2 = S[o2];
+                split_int<PARTS, SHIFT>(add_ovf(g1, g2, bad), xs);
+                split_int<PARTS, SHIFT>(sub_ovf(g1, g2, bad), xd);
+            }
         }
+#pragma unroll
+        for (int c = 0; c < CM; ++c)
+            if (T::num(j, M0 + c) != 0.0) {
+                const bool odd = T::mb(M0 + c) & 1;
+#pragma unroll
+                for (int p = 0; p < PARTS; ++p)
+                    G[p][c] = __fma_rn(T::num(j, M0 + c), jm == j ? x[p] : (odd ? xd[p] : xs[p]), G[p][c]);
+            }
     }
 }
 
@@ -301,7 +314,7 @@ __constant__ double c_num3[bsf_tables::kStencil3][bsf_tables::kMono3] = BSF_NUM3
 __constant__ int c_j3[bsf_tables::kStencil3][2] = BSF_J3_INIT;
 __constant__ MirrorTab3 c_mirror3 = MirrorTab3();
 
-template <int PARTS, int SHIFT, int ALO, int AHI>
+template <int SRC, int PARTS, int SHIFT, int ALO, int AHI>
 __device__ __forceinline__ void accumulate_chunk3(const long long* S, const TapFrame<3>& fr,
                                                   double (&G)[PARTS][mono_index<10>(AHI, 10 - AHI) -
                                                                      mono_index<10>(ALO, 0) + 1],
@@ -309,6 +322,7 @@ __device__ __forceinline__ void accumulate_chunk3(const long long* S, const TapF
     using T = Tab<3>;
     constexpr int M0 = mono_index<10>(ALO, 0);
     constexpr int CM = mono_index<10>(AHI, 10 - AHI) - M0 + 1;
+    const double* Sd = reinterpret_cast<const double*>(S);
     asm volatile("" ::: "memory");  // keep each chunk's LDS reads local to the chunk
 #pragma unroll
     for (int p = 0; p < PARTS; ++p)
@@ -319,10 +333,11 @@ __device__ __forceinline__ void accumulate_chunk3(const long long* S, const TapF
         const int jy = c_j3[j][1];
         if (jy < 0) continue;  // odd order: representatives have jy >= 0
         const int jx = c_j3[j][0];
-        const long long g1 = S[fr.base + jx * fr.s1 + jy * fr.s2];
+        const int o1 = fr.base + jx * fr.s1 + jy * fr.s2, o2 = fr.base + jx * fr.s1 - jy * fr.s2;
         if (jy == 0) {
             double x[PARTS];
-            split_int<PARTS, SHIFT>(g1, x);
+            if constexpr (SRC == SRC_DBL) x[0] = Sd[o1];
+            else split_int<PARTS, SHIFT>(S[o1], x);
 #pragma unroll
             for (int c = 0; c < CM; ++c) {
                 const double w = c_num3[j][M0 + c];
@@ -330,10 +345,16 @@ __device__ __forceinline__ void accumulate_chunk3(const long long* S, const TapF
                 for (int p = 0; p < PARTS; ++p) G[p][c] = __fma_rn(w, x[p], G[p][c]);
             }
         } else {
-            const long long g2 = S[fr.base + jx * fr.s1 - jy * fr.s2];
             double xs[PARTS], xd[PARTS];
-            split_int<PARTS, SHIFT>(add_ovf(g1, g2, bad), xs);
-            split_int<PARTS, SHIFT>(sub_ovf(g1, g2, bad), xd);
+            if constexpr (SRC == SRC_DBL) {
+                const double g1 = Sd[o1], g2 = Sd[o2];
+                xs[0] = g1 + g2;
+                xd[0] = g1 - g2;
+            } else {
+                const long long g1 = S[o1], g2 = S[o2];
+                split_int<PARTS, SHIFT>(add_ovf(g1, g2, bad), xs);
+                split_int<PARTS, SHIFT>(sub_ovf(g1, g2, bad), xd);
+            }
 #pragma unroll
             for (int c = 0; c < CM; ++c) {
                 const double w = c_num3[j][M0 + c];
@@ -368,6 +389,20 @@ __device__ __forceinline__ void horner_chunk_dd(
     }
 }
 
+template <int N, int SRC, int ALO, int AHI, bool FIRST>
+__device__ __forceinline__ void interp_chunk_dd(const long long* S, const TapFrame<N>& fr, dd v1, dd v2, cp& P,
+                                                unsigned& bad) {
+    using T = Tab<N>;
+    constexpr int PARTS = SRC == SRC_DBL ? 1 : T::SPLIT;
+    double G[PARTS][mono_index<T::DEG>(AHI, T::DEG - AHI) - mono_index<T::DEG>(ALO, 0) + 1];
+    if constexpr (N == 3)
+        accumulate_chunk3<SRC, PARTS, T::SHIFT, ALO, AHI>(S, fr, G, bad);
+    else
+        accumulate_chunk<N, SRC, PARTS, T::SHIFT, ALO, AHI>(S, fr, G, bad);
+    horner_chunk_dd<N, PARTS, T::SHIFT, ALO, AHI, FIRST>(G, v1, v2, P);
+}
+
+// Horner over the chunk's u1-powers AHI..ALO in plain double, continuing P.
 template <int N, int ALO, int AHI, bool FIRST>
 __device__ __forceinline__ void horner_chunk_f64(
     const double (&G)[1][mono_index<Tab<N>::DEG>(AHI, Tab<N>::DEG - AHI) - mono_index<Tab<N>::DEG>(ALO, 0) + 1],
@@ -383,66 +418,51 @@ __device__ __forceinline__ void horner_chunk_f64(
     }
 }
 
-template <int N, int ALO, int AHI, bool FIRST>
-__device__ __forceinline__ void interp_chunk_dd(const long long* S, const TapFrame<N>& fr, dd v1, dd v2, cp& P,
-                                                unsigned& bad) {
-    using T = Tab<N>;
-    double G[T::SPLIT][mono_index<T::DEG>(AHI, T::DEG - AHI) - mono_index<T::DEG>(ALO, 0) + 1];
-    if constexpr (N == 3)
-        accumulate_chunk3<T::SPLIT, T::SHIFT, ALO, AHI>(S, fr, G, bad);
-    else
-        accumulate_chunk<N, T::SPLIT, T::SHIFT, ALO, AHI>(S, fr, G, bad);
-    horner_chunk_dd<N, T::SPLIT, T::SHIFT, ALO, AHI, FIRST>(G, v1, v2, P);
-}
-
-template <int N, int ALO, int AHI, bool FIRST>
+template <int N, int SRC, int ALO, int AHI, bool FIRST>
 __device__ __forceinline__ void interp_chunk_f64(const long long* S, const TapFrame<N>& fr, double v1, double v2,
                                                  double& P, unsigned& bad) {
     using T = Tab<N>;
     double G[1][mono_index<T::DEG>(AHI, T::DEG - AHI) - mono_index<T::DEG>(ALO, 0) + 1];
     if constexpr (N == 3)
-        accumulate_chunk3<1, 0, ALO, AHI>(S, fr, G, bad);
+        accumulate_chunk3<SRC, 1, 0, ALO, AHI>(S, fr, G, bad);
     else
-        accumulate_chunk<N, 1, 0, ALO, AHI>(S, fr, G, bad);
+        accumulate_chunk<N, SRC, 1, 0, ALO, AHI>(S, fr, G, bad);
     horner_chunk_f64<N, ALO, AHI, FIRST>(G, v1, v2, P);
 }
 
-// sum_j g[q+j] beta(o + u - j) = (1/DEN) sum_alpha G_alpha v^alpha: double-double with the
-// coefficients accumulated exactly (order 3 in three u1-chunks to bound registers).
-template <int N>
+// sum_j g[q+j] beta(o + u - j) = (1/DEN) sum_alpha G_alpha v^alpha: the coefficients
+// accumulated exactly, the polynomial in compensated arithmetic (order 3 in u1-chunks
+// to bound registers).
+template <int N, int SRC>
 __device__ __forceinline__ cp interp_dd(const long long* S, const TapFrame<N>& fr, dd v1, dd v2, unsigned& bad) {
     using T = Tab<N>;
     cp P = {0.0, 0.0};
     if constexpr (N < 3) {
-        double G[T::SPLIT][T::M];
-        accumulate_chunk<N, T::SPLIT, T::SHIFT, 0, T::DEG>(S, fr, G, bad);
-        horner_chunk_dd<N, T::SPLIT, T::SHIFT, 0, T::DEG, true>(G, v1, v2, P);
+        interp_chunk_dd<N, SRC, 0, T::DEG, true>(S, fr, v1, v2, P, bad);
     } else {
-        interp_chunk_dd<N, 7, 10, true>(S, fr, v1, v2, P, bad);
-        interp_chunk_dd<N, 5, 6, false>(S, fr, v1, v2, P, bad);
-        interp_chunk_dd<N, 3, 4, false>(S, fr, v1, v2, P, bad);
-        interp_chunk_dd<N, 2, 2, false>(S, fr, v1, v2, P, bad);
-        interp_chunk_dd<N, 0, 1, false>(S, fr, v1, v2, P, bad);
+        interp_chunk_dd<N, SRC, 7, 10, true>(S, fr, v1, v2, P, bad);
+        interp_chunk_dd<N, SRC, 5, 6, false>(S, fr, v1, v2, P, bad);
+        interp_chunk_dd<N, SRC, 3, 4, false>(S, fr, v1, v2, P, bad);
+        interp_chunk_dd<N, SRC, 2, 2, false>(S, fr, v1, v2, P, bad);
+        interp_chunk_dd<N, SRC, 0, 1, false>(S, fr, v1, v2, P, bad);
     }
     return P;
 }
 
 // the same in plain double
-template <int N>
+template <int N, int SRC>
 __device__ __forceinline__ double interp_f64(const long long* S, const TapFrame<N>& fr, double v1, double v2,
                                              unsigned& bad) {
     using T = Tab<N>;
     double P = 0.0;
     if constexpr (N < 3) {
-        double G[1][T::M];
-        accumulate_chunk<N, 1, 0, 0, T::DEG>(S, fr, G, bad);
-        horner_chunk_f64<N, 0, T::DEG, true>(G, v1, v2, P);
+        interp_chunk_f64<N, SRC, 0, T::DEG, true>(S, fr, v1, v2, P, bad);
     } else {
-        interp_chunk_f64<N, 7, 10, true>(S, fr, v1, v2, P, bad);
-        interp_chunk_f64<N, 5, 6, false>(S, fr, v1, v2, P, bad);
-        interp_chunk_f64<N, 3, 4, false>(S, fr, v1, v2, P, bad);
-        interp_chunk_f64<N, 2, 2, false>(S, fr, v1, v2, P, bad);
-        interp_chunk_f64<N, 0, 1, false>(S, fr, v1, v2, P, bad);
+        interp_chunk_f64<N, SRC, 7, 10, true>(S, fr, v1, v2, P, bad);
+        interp_chunk_f64<N, SRC, 5, 6, false>(S, fr, v1, v2, P, bad);
+        interp_chunk_f64<N, SRC, 3, 4, false>(S, fr, v1, v2, P, bad);
+        interp_chunk_f64<N, SRC, 2, 2, false>(S, fr, v1, v2, P, bad);
+        interp_chunk_f64<N, SRC, 0, 1, false>(S, fr, v1, v2, P, bad);
     }
     return P;
 }
@@ -465,7 +485,7 @@ __device__ __forceinline__ int cell_triangle(double u1, double u2) {
 // n tau per Section 7 (the shift of eq. factor, n-fold).  Window coordinates: (mx, my)
 // is the pixel relative to the window origin.  Returns s in units of the integer
 // samples (the caller applies the input quantum).
-template <int N>
+template <int N, int SRC>
 __device__ dd mesh_dd(const long long* S, int wq, int hq, int mx, int my, float4 a, unsigned& bad) {
     const dd isq = {kInvSqrt2Hi, kInvSqrt2Lo};
     const double a1 = a.x, a3 = a.z;
@@ -512,7 +532,7 @@ __device__ dd mesh_dd(const long long* S, int wq, int hq, int mx, int my, float4
                         bad = 1;
                         continue;
                     }
-                    const cp P = interp_dd<N>(S, fr, v1, v2, bad);
+                    const cp P = interp_dd<N, SRC>(S, fr, v1, v2, bad);
                     const int c = binom(N, k1) * binom(N, k2) * binom(N, k3) * binom(N, k4);
                     const double cs = ((k1 + k2 + k3 + k4) & 1) ? -(double)c : (double)c;
                     acc = cp_axpy(acc, cs, P);
@@ -535,7 +555,7 @@ __device__ double finalize_dd(dd acc, float4 a) {
     return r.hi + r.lo;
 }
 
-template <int N>
+template <int N, int SRC>
 __device__ double mesh_f64(const long long* S, int wq, int hq, int mx, int my, float4 a, unsigned& bad) {  // raw sum
     const double a1 = a.x, a3 = a.z;
     const double A2 = (double)a.y * kInvSqrt2Hi, A4 = (double)a.w * kInvSqrt2Hi;
@@ -568,7 +588,7 @@ __device__ double mesh_f64(const long long* S, int wq, int hq, int mx, int my, f
                         bad = 1;
                         continue;
                     }
-                    const double P = interp_f64<N>(S, fr, v1, v2, bad);
+                    const double P = interp_f64<N, SRC>(S, fr, v1, v2, bad);
                     const int c = binom(N, k1) * binom(N, k2) * binom(N, k3) * binom(N, k4);
                     acc = __fma_rn(((k1 + k2 + k3 + k4) & 1) ? -(double)c : (double)c, P, acc);
                 }
@@ -786,12 +806,29 @@ __device__ __forceinline__ void process_tile(const JobDesc A, int job, int tile,
                 overflowed = true;
                 break;
             }
+            // when every value the mesh reads is below 2^exact_bits, hold the box as exact
+            // doubles: the coefficient sums then need one part and no conversions per tap
+            unsigned long long mag = 0;
+            for (int i = tid; i < g.qn; i += kThreads) {
+                const long long v = S[i];
+                mag |= (unsigned long long)(v < 0 ? -v : v);
+            }
+            const bool fast = !__syncthreads_or((mag >> exact_bits<N>()) != 0ull);
+            if (fast) {
+                for (int i = tid; i < g.qn; i += kThreads) reinterpret_cast<double*>(S)[i] = (double)S[i];
+                __syncthreads();
+            }
             if (inside && valid) {
                 const double wk = ldexp(1.0, k * B);
-                if (PATH == BSF_PATH_F64)
-                    acc_dd = dd_add(acc_dd, dd_mul_d(mesh_dd<N>(S, g.wq, g.hq, mx, my, a, bad), wk));
-                else
-                    acc_f = __fma_rn(mesh_f64<N>(S, g.wq, g.hq, mx, my, a, bad), wk, acc_f);
+                if (PATH == BSF_PATH_F64) {
+                    const dd m = fast ? mesh_dd<N, SRC_DBL>(S, g.wq, g.hq, mx, my, a, bad)
+                                      : mesh_dd<N, SRC_INT>(S, g.wq, g.hq, mx, my, a, bad);
+                    acc_dd = dd_add(acc_dd, dd_mul_d(m, wk));
+                } else {
+                    const double m = fast ? mesh_f64<N, SRC_DBL>(S, g.wq, g.hq, mx, my, a, bad)
+                                          : mesh_f64<N, SRC_INT>(S, g.wq, g.hq, mx, my, a, bad);
+                    acc_f = __fma_rn(m, wk, acc_f);
+                }
             }
         }
         done = !overflowed;
@@ -834,7 +871,8 @@ __device__ __forceinline__ void process_any(const JobDesc A, int job, int tile, 
 
 // Tier 1 of a single job: one workgroup per tile.
 template <int N, int PATH>
-__global__ __launch_bounds__(kThreads) void tile_kernel(JobDesc A, Launch L) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(N < 3 ? 2 : 1))) void tile_kernel(
+    JobDesc A, Launch L) {
     extern __shared__ long long S[];
     __shared__ Shared sh;
     process_tile<N, PATH>(A, 0, xcd_tile(blockIdx.x, gridDim.x), L, S, sh);

@@ -141,6 +141,28 @@ struct Tab<3> {
 // The reference triangle u1 >= |u2| is symmetric under u2 -> -u2 (about the cell
 // centre), so stencil point j and its mirror j' = (jx, e - jy) (e = 0 odd n, 1 even n)
 // carry the same polynomials up to the sign (-1)^b of the u2-power b.
+// Largest B such that 2^B * max_alpha sum_j |NUM[j][alpha]| <= 2^53: when every window
+// value is below 2^B in magnitude, each coefficient sum G_alpha, its products and all
+// its partial sums are integers below 2^53, exact in a single double.
+template <int N>
+__host__ __device__ constexpr int exact_bits() {
+    using T = Tab<N>;
+    double l1max = 0.0;
+    for (int m = 0; m < T::M; ++m) {
+        double l1 = 0.0;
+        for (int j = 0; j < T::S; ++j) l1 += T::num(j, m) < 0 ? -T::num(j, m) : T::num(j, m);
+        l1max = l1 > l1max ? l1 : l1max;
+    }
+    double lim = 9007199254740992.0;  // 2^53
+    int b = 0;
+    double p = 1.0;
+    while (p * 2.0 * l1max <= lim) {
+        p *= 2.0;
+        ++b;
+    }
+    return b;
+}
+
 template <int N>
 __host__ __device__ constexpr int mirror_of(int j) {
     const int e = (N & 1) ? 0 : 1;

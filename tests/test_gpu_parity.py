@@ -228,6 +228,20 @@ def test_f32_path_error_is_stated(bsf, torch_dev, oracle_mod):
     assert rel_max(s.astype(np.float64), o) < 1e-5
 
 
+@pytest.mark.parametrize("n,lo,hi", [(1, 0.5, 1.5), (2, 0.5, 1.5), (3, 0.5, 1.2)])
+def test_parity_smallest_scales(bsf, torch_dev, oracle_mod, n, lo, hi):
+    """Scales near the admissible minimum: the mesh cancels the most here (the output is
+    a small difference of large interpolated running sums)."""
+    rng = np.random.default_rng(120 + n)
+    H, W = 23, 26
+    sc = synth.uniform_scales(rng, H, W, lo, hi)
+    img = rng.integers(0, 256, size=(H, W)).astype(np.uint8)
+    s, st = run(bsf, torch_dev, img, sc, n)
+    assert st == 0
+    o = oracle_mod.filter(img.astype(np.float64), sc, n)
+    assert rel_max(s, o) < TOL_F64, (n, rel_max(s, o))
+
+
 def test_parity_order3_u8_and_float(bsf, torch_dev, oracle_mod):
     rng = np.random.default_rng(110)
     H, W = 19, 21
