@@ -813,7 +813,8 @@ __device__ __forceinline__ void process_tile(const JobDesc A, int job, int tile,
                 const long long v = S[i];
                 mag |= (unsigned long long)(v < 0 ? -v : v);
             }
-            const bool fast = !__syncthreads_or((mag >> exact_bits<N>()) != 0ull);
+            constexpr int kExact = exact_bits<N>();  // folded at compile time
+            const bool fast = !__syncthreads_or((mag >> kExact) != 0ull);
             if (fast) {
                 for (int i = tid; i < g.qn; i += kThreads) reinterpret_cast<double*>(S)[i] = (double)S[i];
                 __syncthreads();
