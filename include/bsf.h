@@ -63,9 +63,11 @@ typedef enum { BSF_U8 = 0, BSF_F32 = 1, BSF_F64 = 2 } bsf_dtype;
 
 /* BSF_PATH_F64: output float64; mesh interpolation and accumulation in double-double,
  *   so the result matches the exact filter to a few float64 ulps.
- * BSF_PATH_F32_TILED: output float32; the same exact pre-integration, mesh in plain
- *   float64.  Its error grows with the cancellation the mesh performs, about 1e-7 of the
- *   output's magnitude for order 2 at scales up to 32 (float32 rounding dominates). */
+ * BSF_PATH_F32_TILED: output float32; the same restart windows with the running sums
+ *   and the mesh in plain float64 (no integer grid, no digit passes).  Its error is the
+ *   mesh's cancellation times a few float64 roundings: below 1e-5 of the output's
+ *   magnitude for orders 1-3 at every scale in [0.5, 32] that was measured, and about
+ *   1e-7 at scales >= 1 (float32 rounding then dominates). */
 typedef enum { BSF_PATH_F64 = 0, BSF_PATH_F32_TILED = 1 } bsf_path;
 
 /* Boundary rule for samples outside the image (the paper leaves it open): clamp to
@@ -134,7 +136,9 @@ bsf_status bsf_get_device_error(bsf_ctx* ctx, void* stream);
  * (what bsf_filter does) or 0 for the recursions' zero start at the window's lower-left
  * edges; the call writes geom[0..3] = x0, y0, wq, hq of the window and geom[5] = 1 if a
  * value left the int64 range and geom[6] = the power of two sh the samples were scaled by
- * (the window holds the digit-free running sums of f_ext * 2^sh).  Asynchronous on `stream`. */
+ * (the window holds the digit-free running sums of f_ext * 2^sh).  For the float32-output
+ * path the window holds float64 running sums of f_ext, as bit patterns, and geom[5..6]
+ * are 0.  Asynchronous on `stream`. */
 bsf_status bsf_debug_tile_window(bsf_ctx* ctx, const bsf_job* job, int tile, int64_t* window,
                                  long long cap, int* geom, void* stream);
 

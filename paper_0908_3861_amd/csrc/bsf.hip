@@ -83,6 +83,9 @@ __device__ __forceinline__ long long sub_ovf(long long a, long long b, unsigned&
     ovf |= (unsigned)(((a ^ b) & (a ^ s)) < 0);
     return s;
 }
+// float64 running sums (the float32-output path): rounded, no range check
+__device__ __forceinline__ double add_ovf(double a, double b, unsigned&) { return a + b; }
+__device__ __forceinline__ double sub_ovf(double a, double b, unsigned&) { return a - b; }
 
 // Running sum along one line of the window: points (r0 + t*dr, c0 + t*dc), t < len.
 // tref < 0: y[t] = sum_{s<=t} x[s] (zero initial condition at the line's start, as in
@@ -90,14 +93,14 @@ __device__ __forceinline__ long long sub_ovf(long long a, long long b, unsigned&
 // anchored at y[tref] = 0; the two differ by a constant along the line, which every
 // finite difference of the mesh along that direction cancels, and it keeps the
 // integers small near the tile centre.
-__device__ void scan_line(long long* S, const Geo& g, int r0, int c0, int dr, int dc, int len, int tref,
-                          unsigned& ovf) {
+template <typename V>
+__device__ void scan_line(V* S, const Geo& g, int r0, int c0, int dr, int dc, int len, int tref, unsigned& ovf) {
     constexpr int B = 8;
-    long long acc = 0;
+    V acc = 0;
     int t = tref + 1;
     for (; t + B <= len; t += B) {
         int ad[B];
-        long long v[B];
+        V v[B];
 #pragma unroll
         for (int i = 0; i < B; ++i) ad[i] = waddr(g, r0 + (t + i) * dr, c0 + (t + i) * dc);
 #pragma unroll
@@ -115,12 +118,12 @@ __device__ void scan_line(long long* S, const Geo& g, int r0, int c0, int dr, in
     }
     if (tref >= 0) {
         const int aref = waddr(g, r0 + tref * dr, c0 + tref * dc);
-        long long prev = S[aref];
+        V prev = S[aref];
         acc = 0;
         t = tref - 1;
         for (; t - B + 1 >= 0; t -= B) {
             int ad[B];
-            long long v[B];
+            V v[B];
 #pragma unroll
             for (int i = 0; i < B; ++i) ad[i] = waddr(g, r0 + (t - i) * dr, c0 + (t - i) * dc);
 #pragma unroll
@@ -146,8 +149,8 @@ __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? l
 
 // Stage 1 on the window (eq. RS steps (1)-(4), n folds each).  cen: anchor every
 // line at the tile centre (cc, rc) instead of at its start.
-__device__ void preintegrate_window(long long* S, const Geo& g, int n, bool cen, int cc, int rc,
-                                    unsigned& ovf) {
+template <typename V>
+__device__ void preintegrate_window(V* S, const Geo& g, int n, bool cen, int cc, int rc, unsigned& ovf) {
     const int tid = threadIdx.x, nt = blockDim.x;
     const int W = g.wq, H = g.hq, Wt = W + H - 1;
     for (int f = 0; f < n; ++f) {  // (1) along (1,0): rows
@@ -742,6 +745,49 @@ __device__ __forceinline__ void process_tile(const JobDesc A, int job, int tile,
     const Geo g = {w.wq, w.hq, w.wq * w.hq};
     const int ntri = (g.hq * (g.hq - 1)) / 2;
 
+    const bool cen = !L.dbg_window || L.dbg_geom[4];
+    const int cc = t1 + tw / 2 - w.x0, rc = t2 + th / 2 - w.y0;  // centre of the tile's own extent
+    const int mx = m1 - w.x0, my = m2 - w.y0;
+
+    if constexpr (PATH == BSF_PATH_F32_TILED) {
+        // float32 output: stage 1 in float64 (rounded running sums of the samples as they
+        // are), the mesh in float64 from the window as it stands -- no integer grid, no
+        // digits.  The error is the mesh's cancellation times a few float64 roundings.
+        double* Sd = reinterpret_cast<double*>(S);
+        for (int i = tid; i < g.qn; i += kThreads) {
+            const int r = i / g.wq, c = i - r * g.wq;
+            Sd[i] = load_sample(A, w.x0 + c, w.y0 + r);
+        }
+        for (int i = tid; i < ntri; i += kThreads) Sd[g.qn + i] = 0.0;
+        __syncthreads();
+        unsigned unused = 0;
+        preintegrate_window(Sd, g, N, cen, cc, rc, unused);
+        __syncthreads();
+        if (L.dbg_window) {  // the window as float64 bit patterns
+            if (tid == 0) {
+                L.dbg_geom[0] = w.x0; L.dbg_geom[1] = w.y0; L.dbg_geom[2] = w.wq; L.dbg_geom[3] = w.hq;
+                L.dbg_geom[5] = 0;
+                L.dbg_geom[6] = 0;
+            }
+            if ((long long)g.qn <= L.dbg_cap)
+                for (int i = tid; i < g.qn; i += kThreads) L.dbg_window[i] = S[i];
+            return;
+        }
+        if (!inside) return;
+        if (!valid) {
+            store(nan);
+            return;
+        }
+        unsigned bad = 0;
+        double s = finalize_f64<N>(mesh_f64<N, SRC_DBL>(S, g.wq, g.hq, mx, my, a, bad), a);
+        if (bad) {
+            atomicOr(L.err, kErrWindow);
+            s = nan;
+        }
+        store(s);
+        return;
+    }
+
     // 3. an exact integer grid for the window: samples become v * 2^sh with at most 53
     //    significant bits (finer bits than 2^-53 of the window maximum are rounded)
     int top = -1100, fine = 0;
@@ -764,10 +810,6 @@ __device__ __forceinline__ void process_tile(const JobDesc A, int job, int tile,
     fine = max(max(redi[1][0], redi[1][1]), max(redi[1][2], redi[1][3]));
     const int sh = (top + fine > 53) ? 53 - top : fine;
     const int bits = max(top + sh, 1);
-
-    const bool cen = !L.dbg_window || L.dbg_geom[4];
-    const int cc = t1 + tw / 2 - w.x0, rc = t2 + th / 2 - w.y0;  // centre of the tile's own extent
-    const int mx = m1 - w.x0, my = m2 - w.y0;
 
     // 4. stage 1 + mesh, on K base-2^B digits of the samples when the running sums of
     //    the whole samples would leave int64 (the filter is linear in the image)
@@ -853,22 +895,8 @@ __device__ __forceinline__ void process_tile(const JobDesc A, int job, int tile,
     store(s);
 }
 
-// Runtime dispatch on (order, path) for launches that mix jobs; the window is addressed
-// through the kernel's dynamic LDS symbol.
+// The window of the batch kernels, addressed through the kernel's dynamic LDS symbol.
 extern __shared__ long long g_lds[];
-
-__device__ __forceinline__ void process_any(const JobDesc A, int job, int tile, const Launch L, long long* S,
-                                            Shared& sh) {
-    const int v = (A.order - 1) * 2 + A.path;
-    switch (v) {
-        case 0: process_tile<1, BSF_PATH_F64>(A, job, tile, L, S, sh); break;
-        case 1: process_tile<1, BSF_PATH_F32_TILED>(A, job, tile, L, S, sh); break;
-        case 2: process_tile<2, BSF_PATH_F64>(A, job, tile, L, S, sh); break;
-        case 3: process_tile<2, BSF_PATH_F32_TILED>(A, job, tile, L, S, sh); break;
-        case 4: process_tile<3, BSF_PATH_F64>(A, job, tile, L, S, sh); break;
-        default: process_tile<3, BSF_PATH_F32_TILED>(A, job, tile, L, S, sh); break;
-    }
-}
 
 // Tier 1 of a single job: one workgroup per tile.
 template <int N, int PATH>
@@ -943,32 +971,37 @@ __device__ __forceinline__ int find_job(const JobDesc* jobs, int njobs, long lon
     return lo;
 }
 
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 2))) void batch_kernel(
-    const JobDesc* jobs, int njobs, long long total, Launch L, unsigned* cursor) {
+// One (order, path) variant of a batch: its jobs are jobs[j0 .. j0+nj), its items
+// first .. first+count-1 in the batch's numbering.  Each variant runs in kernels of its
+// own, so every variant gets the registers and LDS its own tiles need.
+template <int N, int PATH>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(N < 3 ? 2 : 1))) void batch_kernel(
+    const JobDesc* jobs, int j0, int nj, long long first, long long count, Launch L, unsigned* cursor) {
     __shared__ Shared sh;
     for (;;) {
         const long long i = next_item(cursor, sh);
-        if (i >= total) break;
-        const int j = find_job(jobs, njobs, i);
+        if (i >= count) break;
+        const int j = j0 + find_job(jobs + j0, nj, first + i);
         const JobDesc A = jobs[j];
-        process_any(A, j, (int)(i - A.item_base), L, g_lds, sh);
+        process_tile<N, PATH>(A, j, (int)(first + i - A.item_base), L, g_lds, sh);
     }
 }
 
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void batch_overflow_kernel(
-    const JobDesc* jobs, Launch L, ItemList in) {
+template <int N, int PATH>
+__global__ __launch_bounds__(kThreads) void batch_overflow_kernel(const JobDesc* jobs, Launch L, ItemList in) {
     __shared__ Shared sh;
     const int total = (int)min(*in.count, (unsigned)in.cap);
     for (;;) {
         const int i = next_item(in.cursor, sh);
         if (i >= total) break;
         const int2 it = in.items[i];
-        process_any(jobs[it.x], it.x, it.y, L, g_lds, sh);
+        process_tile<N, PATH>(jobs[it.x], it.x, it.y, L, g_lds, sh);
     }
 }
 
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 2))) void batch_scratch_kernel(
-    const JobDesc* jobs, Launch L, ItemList in, long long* scratch) {
+template <int N, int PATH>
+__global__ __launch_bounds__(kThreads) void batch_scratch_kernel(const JobDesc* jobs, Launch L, ItemList in,
+                                                                 long long* scratch) {
     __shared__ Shared sh;
     long long* S = scratch + (long long)blockIdx.x * L.lds_cap;
     const int total = (int)min(*in.count, (unsigned)in.cap);
@@ -976,12 +1009,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 2))
         const int i = next_item(in.cursor, sh);
         if (i >= total) break;
         const int2 it = in.items[i];
-        process_any(jobs[it.x], it.x, it.y, L, S, sh);
+        process_tile<N, PATH>(jobs[it.x], it.x, it.y, L, S, sh);
     }
 }
 
+// The 64 counters at the head of a call's work area (8 per batch variant).
 __global__ void reset_counters(unsigned* c) {
-    if (threadIdx.x < 8) c[threadIdx.x] = 0u;
+    if (threadIdx.x < 64) c[threadIdx.x] = 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -1384,11 +1418,12 @@ struct Tiers {
     int grid2 = 1, grid3 = 1;
 };
 
-Tiers make_tiers(const bsf_ctx* c, const Plan& p, char* work, const WorkLayout& w, long long items) {
+// Tiers over `items` tiles whose overflow lists are la / lb (capacity items each) and
+// whose counters are ctr[0..4]: [0] list A count, [1] list A cursor, [2] tier-1 cursor,
+// [3] list B count, [4] list B cursor.
+Tiers make_tiers_at(const bsf_ctx* c, const Plan& p, unsigned* ctr, int2* la, int2* lb, long long* scratch,
+                    long long items) {
     Tiers t;
-    unsigned* ctr = (unsigned*)work;
-    int2* la = (int2*)(work + w.lists_off);
-    int2* lb = (int2*)(work + w.listb_off);
     t.L1 = Launch{};
     t.L1.lds_cap = p.t1;
     t.L1.err = c->d_err;
@@ -1409,9 +1444,15 @@ Tiers make_tiers(const bsf_ctx* c, const Plan& p, char* work, const WorkLayout& 
         t.L2.push_cap = (int)items;
         t.inB = ItemList{ctr + 3, lb, ctr + 4, (int)items};
         t.grid3 = (int)std::min<long long>(items, (long long)c->cus * 2);
-        t.scratch = (long long*)(work + w.scratch_off);
+        t.scratch = scratch;
     }
     return t;
+}
+
+Tiers make_tiers(const bsf_ctx* c, const Plan& p, char* work, const WorkLayout& w, long long items) {
+    if (!work) return make_tiers_at(c, p, nullptr, nullptr, nullptr, nullptr, items);  // tier 1 only
+    return make_tiers_at(c, p, (unsigned*)work, (int2*)(work + w.lists_off), (int2*)(work + w.listb_off),
+                         (long long*)(work + w.scratch_off), items);
 }
 
 template <int N, int PATH>
@@ -1551,10 +1592,58 @@ long long measure_static_lds() {
     static_lds(&debug_tile_kernel<1, 1>, mx);
     static_lds(&debug_tile_kernel<2, 1>, mx);
     static_lds(&debug_tile_kernel<3, 1>, mx);
-    static_lds(&batch_kernel, mx);
-    static_lds(&batch_overflow_kernel, mx);
-    static_lds(&batch_scratch_kernel, mx);
+    static_lds(&batch_kernel<1, 0>, mx);
+    static_lds(&batch_kernel<2, 0>, mx);
+    static_lds(&batch_kernel<3, 0>, mx);
+    static_lds(&batch_kernel<1, 1>, mx);
+    static_lds(&batch_kernel<2, 1>, mx);
+    static_lds(&batch_kernel<3, 1>, mx);
+    static_lds(&batch_overflow_kernel<1, 0>, mx);
+    static_lds(&batch_overflow_kernel<2, 0>, mx);
+    static_lds(&batch_overflow_kernel<3, 0>, mx);
+    static_lds(&batch_overflow_kernel<1, 1>, mx);
+    static_lds(&batch_overflow_kernel<2, 1>, mx);
+    static_lds(&batch_overflow_kernel<3, 1>, mx);
+    static_lds(&batch_scratch_kernel<1, 0>, mx);
+    static_lds(&batch_scratch_kernel<2, 0>, mx);
+    static_lds(&batch_scratch_kernel<3, 0>, mx);
+    static_lds(&batch_scratch_kernel<1, 1>, mx);
+    static_lds(&batch_scratch_kernel<2, 1>, mx);
+    static_lds(&batch_scratch_kernel<3, 1>, mx);
     return mx;
+}
+
+template <int N, int PATH>
+hipError_t launch_batch_group(const bsf_ctx* c, const JobDesc* djobs, int j0, int nj, long long first,
+                              long long count, const Plan& p, const Tiers& t, unsigned* ctr, hipStream_t st) {
+    static bool once = false;
+    if (!once) {
+        allow_big_lds(&batch_kernel<N, PATH>);
+        allow_big_lds(&batch_overflow_kernel<N, PATH>);
+        once = true;
+    }
+    const int grid1 = (int)std::min<long long>(count, (long long)c->cus * std::min(per_cu(c, p.t1), 8));
+    hipLaunchKernelGGL((batch_kernel<N, PATH>), dim3(grid1), dim3(kThreads), (size_t)p.t1 * 8, st, djobs, j0, nj,
+                       first, count, t.L1, ctr + 2);
+    if (p.use2)
+        hipLaunchKernelGGL((batch_overflow_kernel<N, PATH>), dim3(t.grid2), dim3(kThreads), (size_t)p.t2 * 8, st,
+                           djobs, t.L2, t.inA);
+    if (p.use3)
+        hipLaunchKernelGGL((batch_scratch_kernel<N, PATH>), dim3(t.grid3), dim3(kThreads), 0, st, djobs, t.L3, t.inB,
+                           t.scratch);
+    return hipGetLastError();
+}
+
+hipError_t dispatch_batch_group(const bsf_ctx* c, int v, const JobDesc* djobs, int j0, int nj, long long first,
+                                long long count, const Plan& p, const Tiers& t, unsigned* ctr, hipStream_t st) {
+    switch (v) {
+        case 0: return launch_batch_group<1, 0>(c, djobs, j0, nj, first, count, p, t, ctr, st);
+        case 1: return launch_batch_group<1, 1>(c, djobs, j0, nj, first, count, p, t, ctr, st);
+        case 2: return launch_batch_group<2, 0>(c, djobs, j0, nj, first, count, p, t, ctr, st);
+        case 3: return launch_batch_group<2, 1>(c, djobs, j0, nj, first, count, p, t, ctr, st);
+        case 4: return launch_batch_group<3, 0>(c, djobs, j0, nj, first, count, p, t, ctr, st);
+        default: return launch_batch_group<3, 1>(c, djobs, j0, nj, first, count, p, t, ctr, st);
+    }
 }
 
 }  // namespace
@@ -1688,20 +1777,29 @@ bsf_status bsf_filter_batched(bsf_ctx* c, const bsf_job* jobs, int njobs, void* 
     if (!c) return BSF_ERR_INVALID_ARG;
     if (njobs < 0 || (njobs > 0 && !jobs)) return fail(c, BSF_ERR_INVALID_ARG, "bad batch");
     if (njobs == 0) return BSF_OK;
-    long long need = 0;
+    constexpr int kVariants = 6;  // (order - 1) * 2 + path
+    long long need[kVariants] = {};
+    double vcost[kVariants] = {};
     std::vector<int> order(njobs);
     std::vector<double> cost(njobs);
     for (int i = 0; i < njobs; ++i) {
         bsf_status s = validate(c, jobs + i, true);
         if (s != BSF_OK) return fail(c, s, "job " + std::to_string(i) + ": " + c->last);
-        need = std::max(need, job_window_need(c, jobs + i));
-        const int n = jobs[i].order;
+        const int n = jobs[i].order, v = (n - 1) * 2 + (int)jobs[i].path;
+        need[v] = std::max(need[v], job_window_need(c, jobs + i));
         // per-pixel mesh work ~ (n+1)^4 taps x 7n^2 interpolation weights
         cost[i] = (double)jobs[i].width * jobs[i].height * std::pow(n + 1.0, 4) * 7.0 * n * n;
+        vcost[v] += cost[i];
         order[i] = i;
     }
-    // heaviest jobs first: their tiles are handed out first (longest-processing-time order)
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    // jobs grouped by variant, heaviest variant first, and heaviest jobs first within a
+    // variant: their tiles are handed out first (longest-processing-time order)
+    auto var = [&](int i) { return (jobs[i].order - 1) * 2 + (int)jobs[i].path; };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        const int va = var(a), vb = var(b);
+        if (va != vb) return vcost[va] > vcost[vb] || (vcost[va] == vcost[vb] && va < vb);
+        return cost[a] > cost[b];
+    });
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
@@ -1709,9 +1807,34 @@ bsf_status bsf_filter_batched(bsf_ctx* c, const bsf_job* jobs, int njobs, void* 
     for (int k = 0; k < njobs; ++k)
         total += (long long)((jobs[order[k]].width + kTile - 1) / kTile) * ((jobs[order[k]].height + kTile - 1) / kTile);
     if (total >= (1ll << 31)) return fail(c, BSF_ERR_INVALID_ARG, "batch has too many tiles");
-    const Plan p = plan_tiers(c, need);
-    const int grid3 = (int)std::min<long long>(total, (long long)c->cus * 2);
-    const WorkLayout w = work_layout(total, njobs, p.use3 ? (size_t)grid3 * (size_t)p.t3 * 8 : 0);
+    // groups: contiguous runs of one variant in `order`
+    struct Group {
+        int v, j0, nj;
+        long long first, count;
+        Plan p;
+    };
+    std::vector<Group> groups;
+    size_t scratch_bytes = 0;
+    {
+        long long items = 0;
+        for (int k = 0; k < njobs;) {
+            Group g{var(order[k]), k, 0, items, 0, Plan{}};
+            while (k < njobs && var(order[k]) == g.v) {
+                items += (long long)((jobs[order[k]].width + kTile - 1) / kTile) *
+                         ((jobs[order[k]].height + kTile - 1) / kTile);
+                ++k;
+                ++g.nj;
+            }
+            g.count = items - g.first;
+            g.p = plan_tiers(c, need[g.v]);
+            if (g.p.use3) {
+                const long long grid3 = std::min<long long>(g.count, (long long)c->cus * 2);
+                scratch_bytes = std::max(scratch_bytes, (size_t)grid3 * (size_t)g.p.t3 * 8);
+            }
+            groups.push_back(g);
+        }
+    }
+    const WorkLayout w = work_layout(total, njobs, scratch_bytes);
     int slot = -1;
     bsf_status s = acquire_slot(c, w.total, njobs, slot);
     if (s != BSF_OK) return s;
@@ -1727,24 +1850,17 @@ bsf_status bsf_filter_batched(bsf_ctx* c, const bsf_job* jobs, int njobs, void* 
     const JobDesc* djobs = (const JobDesc*)(work + w.jobs_off);
     e = hipMemcpyAsync((void*)djobs, sl.host, sizeof(JobDesc) * (size_t)njobs, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return hip_fail(c, e, "uploading the batch descriptors");
-    const Tiers t = make_tiers(c, p, work, w, total);
-    static bool once = false;
-    if (!once) {
-        allow_big_lds(&batch_kernel);
-        allow_big_lds(&batch_overflow_kernel);
-        once = true;
-    }
     hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, st, (unsigned*)work);
-    const int grid1 = (int)std::min<long long>(total, (long long)c->cus * std::min(per_cu(c, p.t1), 8));
-    hipLaunchKernelGGL(batch_kernel, dim3(grid1), dim3(kThreads), (size_t)p.t1 * 8, st, djobs, njobs, total, t.L1,
-                       (unsigned*)work + 2);
-    if (p.use2)
-        hipLaunchKernelGGL(batch_overflow_kernel, dim3(t.grid2), dim3(kThreads), (size_t)p.t2 * 8, st, djobs, t.L2,
-                           t.inA);
-    if (p.use3)
-        hipLaunchKernelGGL(batch_scratch_kernel, dim3(t.grid3), dim3(kThreads), 0, st, djobs, t.L3, t.inB, t.scratch);
-    e = hipGetLastError();
-    if (e == hipSuccess) e = hipEventRecord(sl.done, st);
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+        const Group& g = groups[gi];
+        unsigned* ctr = (unsigned*)work + 8 * g.v;  // each variant appears in one group
+        const Tiers t = make_tiers_at(c, g.p, ctr, (int2*)(work + w.lists_off) + g.first,
+                                      (int2*)(work + w.listb_off) + g.first, (long long*)(work + w.scratch_off),
+                                      g.count);
+        e = dispatch_batch_group(c, g.v, djobs, g.j0, g.nj, g.first, g.count, g.p, t, ctr, st);
+        if (e != hipSuccess) return hip_fail(c, e, "batch kernel launch");
+    }
+    e = hipEventRecord(sl.done, st);
     if (e != hipSuccess) return hip_fail(c, e, "batch kernel launch");
     return BSF_OK;
 }
