@@ -304,18 +304,36 @@ __device__ __forceinline__ void accumulate_chunk(const long long* S, const TapFr
     }
 }
 
-// Order 3: the same accumulation with a runtime loop over the stencil (the table rows are
-// uniform across the wave and come from constant memory).  Fully unrolled, order 3 would
-// be tens of thousands of instructions per variant.
-struct MirrorTab3 {
-    int m[bsf_tables::kStencil3];
-    constexpr MirrorTab3() : m() {
-        for (int j = 0; j < bsf_tables::kStencil3; ++j) m[j] = mirror_of<3>(j);
+// Order 3: the same accumulation with a runtime loop over the stencil; fully unrolled,
+// order 3 would be tens of thousands of instructions per variant, and its table values
+// (up to 6e7) do not fit the literal forms of the FMA, so each would first be built in
+// registers.  The table rows come from constant memory, laid out chunk by chunk: the
+// slice one u1-chunk reads (at most 63 x 21 doubles, 10.6 KB) is contiguous and stays
+// in the scalar cache across the taps, where the row-major 33 KB table thrashes it.
+template <int ALO, int AHI>
+struct Num3Chunk {
+    static constexpr int M0 = mono_index<10>(ALO, 0);
+    static constexpr int CM = mono_index<10>(AHI, 10 - AHI) - M0 + 1;
+    double w[bsf_tables::kStencil3][CM];
+    constexpr Num3Chunk() : w() {
+        for (int j = 0; j < bsf_tables::kStencil3; ++j)
+            for (int c = 0; c < CM; ++c) w[j][c] = bsf_tables::kNum3[j][M0 + c];
     }
 };
-__constant__ double c_num3[bsf_tables::kStencil3][bsf_tables::kMono3] = BSF_NUM3_INIT;
+__constant__ Num3Chunk<7, 10> c_num3_a = Num3Chunk<7, 10>();
+__constant__ Num3Chunk<5, 6> c_num3_b = Num3Chunk<5, 6>();
+__constant__ Num3Chunk<3, 4> c_num3_c = Num3Chunk<3, 4>();
+__constant__ Num3Chunk<2, 2> c_num3_d = Num3Chunk<2, 2>();
+__constant__ Num3Chunk<0, 1> c_num3_e = Num3Chunk<0, 1>();
+template <int ALO, int AHI>
+__device__ __forceinline__ const Num3Chunk<ALO, AHI>& num3_chunk() {
+    if constexpr (ALO == 7) return c_num3_a;
+    else if constexpr (ALO == 5) return c_num3_b;
+    else if constexpr (ALO == 3) return c_num3_c;
+    else if constexpr (ALO == 2) return c_num3_d;
+    else return c_num3_e;
+}
 __constant__ int c_j3[bsf_tables::kStencil3][2] = BSF_J3_INIT;
-__constant__ MirrorTab3 c_mirror3 = MirrorTab3();
 
 template <int SRC, int PARTS, int SHIFT, int ALO, int AHI>
 __device__ __forceinline__ void accumulate_chunk3(const long long* S, const TapFrame<3>& fr,
@@ -326,6 +344,7 @@ __device__ __forceinline__ void accumulate_chunk3(const long long* S, const TapF
     constexpr int M0 = mono_index<10>(ALO, 0);
     constexpr int CM = mono_index<10>(AHI, 10 - AHI) - M0 + 1;
     const double* Sd = reinterpret_cast<const double*>(S);
+    const auto& tab = num3_chunk<ALO, AHI>();
     asm volatile("" ::: "memory");  // keep each chunk's LDS reads local to the chunk
 #pragma unroll
     for (int p = 0; p < PARTS; ++p)
@@ -343,7 +362,7 @@ __device__ __forceinline__ void accumulate_chunk3(const long long* S, const TapF
             else split_int<PARTS, SHIFT>(S[o1], x);
 #pragma unroll
             for (int c = 0; c < CM; ++c) {
-                const double w = c_num3[j][M0 + c];
+                const double w = tab.w[j][c];
 #pragma unroll
                 for (int p = 0; p < PARTS; ++p) G[p][c] = __fma_rn(w, x[p], G[p][c]);
             }
@@ -360,7 +379,7 @@ __device__ __forceinline__ void accumulate_chunk3(const long long* S, const TapF
             }
 #pragma unroll
             for (int c = 0; c < CM; ++c) {
-                const double w = c_num3[j][M0 + c];
+                const double w = tab.w[j][c];
 #pragma unroll
                 for (int p = 0; p < PARTS; ++p)
                     G[p][c] = __fma_rn(w, (T::mb(M0 + c) & 1) ? xd[p] : xs[p], G[p][c]);
@@ -489,7 +508,8 @@ __device__ __forceinline__ int cell_triangle(double u1, double u2) {
 // is the pixel relative to the window origin.  Returns s in units of the integer
 // samples (the caller applies the input quantum).
 template <int N, int SRC>
-__device__ dd mesh_dd(const long long* S, int wq, int hq, int mx, int my, float4 a, unsigned& bad) {
+__device__ dd mesh_dd(const long long* S, int wq, int hq, int mx, int my, float4 a, int k2lo, int k2hi,
+                      unsigned& bad) {
     const dd isq = {kInvSqrt2Hi, kInvSqrt2Lo};
     const double a1 = a.x, a3 = a.z;
     const dd A2 = dd_mul_d(isq, (double)a.y);  // a'_2 = a2/sqrt2 (lattice units along (1,1))
@@ -499,7 +519,7 @@ __device__ dd mesh_dd(const long long* S, int wq, int hq, int mx, int my, float4
     const dd T1 = dd_mul_d(dd_add_d(dd_add(A2, dd_neg(A4)), a1 - 1.0), h);
     const dd T2 = dd_mul_d(dd_add_d(dd_add(A2, A4), a3 - 3.0), h);
     cp acc = {0.0, 0.0};
-    for (int k2 = 0; k2 <= N; ++k2) {
+    for (int k2 = k2lo; k2 <= k2hi; ++k2) {
         for (int k4 = 0; k4 <= N; ++k4) {
             const dd D2 = dd_mul_d(A2, (double)k2), D4 = dd_mul_d(A4, (double)k4);
             const dd B1 = dd_add(T1, dd_add(D4, dd_neg(D2)));        // n tau_1 - k2 a'2 + k4 a'4
@@ -559,14 +579,15 @@ __device__ double finalize_dd(dd acc, float4 a) {
 }
 
 template <int N, int SRC>
-__device__ double mesh_f64(const long long* S, int wq, int hq, int mx, int my, float4 a, unsigned& bad) {  // raw sum
+__device__ double mesh_f64(const long long* S, int wq, int hq, int mx, int my, float4 a, int k2lo, int k2hi,
+                           unsigned& bad) {  // raw sum over k2 in [k2lo, k2hi]
     const double a1 = a.x, a3 = a.z;
     const double A2 = (double)a.y * kInvSqrt2Hi, A4 = (double)a.w * kInvSqrt2Hi;
     constexpr double h = 0.5 * N;
     const double T1 = h * (a1 + A2 - A4 - 1.0);
     const double T2 = h * (A2 + a3 + A4 - 3.0);
     double acc = 0.0;
-    for (int k2 = 0; k2 <= N; ++k2) {
+    for (int k2 = k2lo; k2 <= k2hi; ++k2) {
         for (int k4 = 0; k4 <= N; ++k4) {
             const double B1 = T1 - k2 * A2 + k4 * A4;
             const double B2 = T2 - k2 * A2 - k4 * A4;
@@ -668,10 +689,32 @@ __device__ __forceinline__ int wave_max_i(int v) {
 }
 
 struct Shared {
-    double red[2][kThreads / 64];
-    int redi[2][kThreads / 64];
+    double red[2][kMaxWaves];
+    int redi[2][kMaxWaves];
     int item;
 };
+
+// Order 3: the thread pair of a pixel adds its two partial tap sums, in a fixed order
+// (first half + second half), and merges its error flags; the first thread keeps them.
+template <int SPLIT>
+__device__ __forceinline__ void combine_halves(dd& acc, unsigned& bad) {
+    if constexpr (SPLIT == 2) {
+        __shared__ double part[2][kThreads];
+        __shared__ unsigned partbad[kThreads];
+        const int pix = threadIdx.x % kThreads;
+        __syncthreads();
+        if (threadIdx.x >= kThreads) {
+            part[0][pix] = acc.hi;
+            part[1][pix] = acc.lo;
+            partbad[pix] = bad;
+        }
+        __syncthreads();
+        if (threadIdx.x < kThreads) {
+            acc = dd_add(acc, dd{part[0][pix], part[1][pix]});
+            bad |= partbad[pix];
+        }
+    }
+}
 
 // Filter one 16x16 tile of job A (index `job`) with the window in S.
 template <int N, int PATH>
@@ -679,12 +722,15 @@ __device__ __forceinline__ void process_tile(const JobDesc A, int job, int tile,
                                              Shared& sh_) {
     auto& red = sh_.red;
     auto& redi = sh_.redi;
+    constexpr int SPLIT = split_of<N, PATH>(), NT = threads_of<N, PATH>(), NW = NT / 64;
     const int tid = threadIdx.x;
+    const int pix = tid % kThreads, half = tid / kThreads;  // the pixel, and the thread's share of its taps
+    const int k2lo = SPLIT == 1 ? 0 : half * (N + 1) / 2, k2hi = SPLIT == 1 ? N : (half + 1) * (N + 1) / 2 - 1;
     __syncthreads();  // the previous item of this workgroup is done with S and the scratch
     const int tx = tile % A.tiles_x, ty = tile / A.tiles_x;
     const int t1 = tx * kTile, t2 = ty * kTile;
     const int tw = std::min(kTile, A.width - t1), th = std::min(kTile, A.height - t2);
-    const int px = tid % kTile, py = tid / kTile;
+    const int px = pix % kTile, py = pix / kTile;
     const int m1 = t1 + px, m2 = t2 + py;
     const bool inside = px < tw && py < th;
 
@@ -708,15 +754,20 @@ __device__ __forceinline__ void process_tile(const JobDesc A, int job, int tile,
         red[1][tid >> 6] = R2;
     }
     __syncthreads();
-    R1 = fmax(fmax(red[0][0], red[0][1]), fmax(red[0][2], red[0][3]));
-    R2 = fmax(fmax(red[1][0], red[1][1]), fmax(red[1][2], red[1][3]));
+    R1 = red[0][0];
+    R2 = red[1][0];
+#pragma unroll
+    for (int wv = 1; wv < NW; ++wv) {
+        R1 = fmax(R1, red[0][wv]);
+        R2 = fmax(R2, red[1][wv]);
+    }
 
     // 2. the restart window
     const Window w = tile_window<N>(t1, t2, tw, th, R1, R2);
     const long long need = window_elems(w);
     const double nan = __builtin_nan("");
     auto store = [&](double v) {
-        if (!inside) return;
+        if (!inside || half) return;
         const long long off = (long long)m2 * A.out_pitch + m1;
         if (PATH == BSF_PATH_F64)
             ((double*)A.out)[off] = v;
@@ -754,11 +805,11 @@ __device__ __forceinline__ void process_tile(const JobDesc A, int job, int tile,
         // are), the mesh in float64 from the window as it stands -- no integer grid, no
         // digits.  The error is the mesh's cancellation times a few float64 roundings.
         double* Sd = reinterpret_cast<double*>(S);
-        for (int i = tid; i < g.qn; i += kThreads) {
+        for (int i = tid; i < g.qn; i += NT) {
             const int r = i / g.wq, c = i - r * g.wq;
             Sd[i] = load_sample(A, w.x0 + c, w.y0 + r);
         }
-        for (int i = tid; i < ntri; i += kThreads) Sd[g.qn + i] = 0.0;
+        for (int i = tid; i < ntri; i += NT) Sd[g.qn + i] = 0.0;
         __syncthreads();
         unsigned unused = 0;
         preintegrate_window(Sd, g, N, cen, cc, rc, unused);
@@ -770,16 +821,19 @@ __device__ __forceinline__ void process_tile(const JobDesc A, int job, int tile,
                 L.dbg_geom[6] = 0;
             }
             if ((long long)g.qn <= L.dbg_cap)
-                for (int i = tid; i < g.qn; i += kThreads) L.dbg_window[i] = S[i];
+                for (int i = tid; i < g.qn; i += NT) L.dbg_window[i] = S[i];
             return;
         }
-        if (!inside) return;
+        unsigned bad = 0;
+        dd m = {0.0, 0.0};
+        if (inside && valid) m.hi = mesh_f64<N, SRC_DBL>(S, g.wq, g.hq, mx, my, a, k2lo, k2hi, bad);
+        combine_halves<SPLIT>(m, bad);
+        if (!inside || half) return;
         if (!valid) {
             store(nan);
             return;
         }
-        unsigned bad = 0;
-        double s = finalize_f64<N>(mesh_f64<N, SRC_DBL>(S, g.wq, g.hq, mx, my, a, bad), a);
+        double s = finalize_f64<N>(m.hi, a);
         if (bad) {
             atomicOr(L.err, kErrWindow);
             s = nan;
@@ -791,7 +845,7 @@ __device__ __forceinline__ void process_tile(const JobDesc A, int job, int tile,
     // 3. an exact integer grid for the window: samples become v * 2^sh with at most 53
     //    significant bits (finer bits than 2^-53 of the window maximum are rounded)
     int top = -1100, fine = 0;
-    for (int i = tid; i < g.qn; i += kThreads) {
+    for (int i = tid; i < g.qn; i += NT) {
         const int r = i / g.wq, c = i - r * g.wq;
         int t_, f_;
         sample_grid(load_sample(A, w.x0 + c, w.y0 + r), t_, f_);
@@ -806,8 +860,13 @@ __device__ __forceinline__ void process_tile(const JobDesc A, int job, int tile,
         redi[1][tid >> 6] = fine;
     }
     __syncthreads();
-    top = max(max(redi[0][0], redi[0][1]), max(redi[0][2], redi[0][3]));
-    fine = max(max(redi[1][0], redi[1][1]), max(redi[1][2], redi[1][3]));
+    top = redi[0][0];
+    fine = redi[1][0];
+#pragma unroll
+    for (int wv = 1; wv < NW; ++wv) {
+        top = max(top, redi[0][wv]);
+        fine = max(fine, redi[1][wv]);
+    }
     const int sh = (top + fine > 53) ? 53 - top : fine;
     const int bits = max(top + sh, 1);
 
@@ -824,12 +883,12 @@ __device__ __forceinline__ void process_tile(const JobDesc A, int job, int tile,
         bool overflowed = false;
         for (int k = 0; k < K; ++k) {
             __syncthreads();  // the previous digit's mesh has finished reading the window
-            for (int i = tid; i < g.qn; i += kThreads) {
+            for (int i = tid; i < g.qn; i += NT) {
                 const int r = i / g.wq, c = i - r * g.wq;
                 const long long iv = (long long)rint(ldexp(load_sample(A, w.x0 + c, w.y0 + r), sh));
                 S[i] = digit(iv, k, K, B);
             }
-            for (int i = tid; i < ntri; i += kThreads) S[g.qn + i] = 0;
+            for (int i = tid; i < ntri; i += NT) S[g.qn + i] = 0;
             __syncthreads();
             unsigned ovf = 0;
             preintegrate_window(S, g, N, cen, cc, rc, ovf);
@@ -841,7 +900,7 @@ __device__ __forceinline__ void process_tile(const JobDesc A, int job, int tile,
                     L.dbg_geom[6] = sh;
                 }
                 if ((long long)g.qn <= L.dbg_cap)
-                    for (int i = tid; i < g.qn; i += kThreads) L.dbg_window[i] = S[i];
+                    for (int i = tid; i < g.qn; i += NT) L.dbg_window[i] = S[i];
                 return;
             }
             if (ovf) {
@@ -851,25 +910,25 @@ __device__ __forceinline__ void process_tile(const JobDesc A, int job, int tile,
             // when every value the mesh reads is below 2^exact_bits, hold the box as exact
             // doubles: the coefficient sums then need one part and no conversions per tap
             unsigned long long mag = 0;
-            for (int i = tid; i < g.qn; i += kThreads) {
+            for (int i = tid; i < g.qn; i += NT) {
                 const long long v = S[i];
                 mag |= (unsigned long long)(v < 0 ? -v : v);
             }
             constexpr int kExact = exact_bits<N>();  // folded at compile time
             const bool fast = !__syncthreads_or((mag >> kExact) != 0ull);
             if (fast) {
-                for (int i = tid; i < g.qn; i += kThreads) reinterpret_cast<double*>(S)[i] = (double)S[i];
+                for (int i = tid; i < g.qn; i += NT) reinterpret_cast<double*>(S)[i] = (double)S[i];
                 __syncthreads();
             }
             if (inside && valid) {
                 const double wk = ldexp(1.0, k * B);
                 if (PATH == BSF_PATH_F64) {
-                    const dd m = fast ? mesh_dd<N, SRC_DBL>(S, g.wq, g.hq, mx, my, a, bad)
-                                      : mesh_dd<N, SRC_INT>(S, g.wq, g.hq, mx, my, a, bad);
+                    const dd m = fast ? mesh_dd<N, SRC_DBL>(S, g.wq, g.hq, mx, my, a, k2lo, k2hi, bad)
+                                      : mesh_dd<N, SRC_INT>(S, g.wq, g.hq, mx, my, a, k2lo, k2hi, bad);
                     acc_dd = dd_add(acc_dd, dd_mul_d(m, wk));
                 } else {
-                    const double m = fast ? mesh_f64<N, SRC_DBL>(S, g.wq, g.hq, mx, my, a, bad)
-                                          : mesh_f64<N, SRC_INT>(S, g.wq, g.hq, mx, my, a, bad);
+                    const double m = fast ? mesh_f64<N, SRC_DBL>(S, g.wq, g.hq, mx, my, a, k2lo, k2hi, bad)
+                                          : mesh_f64<N, SRC_INT>(S, g.wq, g.hq, mx, my, a, k2lo, k2hi, bad);
                     acc_f = __fma_rn(m, wk, acc_f);
                 }
             }
@@ -881,7 +940,14 @@ __device__ __forceinline__ void process_tile(const JobDesc A, int job, int tile,
         store(nan);
         return;
     }
-    if (!inside) return;
+    if (PATH == BSF_PATH_F64) {
+        combine_halves<SPLIT>(acc_dd, bad);
+    } else {
+        dd t = {acc_f, 0.0};
+        combine_halves<SPLIT>(t, bad);
+        acc_f = t.hi;
+    }
+    if (!inside || half) return;
     if (!valid) {
         store(nan);
         return;
@@ -900,7 +966,7 @@ extern __shared__ long long g_lds[];
 
 // Tier 1 of a single job: one workgroup per tile.
 template <int N, int PATH>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(N < 3 ? 2 : 1))) void tile_kernel(
+__global__ __launch_bounds__((threads_of<N, PATH>())) __attribute__((amdgpu_waves_per_eu(N < 3 ? 2 : 1))) void tile_kernel(
     JobDesc A, Launch L) {
     extern __shared__ long long S[];
     __shared__ Shared sh;
@@ -909,7 +975,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(N < 3 
 
 // Test aid: stage 1 of one tile.
 template <int N, int PATH>
-__global__ __launch_bounds__(kThreads) void debug_tile_kernel(JobDesc A, Launch L, int tile) {
+__global__ __launch_bounds__((threads_of<N, PATH>())) void debug_tile_kernel(JobDesc A, Launch L, int tile) {
     extern __shared__ long long S[];
     __shared__ Shared sh;
     process_tile<N, PATH>(A, 0, tile, L, S, sh);
@@ -934,7 +1000,7 @@ struct ItemList {
 
 // Tier 2 of a single job: the tiles that did not fit tier 1's LDS (full LDS here).
 template <int N, int PATH>
-__global__ __launch_bounds__(kThreads) void overflow_kernel(JobDesc A, Launch L, ItemList in) {
+__global__ __launch_bounds__((threads_of<N, PATH>())) void overflow_kernel(JobDesc A, Launch L, ItemList in) {
     extern __shared__ long long S[];
     __shared__ Shared sh;
     const int total = (int)min(*in.count, (unsigned)in.cap);
@@ -948,7 +1014,7 @@ __global__ __launch_bounds__(kThreads) void overflow_kernel(JobDesc A, Launch L,
 // Tier 3 of a single job: windows larger than any workgroup's LDS, each workgroup
 // working in its own slice of a global scratch buffer (L2/MALL-resident).
 template <int N, int PATH>
-__global__ __launch_bounds__(kThreads) void scratch_kernel(JobDesc A, Launch L, ItemList in, long long* scratch) {
+__global__ __launch_bounds__((threads_of<N, PATH>())) void scratch_kernel(JobDesc A, Launch L, ItemList in, long long* scratch) {
     __shared__ Shared sh;
     long long* S = scratch + (long long)blockIdx.x * L.lds_cap;
     const int total = (int)min(*in.count, (unsigned)in.cap);
@@ -975,7 +1041,7 @@ __device__ __forceinline__ int find_job(const JobDesc* jobs, int njobs, long lon
 // first .. first+count-1 in the batch's numbering.  Each variant runs in kernels of its
 // own, so every variant gets the registers and LDS its own tiles need.
 template <int N, int PATH>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(N < 3 ? 2 : 1))) void batch_kernel(
+__global__ __launch_bounds__((threads_of<N, PATH>())) __attribute__((amdgpu_waves_per_eu(N < 3 ? 2 : 1))) void batch_kernel(
     const JobDesc* jobs, int j0, int nj, long long first, long long count, Launch L, unsigned* cursor) {
     __shared__ Shared sh;
     for (;;) {
@@ -988,7 +1054,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(N < 3 
 }
 
 template <int N, int PATH>
-__global__ __launch_bounds__(kThreads) void batch_overflow_kernel(const JobDesc* jobs, Launch L, ItemList in) {
+__global__ __launch_bounds__((threads_of<N, PATH>())) void batch_overflow_kernel(const JobDesc* jobs, Launch L, ItemList in) {
     __shared__ Shared sh;
     const int total = (int)min(*in.count, (unsigned)in.cap);
     for (;;) {
@@ -1000,7 +1066,7 @@ __global__ __launch_bounds__(kThreads) void batch_overflow_kernel(const JobDesc*
 }
 
 template <int N, int PATH>
-__global__ __launch_bounds__(kThreads) void batch_scratch_kernel(const JobDesc* jobs, Launch L, ItemList in,
+__global__ __launch_bounds__((threads_of<N, PATH>())) void batch_scratch_kernel(const JobDesc* jobs, Launch L, ItemList in,
                                                                  long long* scratch) {
     __shared__ Shared sh;
     long long* S = scratch + (long long)blockIdx.x * L.lds_cap;
@@ -1303,7 +1369,7 @@ struct bsf_ctx {
     } slot[kRing];
     int slot_next = 0;
     long long lds_max_bytes = 0;   // LDS a workgroup may hold
-    long long lds_static = 1024;   // the largest static LDS of the tile kernels, plus a margin
+    long long lds_static[4] = {1024, 1024, 1024, 1024};  // per order: the largest static LDS of its kernels, plus a margin
     std::string last;
 };
 
@@ -1374,9 +1440,9 @@ struct Plan {
     bool use2 = false, use3 = false;
 };
 
-Plan plan_tiers(const bsf_ctx* c, long long need) {
-    const long long full = (c->lds_max_bytes - c->lds_static) / 8;
-    const long long half = (c->lds_max_bytes / 2 - c->lds_static) / 8;
+Plan plan_tiers(const bsf_ctx* c, long long need, int order) {
+    const long long full = (c->lds_max_bytes - c->lds_static[order]) / 8;
+    const long long half = (c->lds_max_bytes / 2 - c->lds_static[order]) / 8;
     Plan p;
     if (need <= half) {
         p.t1 = need;
@@ -1393,8 +1459,8 @@ Plan plan_tiers(const bsf_ctx* c, long long need) {
     return p;
 }
 
-int per_cu(const bsf_ctx* c, long long elems) {
-    return (int)std::max(1ll, c->lds_max_bytes / (elems * 8 + c->lds_static));
+int per_cu(const bsf_ctx* c, long long elems, int order) {
+    return (int)std::max(1ll, c->lds_max_bytes / (elems * 8 + c->lds_static[order]));
 }
 
 // Device work area of one call: counters | list A | list B | job descriptors | scratch.
@@ -1422,7 +1488,7 @@ struct Tiers {
 // whose counters are ctr[0..4]: [0] list A count, [1] list A cursor, [2] tier-1 cursor,
 // [3] list B count, [4] list B cursor.
 Tiers make_tiers_at(const bsf_ctx* c, const Plan& p, unsigned* ctr, int2* la, int2* lb, long long* scratch,
-                    long long items) {
+                    long long items, int order) {
     Tiers t;
     t.L1 = Launch{};
     t.L1.lds_cap = p.t1;
@@ -1436,7 +1502,7 @@ Tiers make_tiers_at(const bsf_ctx* c, const Plan& p, unsigned* ctr, int2* la, in
         t.L1.push_list = la;
         t.L1.push_cap = (int)items;
         t.inA = ItemList{ctr + 0, la, ctr + 1, (int)items};
-        t.grid2 = (int)std::min<long long>(items, (long long)c->cus * per_cu(c, p.t2));
+        t.grid2 = (int)std::min<long long>(items, (long long)c->cus * per_cu(c, p.t2, order));
     }
     if (p.use3) {
         t.L2.push_count = ctr + 3;
@@ -1449,10 +1515,10 @@ Tiers make_tiers_at(const bsf_ctx* c, const Plan& p, unsigned* ctr, int2* la, in
     return t;
 }
 
-Tiers make_tiers(const bsf_ctx* c, const Plan& p, char* work, const WorkLayout& w, long long items) {
-    if (!work) return make_tiers_at(c, p, nullptr, nullptr, nullptr, nullptr, items);  // tier 1 only
+Tiers make_tiers(const bsf_ctx* c, const Plan& p, char* work, const WorkLayout& w, long long items, int order) {
+    if (!work) return make_tiers_at(c, p, nullptr, nullptr, nullptr, nullptr, items, order);  // tier 1 only
     return make_tiers_at(c, p, (unsigned*)work, (int2*)(work + w.lists_off), (int2*)(work + w.listb_off),
-                         (long long*)(work + w.scratch_off), items);
+                         (long long*)(work + w.scratch_off), items, order);
 }
 
 template <int N, int PATH>
@@ -1464,12 +1530,12 @@ hipError_t launch_single(const JobDesc& A, const Plan& p, const Tiers& t, int ti
         allow_big_lds(&debug_tile_kernel<N, PATH>);
         once = true;
     }
-    hipLaunchKernelGGL((tile_kernel<N, PATH>), dim3(tiles), dim3(kThreads), (size_t)p.t1 * 8, st, A, t.L1);
+    hipLaunchKernelGGL((tile_kernel<N, PATH>), dim3(tiles), dim3(threads_of<N, PATH>()), (size_t)p.t1 * 8, st, A, t.L1);
     if (p.use2)
-        hipLaunchKernelGGL((overflow_kernel<N, PATH>), dim3(t.grid2), dim3(kThreads), (size_t)p.t2 * 8, st, A, t.L2,
+        hipLaunchKernelGGL((overflow_kernel<N, PATH>), dim3(t.grid2), dim3(threads_of<N, PATH>()), (size_t)p.t2 * 8, st, A, t.L2,
                            t.inA);
     if (p.use3)
-        hipLaunchKernelGGL((scratch_kernel<N, PATH>), dim3(t.grid3), dim3(kThreads), 0, st, A, t.L3, t.inB, t.scratch);
+        hipLaunchKernelGGL((scratch_kernel<N, PATH>), dim3(t.grid3), dim3(threads_of<N, PATH>()), 0, st, A, t.L3, t.inB, t.scratch);
     return hipGetLastError();
 }
 
@@ -1491,7 +1557,7 @@ hipError_t dispatch_debug(int n, int path, const JobDesc& A, const Launch& L, in
 #define BSF_DBG(NN, PP)                                                                          \
     do {                                                                                         \
         allow_big_lds(&debug_tile_kernel<NN, PP>);                                               \
-        hipLaunchKernelGGL((debug_tile_kernel<NN, PP>), dim3(1), dim3(kThreads), lds, st, A, L, tile); \
+        hipLaunchKernelGGL((debug_tile_kernel<NN, PP>), dim3(1), dim3(threads_of<NN, PP>()), lds, st, A, L, tile); \
         return hipGetLastError();                                                                \
     } while (0)
     if (path == BSF_PATH_F64) {
@@ -1527,7 +1593,7 @@ JobDesc make_desc(const bsf_job* j) {
 
 // Window elements a job's tiles can need, from its a_max (0: at most the whole LDS)
 long long job_window_need(const bsf_ctx* c, const bsf_job* j) {
-    const long long full = ((long long)c->lds_max_bytes - c->lds_static) / 8;
+    const long long full = ((long long)c->lds_max_bytes - c->lds_static[j->order]) / 8;
     if (j->a_max > 0.0f) return window_bound(j->order, j->a_max) + 64;
     return full;
 }
@@ -1571,45 +1637,22 @@ void static_lds(K* kernel, long long& mx) {
     (void)hipGetLastError();
 }
 
-// the largest static LDS any tile kernel declares (dynamic LDS + static must fit the chip)
-long long measure_static_lds() {
+// the largest static LDS an order's tile kernels declare (dynamic LDS + static must fit)
+template <int N>
+long long measure_static_lds_n() {
     long long mx = 0;
-    static_lds(&tile_kernel<1, 0>, mx);
-    static_lds(&tile_kernel<2, 0>, mx);
-    static_lds(&tile_kernel<3, 0>, mx);
-    static_lds(&tile_kernel<1, 1>, mx);
-    static_lds(&tile_kernel<2, 1>, mx);
-    static_lds(&tile_kernel<3, 1>, mx);
-    static_lds(&overflow_kernel<1, 0>, mx);
-    static_lds(&overflow_kernel<2, 0>, mx);
-    static_lds(&overflow_kernel<3, 0>, mx);
-    static_lds(&overflow_kernel<1, 1>, mx);
-    static_lds(&overflow_kernel<2, 1>, mx);
-    static_lds(&overflow_kernel<3, 1>, mx);
-    static_lds(&debug_tile_kernel<1, 0>, mx);
-    static_lds(&debug_tile_kernel<2, 0>, mx);
-    static_lds(&debug_tile_kernel<3, 0>, mx);
-    static_lds(&debug_tile_kernel<1, 1>, mx);
-    static_lds(&debug_tile_kernel<2, 1>, mx);
-    static_lds(&debug_tile_kernel<3, 1>, mx);
-    static_lds(&batch_kernel<1, 0>, mx);
-    static_lds(&batch_kernel<2, 0>, mx);
-    static_lds(&batch_kernel<3, 0>, mx);
-    static_lds(&batch_kernel<1, 1>, mx);
-    static_lds(&batch_kernel<2, 1>, mx);
-    static_lds(&batch_kernel<3, 1>, mx);
-    static_lds(&batch_overflow_kernel<1, 0>, mx);
-    static_lds(&batch_overflow_kernel<2, 0>, mx);
-    static_lds(&batch_overflow_kernel<3, 0>, mx);
-    static_lds(&batch_overflow_kernel<1, 1>, mx);
-    static_lds(&batch_overflow_kernel<2, 1>, mx);
-    static_lds(&batch_overflow_kernel<3, 1>, mx);
-    static_lds(&batch_scratch_kernel<1, 0>, mx);
-    static_lds(&batch_scratch_kernel<2, 0>, mx);
-    static_lds(&batch_scratch_kernel<3, 0>, mx);
-    static_lds(&batch_scratch_kernel<1, 1>, mx);
-    static_lds(&batch_scratch_kernel<2, 1>, mx);
-    static_lds(&batch_scratch_kernel<3, 1>, mx);
+    static_lds(&tile_kernel<N, 0>, mx);
+    static_lds(&tile_kernel<N, 1>, mx);
+    static_lds(&overflow_kernel<N, 0>, mx);
+    static_lds(&overflow_kernel<N, 1>, mx);
+    static_lds(&debug_tile_kernel<N, 0>, mx);
+    static_lds(&debug_tile_kernel<N, 1>, mx);
+    static_lds(&batch_kernel<N, 0>, mx);
+    static_lds(&batch_kernel<N, 1>, mx);
+    static_lds(&batch_overflow_kernel<N, 0>, mx);
+    static_lds(&batch_overflow_kernel<N, 1>, mx);
+    static_lds(&batch_scratch_kernel<N, 0>, mx);
+    static_lds(&batch_scratch_kernel<N, 1>, mx);
     return mx;
 }
 
@@ -1622,14 +1665,14 @@ hipError_t launch_batch_group(const bsf_ctx* c, const JobDesc* djobs, int j0, in
         allow_big_lds(&batch_overflow_kernel<N, PATH>);
         once = true;
     }
-    const int grid1 = (int)std::min<long long>(count, (long long)c->cus * std::min(per_cu(c, p.t1), 8));
-    hipLaunchKernelGGL((batch_kernel<N, PATH>), dim3(grid1), dim3(kThreads), (size_t)p.t1 * 8, st, djobs, j0, nj,
+    const int grid1 = (int)std::min<long long>(count, (long long)c->cus * std::min(per_cu(c, p.t1, N), 8));
+    hipLaunchKernelGGL((batch_kernel<N, PATH>), dim3(grid1), dim3(threads_of<N, PATH>()), (size_t)p.t1 * 8, st, djobs, j0, nj,
                        first, count, t.L1, ctr + 2);
     if (p.use2)
-        hipLaunchKernelGGL((batch_overflow_kernel<N, PATH>), dim3(t.grid2), dim3(kThreads), (size_t)p.t2 * 8, st,
+        hipLaunchKernelGGL((batch_overflow_kernel<N, PATH>), dim3(t.grid2), dim3(threads_of<N, PATH>()), (size_t)p.t2 * 8, st,
                            djobs, t.L2, t.inA);
     if (p.use3)
-        hipLaunchKernelGGL((batch_scratch_kernel<N, PATH>), dim3(t.grid3), dim3(kThreads), 0, st, djobs, t.L3, t.inB,
+        hipLaunchKernelGGL((batch_scratch_kernel<N, PATH>), dim3(t.grid3), dim3(threads_of<N, PATH>()), 0, st, djobs, t.L3, t.inB,
                            t.scratch);
     return hipGetLastError();
 }
@@ -1691,7 +1734,8 @@ bsf_status bsf_create(bsf_ctx** out, int hip_device, size_t workspace_limit_byte
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, hip_device) == hipSuccess && cus > 0)
         c->cus = cus;
     // static LDS of the kernels (rounded up, plus a margin); never below 1 KiB
-    c->lds_static = std::max(1024ll, ((measure_static_lds() + 255) / 256) * 256 + 256);
+    const long long st_n[4] = {0, measure_static_lds_n<1>(), measure_static_lds_n<2>(), measure_static_lds_n<3>()};
+    for (int n = 1; n <= 3; ++n) c->lds_static[n] = std::max(1024ll, ((st_n[n] + 255) / 256) * 256 + 256);
     (void)hipGetLastError();
     for (int r = 0; r < bsf_ctx::kRing; ++r) {
         e = hipEventCreateWithFlags(&c->slot[r].done, hipEventDisableTiming);
@@ -1749,7 +1793,7 @@ bsf_status bsf_filter(bsf_ctx* c, const bsf_job* j, void* stream) {
     if (!c) return BSF_ERR_INVALID_ARG;
     bsf_status s = validate(c, j, true);
     if (s != BSF_OK) return s;
-    const Plan p = plan_tiers(c, job_window_need(c, j));
+    const Plan p = plan_tiers(c, job_window_need(c, j), j->order);
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
@@ -1762,10 +1806,10 @@ bsf_status bsf_filter(bsf_ctx* c, const bsf_job* j, void* stream) {
         const WorkLayout w = work_layout(tiles, 0, p.use3 ? (size_t)grid3 * (size_t)p.t3 * 8 : 0);
         s = acquire_slot(c, w.total, 0, slot);
         if (s != BSF_OK) return s;
-        t = make_tiers(c, p, (char*)c->slot[slot].dev, w, tiles);
+        t = make_tiers(c, p, (char*)c->slot[slot].dev, w, tiles, j->order);
         hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, st, (unsigned*)c->slot[slot].dev);
     } else {
-        t = make_tiers(c, p, nullptr, WorkLayout{}, tiles);
+        t = make_tiers(c, p, nullptr, WorkLayout{}, tiles, j->order);
     }
     e = dispatch_single(j->order, j->path, A, p, t, tiles, st);
     if (e == hipSuccess && slot >= 0) e = hipEventRecord(c->slot[slot].done, st);
@@ -1826,7 +1870,7 @@ bsf_status bsf_filter_batched(bsf_ctx* c, const bsf_job* jobs, int njobs, void* 
                 ++g.nj;
             }
             g.count = items - g.first;
-            g.p = plan_tiers(c, need[g.v]);
+            g.p = plan_tiers(c, need[g.v], g.v / 2 + 1);
             if (g.p.use3) {
                 const long long grid3 = std::min<long long>(g.count, (long long)c->cus * 2);
                 scratch_bytes = std::max(scratch_bytes, (size_t)grid3 * (size_t)g.p.t3 * 8);
@@ -1856,7 +1900,7 @@ bsf_status bsf_filter_batched(bsf_ctx* c, const bsf_job* jobs, int njobs, void* 
         unsigned* ctr = (unsigned*)work + 8 * g.v;  // each variant appears in one group
         const Tiers t = make_tiers_at(c, g.p, ctr, (int2*)(work + w.lists_off) + g.first,
                                       (int2*)(work + w.listb_off) + g.first, (long long*)(work + w.scratch_off),
-                                      g.count);
+                                      g.count, g.v / 2 + 1);
         e = dispatch_batch_group(c, g.v, djobs, g.j0, g.nj, g.first, g.count, g.p, t, ctr, st);
         if (e != hipSuccess) return hip_fail(c, e, "batch kernel launch");
     }
@@ -1939,7 +1983,7 @@ bsf_status bsf_debug_tile_window(bsf_ctx* c, const bsf_job* j, int tile, int64_t
     const JobDesc A = make_desc(j);
     if (tile < 0 || tile >= A.tiles_x * A.tiles_y || !window || !geom)
         return fail(c, BSF_ERR_INVALID_ARG, "bad debug tile arguments");
-    const long long full = (c->lds_max_bytes - c->lds_static) / 8;
+    const long long full = (c->lds_max_bytes - c->lds_static[j->order]) / 8;
     Launch L{};
     L.lds_cap = std::min(job_window_need(c, j), full);
     L.err = c->d_err;

@@ -9,7 +9,18 @@
 namespace bsf {
 
 constexpr int kTile = 16;       // output tile edge (pixels)
-constexpr int kThreads = 256;   // one output pixel per thread
+constexpr int kThreads = 256;   // one output pixel per thread (per thread pair at order 3)
+
+// Order 3 on the float32-output path shares each pixel's taps between two threads (k2
+// in {0,1} and {2,3}) in workgroups of 512, so that the large order-3 windows, one
+// workgroup per CU, still keep two waves per SIMD busy.  Every such tile is computed
+// this way, whatever launch it lands in.  (The float64 path at order 3 needs about 500
+// registers per thread and keeps one thread per pixel.)
+template <int N, int PATH>
+__host__ __device__ constexpr int split_of() { return (N == 3 && PATH == 1) ? 2 : 1; }
+template <int N, int PATH>
+__host__ __device__ constexpr int threads_of() { return kThreads * split_of<N, PATH>(); }
+constexpr int kMaxWaves = 2 * kThreads / 64;
 constexpr double kScaleMin = 0.5;
 constexpr double kScaleMax = 1e4;
 
