@@ -405,7 +405,8 @@ __device__ __forceinline__ void horner_chunk_dd(
         for (int b = DEG - a - 1; b >= 0; --b) {
 #pragma unroll
             for (int p = 0; p < PARTS; ++p) c[p] = G[p][mono_index<DEG>(a, b) - M0];
-            q = cp_horner(q, v2, join_parts<PARTS, SHIFT>(c));
+            if constexpr (PARTS == 1) q = cp_horner(q, v2, c[0]);  // exact single-part coefficient
+            else q = cp_horner(q, v2, join_parts<PARTS, SHIFT>(c));
         }
         P = (FIRST && a == AHI) ? q : cp_horner(P, v1, q);
     }

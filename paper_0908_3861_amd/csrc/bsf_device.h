@@ -100,10 +100,18 @@ __device__ __forceinline__ cp cp_horner(cp acc, dd x, cp coef) {
     const double p = acc.s * x.hi;
     const double pi = __fma_rn(acc.s, x.hi, -p);
     const dd t = two_sum(p, coef.s);
-    const double corr = ((pi + t.lo) + coef.c) + acc.s * x.lo;
+    const double corr = __fma_rn(acc.s, x.lo, (pi + t.lo) + coef.c);
     return {t.hi, __fma_rn(acc.c, x.hi, corr)};
 }
 // acc + w * v for a small integer weight w (exact as a double)
+// the same step for an exact double coefficient (no low part to carry)
+__device__ __forceinline__ cp cp_horner(cp acc, dd x, double coef) {
+    const double p = acc.s * x.hi;
+    const double pi = __fma_rn(acc.s, x.hi, -p);
+    const dd t = two_sum(p, coef);
+    const double corr = __fma_rn(acc.s, x.lo, pi + t.lo);
+    return {t.hi, __fma_rn(acc.c, x.hi, corr)};
+}
 __device__ __forceinline__ cp cp_axpy(cp acc, double w, cp v) {
     const dd h = two_prod(v.s, w);
     const dd t = two_sum(acc.s, h.hi);
