@@ -304,36 +304,37 @@ __device__ __forceinline__ void accumulate_chunk(const long long* S, const TapFr
     }
 }
 
-// Order 3: the same accumulation with a runtime loop over the stencil; fully unrolled,
-// order 3 would be tens of thousands of instructions per variant, and its table values
-// (up to 6e7) do not fit the literal forms of the FMA, so each would first be built in
-// registers.  The table rows come from constant memory, laid out chunk by chunk: the
-// slice one u1-chunk reads (at most 63 x 21 doubles, 10.6 KB) is contiguous and stays
-// in the scalar cache across the taps, where the row-major 33 KB table thrashes it.
-template <int ALO, int AHI>
-struct Num3Chunk {
-    static constexpr int M0 = mono_index<10>(ALO, 0);
-    static constexpr int CM = mono_index<10>(AHI, 10 - AHI) - M0 + 1;
-    double w[bsf_tables::kStencil3][CM];
-    constexpr Num3Chunk() : w() {
-        for (int j = 0; j < bsf_tables::kStencil3; ++j)
-            for (int c = 0; c < CM; ++c) w[j][c] = bsf_tables::kNum3[j][M0 + c];
+// Order 3: the same accumulation as a runtime loop over the 36 representative stencil
+// points (fully unrolled, order 3 would be tens of thousands of instructions per variant,
+// and its table values up to 6e7 do not fit the literal forms of the FMA, so each would
+// first be built in registers).  The table, in constant memory, is laid out by
+// representative: its offsets, its mirror's, and its 66 weights (zeros included).  From a
+// float64 window (one part) all 66 coefficient sums are formed in one pass, so every loop
+// iteration carries 66 FMAs and the stencil is read once per tap; with three exact parts
+// the sums are formed in two passes over u1-chunks (84 and 114 accumulators).
+struct Rep3 {
+    int jx, jy, mjx, mjy, self;
+    double w[bsf_tables::kMono3];
+};
+struct Rep3Table {
+    static constexpr int R = (bsf_tables::kStencil3 + 9) / 2;  // 9 self-mirrored points (jy = 0)
+    Rep3 r[R];
+    int count;
+    constexpr Rep3Table() : r(), count(0) {
+        for (int j = 0; j < bsf_tables::kStencil3; ++j) {
+            if (!is_rep<3>(j)) continue;
+            const int jm = mirror_of<3>(j);
+            Rep3& q = r[count++];
+            q.jx = bsf_tables::kJ3[j][0];
+            q.jy = bsf_tables::kJ3[j][1];
+            q.mjx = bsf_tables::kJ3[jm][0];
+            q.mjy = bsf_tables::kJ3[jm][1];
+            q.self = jm == j;
+            for (int m = 0; m < bsf_tables::kMono3; ++m) q.w[m] = bsf_tables::kNum3[j][m];
+        }
     }
 };
-__constant__ Num3Chunk<7, 10> c_num3_a = Num3Chunk<7, 10>();
-__constant__ Num3Chunk<5, 6> c_num3_b = Num3Chunk<5, 6>();
-__constant__ Num3Chunk<3, 4> c_num3_c = Num3Chunk<3, 4>();
-__constant__ Num3Chunk<2, 2> c_num3_d = Num3Chunk<2, 2>();
-__constant__ Num3Chunk<0, 1> c_num3_e = Num3Chunk<0, 1>();
-template <int ALO, int AHI>
-__device__ __forceinline__ const Num3Chunk<ALO, AHI>& num3_chunk() {
-    if constexpr (ALO == 7) return c_num3_a;
-    else if constexpr (ALO == 5) return c_num3_b;
-    else if constexpr (ALO == 3) return c_num3_c;
-    else if constexpr (ALO == 2) return c_num3_d;
-    else return c_num3_e;
-}
-__constant__ int c_j3[bsf_tables::kStencil3][2] = BSF_J3_INIT;
+__constant__ Rep3Table c_rep3 = Rep3Table();
 
 template <int SRC, int PARTS, int SHIFT, int ALO, int AHI>
 __device__ __forceinline__ void accumulate_chunk3(const long long* S, const TapFrame<3>& fr,
@@ -344,47 +345,48 @@ __device__ __forceinline__ void accumulate_chunk3(const long long* S, const TapF
     constexpr int M0 = mono_index<10>(ALO, 0);
     constexpr int CM = mono_index<10>(AHI, 10 - AHI) - M0 + 1;
     const double* Sd = reinterpret_cast<const double*>(S);
-    const auto& tab = num3_chunk<ALO, AHI>();
     asm volatile("" ::: "memory");  // keep each chunk's LDS reads local to the chunk
 #pragma unroll
     for (int p = 0; p < PARTS; ++p)
 #pragma unroll
         for (int c = 0; c < CM; ++c) G[p][c] = 0.0;
 #pragma unroll 1
-    for (int j = 0; j < T::S; ++j) {
-        const int jy = c_j3[j][1];
-        if (jy < 0) continue;  // odd order: representatives have jy >= 0
-        const int jx = c_j3[j][0];
-        const int o1 = fr.base + jx * fr.s1 + jy * fr.s2, o2 = fr.base + jx * fr.s1 - jy * fr.s2;
-        if (jy == 0) {
-            double x[PARTS];
-            if constexpr (SRC == SRC_DBL) x[0] = Sd[o1];
-            else split_int<PARTS, SHIFT>(S[o1], x);
-#pragma unroll
-            for (int c = 0; c < CM; ++c) {
-                const double w = tab.w[j][c];
-#pragma unroll
-                for (int p = 0; p < PARTS; ++p) G[p][c] = __fma_rn(w, x[p], G[p][c]);
-            }
+    for (int k = 0; k < Rep3Table::R; ++k) {
+        const Rep3& q = c_rep3.r[k];
+        const int o1 = fr.base + q.jx * fr.s1 + q.jy * fr.s2, o2 = fr.base + q.mjx * fr.s1 + q.mjy * fr.s2;
+        double xs[PARTS], xd[PARTS];
+        if constexpr (SRC == SRC_DBL) {
+            const double g1 = Sd[o1], g2 = q.self ? 0.0 : Sd[o2];
+            xs[0] = g1 + g2;
+            xd[0] = g1 - g2;
         } else {
-            double xs[PARTS], xd[PARTS];
-            if constexpr (SRC == SRC_DBL) {
-                const double g1 = Sd[o1], g2 = Sd[o2];
-                xs[0] = g1 + g2;
-                xd[0] = g1 - g2;
-            } else {
-                const long long g1 = S[o1], g2 = S[o2];
-                split_int<PARTS, SHIFT>(add_ovf(g1, g2, bad), xs);
-                split_int<PARTS, SHIFT>(sub_ovf(g1, g2, bad), xd);
-            }
-#pragma unroll
-            for (int c = 0; c < CM; ++c) {
-                const double w = tab.w[j][c];
-#pragma unroll
-                for (int p = 0; p < PARTS; ++p)
-                    G[p][c] = __fma_rn(w, (T::mb(M0 + c) & 1) ? xd[p] : xs[p], G[p][c]);
-            }
+            const long long g1 = S[o1], g2 = q.self ? 0ll : S[o2];
+            split_int<PARTS, SHIFT>(add_ovf(g1, g2, bad), xs);
+            split_int<PARTS, SHIFT>(sub_ovf(g1, g2, bad), xd);
         }
+#pragma unroll
+        for (int c = 0; c < CM; ++c) {
+            const double w = q.w[M0 + c];
+#pragma unroll
+            for (int p = 0; p < PARTS; ++p) G[p][c] = __fma_rn(w, (T::mb(M0 + c) & 1) ? xd[p] : xs[p], G[p][c]);
+        }
+    }
+}
+
+__device__ __forceinline__ void accumulate_all3_dbl(const long long* S, const TapFrame<3>& fr,
+                                                    double (&G)[1][bsf_tables::kMono3]) {
+    using T = Tab<3>;
+    const double* Sd = reinterpret_cast<const double*>(S);
+#pragma unroll
+    for (int c = 0; c < T::M; ++c) G[0][c] = 0.0;
+#pragma unroll 1
+    for (int k = 0; k < Rep3Table::R; ++k) {
+        const Rep3& q = c_rep3.r[k];
+        const double g1 = Sd[fr.base + q.jx * fr.s1 + q.jy * fr.s2];
+        const double g2 = q.self ? 0.0 : Sd[fr.base + q.mjx * fr.s1 + q.mjy * fr.s2];
+        const double xs = g1 + g2, xd = g1 - g2;  // exact: window values below 2^exact_bits
+#pragma unroll
+        for (int c = 0; c < T::M; ++c) G[0][c] = __fma_rn(q.w[c], (T::mb(c) & 1) ? xd : xs, G[0][c]);
     }
 }
 
@@ -418,7 +420,9 @@ __device__ __forceinline__ void interp_chunk_dd(const long long* S, const TapFra
     using T = Tab<N>;
     constexpr int PARTS = SRC == SRC_DBL ? 1 : T::SPLIT;
     double G[PARTS][mono_index<T::DEG>(AHI, T::DEG - AHI) - mono_index<T::DEG>(ALO, 0) + 1];
-    if constexpr (N == 3)
+    if constexpr (N == 3 && SRC == SRC_DBL && ALO == 0 && AHI == 10)
+        accumulate_all3_dbl(S, fr, G);
+    else if constexpr (N == 3)
         accumulate_chunk3<SRC, PARTS, T::SHIFT, ALO, AHI>(S, fr, G, bad);
     else
         accumulate_chunk<N, SRC, PARTS, T::SHIFT, ALO, AHI>(S, fr, G, bad);
@@ -446,7 +450,9 @@ __device__ __forceinline__ void interp_chunk_f64(const long long* S, const TapFr
                                                  double& P, unsigned& bad) {
     using T = Tab<N>;
     double G[1][mono_index<T::DEG>(AHI, T::DEG - AHI) - mono_index<T::DEG>(ALO, 0) + 1];
-    if constexpr (N == 3)
+    if constexpr (N == 3 && SRC == SRC_DBL && ALO == 0 && AHI == 10)
+        accumulate_all3_dbl(S, fr, G);
+    else if constexpr (N == 3)
         accumulate_chunk3<SRC, 1, 0, ALO, AHI>(S, fr, G, bad);
     else
         accumulate_chunk<N, SRC, 1, 0, ALO, AHI>(S, fr, G, bad);
@@ -460,14 +466,11 @@ template <int N, int SRC>
 __device__ __forceinline__ cp interp_dd(const long long* S, const TapFrame<N>& fr, dd v1, dd v2, unsigned& bad) {
     using T = Tab<N>;
     cp P = {0.0, 0.0};
-    if constexpr (N < 3) {
+    if constexpr (N < 3 || SRC == SRC_DBL) {
         interp_chunk_dd<N, SRC, 0, T::DEG, true>(S, fr, v1, v2, P, bad);
-    } else {
-        interp_chunk_dd<N, SRC, 7, 10, true>(S, fr, v1, v2, P, bad);
-        interp_chunk_dd<N, SRC, 5, 6, false>(S, fr, v1, v2, P, bad);
-        interp_chunk_dd<N, SRC, 3, 4, false>(S, fr, v1, v2, P, bad);
-        interp_chunk_dd<N, SRC, 2, 2, false>(S, fr, v1, v2, P, bad);
-        interp_chunk_dd<N, SRC, 0, 1, false>(S, fr, v1, v2, P, bad);
+    } else {  // three parts: two u1-chunks (84 and 114 accumulators)
+        interp_chunk_dd<N, SRC, 4, 10, true>(S, fr, v1, v2, P, bad);
+        interp_chunk_dd<N, SRC, 0, 3, false>(S, fr, v1, v2, P, bad);
     }
     return P;
 }
@@ -478,14 +481,11 @@ __device__ __forceinline__ double interp_f64(const long long* S, const TapFrame<
                                              unsigned& bad) {
     using T = Tab<N>;
     double P = 0.0;
-    if constexpr (N < 3) {
+    if constexpr (N < 3 || SRC == SRC_DBL) {
         interp_chunk_f64<N, SRC, 0, T::DEG, true>(S, fr, v1, v2, P, bad);
     } else {
-        interp_chunk_f64<N, SRC, 7, 10, true>(S, fr, v1, v2, P, bad);
-        interp_chunk_f64<N, SRC, 5, 6, false>(S, fr, v1, v2, P, bad);
-        interp_chunk_f64<N, SRC, 3, 4, false>(S, fr, v1, v2, P, bad);
-        interp_chunk_f64<N, SRC, 2, 2, false>(S, fr, v1, v2, P, bad);
-        interp_chunk_f64<N, SRC, 0, 1, false>(S, fr, v1, v2, P, bad);
+        interp_chunk_f64<N, SRC, 4, 10, true>(S, fr, v1, v2, P, bad);
+        interp_chunk_f64<N, SRC, 0, 3, false>(S, fr, v1, v2, P, bad);
     }
     return P;
 }
