@@ -37,6 +37,9 @@ PEAK_HBM = 8.0e12          # B/s
 # (scaled by a 1 GiB device copy), keyed by the kernel source they were taken on: once
 # the source changes, the figure no longer applies and the bench reports null.
 MEASURED_TRAFFIC = {"bb6dbc8e7ed0a194": {("plain", "f64"): 107.4e6}}
+# Fraction of the chip's VALU issue slots the dominant kernel used (rocprofv3 SQ_INSTS_VALU x 4
+# cycles over 1024 SIMDs x 2.4 GHz x kernel time), keyed the same way.
+MEASURED_VALU_ISSUE = {"bb6dbc8e7ed0a194": {("plain", "f64"): 0.76}}
 
 
 def kernel_source_key() -> str:
@@ -201,7 +204,9 @@ def workload_plain(args):
     # halo of the largest scale: R = (n/2)(a + 2a/sqrt2) + 3n, about 42 at n = 2, a = 16
     extra["stage1_global_alone"] = stage1_alone(job, 42, max(3, args.steps // 2), 2)
     if W == 2048 and H == 2048:
-        roof["traffic"] = MEASURED_TRAFFIC.get(kernel_source_key(), {}).get(("plain", args.path))
+        key = kernel_source_key()
+        roof["traffic"] = MEASURED_TRAFFIC.get(key, {}).get(("plain", args.path))
+        extra["executed_valu_issue_frac"] = MEASURED_VALU_ISSUE.get(key, {}).get(("plain", args.path))
     config = {"workload": f"plain: {W}x{H} uint8 blurred-noise image, smooth real scales in [1,16], "
                           f"order {job.order}, {args.path} path", "pixels": P, "order": job.order, "path": args.path}
     dtype = "f64" if args.path == "f64" else "f64-mesh/f32-out"
