@@ -177,11 +177,19 @@ def make_job(img, scales, order: int, path: str = "f64", border: str = "clamp", 
     return j, out
 
 
+def _on(stream):
+    """Allocate on the stream the library writes on (the caching allocator ties memory to it)."""
+    import contextlib
+    import torch
+    return torch.cuda.stream(stream) if stream is not None else contextlib.nullcontext()
+
+
 def filter(img, scales, order: int, path: str = "f64", border: str = "clamp", a_max: float | None = None,
            out=None, ctx: Context | None = None, stream=None, check: bool = False):
     """Adaptive box-spline filter of ``img`` with per-pixel scale vectors ``scales``."""
     ctx = ctx or default_context(img.device.index)
-    j, out = make_job(img, scales, order, path, border, a_max, out)
+    with _on(stream):
+        j, out = make_job(img, scales, order, path, border, a_max, out)
     ctx._check(ctx.lib.bsf_filter(ctx.handle, ctypes.byref(j), _stream_ptr(stream)))
     if check:
         ctx.check_device(stream)
@@ -195,11 +203,12 @@ def filter_batched(items, ctx: Context | None = None, stream=None, check: bool =
     ctx = ctx or default_context(items[0]["img"].device.index)
     jobs = (Job * len(items))()
     outs = []
-    for i, it in enumerate(items):
-        j, o = make_job(it["img"], it["scales"], it["order"], it.get("path", "f64"), it.get("border", "clamp"),
-                        it.get("a_max"), it.get("out"))
-        jobs[i] = j
-        outs.append(o)
+    with _on(stream):
+        for i, it in enumerate(items):
+            j, o = make_job(it["img"], it["scales"], it["order"], it.get("path", "f64"), it.get("border", "clamp"),
+                            it.get("a_max"), it.get("out"))
+            jobs[i] = j
+            outs.append(o)
     ctx._check(ctx.lib.bsf_filter_batched(ctx.handle, jobs, len(items), _stream_ptr(stream)))
     if check:
         ctx.check_device(stream)
@@ -219,7 +228,8 @@ def preintegrate(img, order: int, x0: int, y0: int, wq: int, hq: int, border: st
     j.in_pitch = img.stride(0)
     j.order = int(order)
     j.border = BORDERS[border]
-    g = torch.empty((hq, wq), dtype=torch.int64, device=img.device)
+    with _on(stream):
+        g = torch.empty((hq, wq), dtype=torch.int64, device=img.device)
     ctx._check(ctx.lib.bsf_preintegrate(ctx.handle, ctypes.byref(j), x0, y0, wq, hq, g.data_ptr(), g.stride(0),
                                         _stream_ptr(stream)))
     return g

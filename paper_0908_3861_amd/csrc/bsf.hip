@@ -1355,8 +1355,6 @@ struct bsf_ctx {
     int cus = 256;
     size_t ws_limit = 0;
     unsigned* d_err = nullptr;
-    void* ws = nullptr;  // stage-1 workspace of bsf_preintegrate
-    size_t ws_bytes = 0;
     // Per-call device work areas (counters, overflow list, batch descriptors) and pinned
     // host staging, in a ring: calls on different streams may be in flight together; a
     // slot is reused only after the call that last used it has finished on the device.
@@ -1764,7 +1762,6 @@ bsf_status bsf_destroy(bsf_ctx* c) {
     if (!c) return BSF_ERR_INVALID_ARG;
     hipSetDevice(c->device);
     if (c->d_err) (void)hipFree(c->d_err);
-    if (c->ws) (void)hipFree(c->ws);
     for (int r = 0; r < bsf_ctx::kRing; ++r) {
         if (c->slot[r].dev) (void)hipFree(c->slot[r].dev);
         if (c->slot[r].host) (void)hipHostFree(c->slot[r].host);
@@ -1918,20 +1915,13 @@ bsf_status bsf_preintegrate(bsf_ctx* c, const bsf_job* j, int x0, int y0, int wq
     if (wq < 1 || hq < 1 || !g || g_pitch < wq) return fail(c, BSF_ERR_INVALID_ARG, "bad window");
     const size_t tp = ((size_t)(wq + hq - 1) + 3) & ~(size_t)3;
     const size_t need = (size_t)hq * tp * 8 + bsf::kZeros * 8;  // + the zero words
-    if (need > c->ws_limit) return fail(c, BSF_ERR_OUT_OF_MEMORY, "window workspace exceeds the limit");
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
-    if (need > c->ws_bytes) {
-        if (c->ws) {
-            hipStreamSynchronize((hipStream_t)stream);
-            hipFree(c->ws);
-            c->ws = nullptr;
-            c->ws_bytes = 0;
-        }
-        e = hipMalloc(&c->ws, need);
-        if (e != hipSuccess) return hip_fail(c, e, "workspace allocation");
-        c->ws_bytes = need;
-    }
+    // the workspace is a slot of the context's ring: calls on different streams never share
+    // one, and a slot is reused (or grown) only after its previous call has finished
+    int slot = -1;
+    s = acquire_slot(c, need, 0, slot);
+    if (s != BSF_OK) return s;
     GlobalArgs A{};
     A.in = j->in;
     A.in_pitch = j->in_pitch;
@@ -1943,7 +1933,7 @@ bsf_status bsf_preintegrate(bsf_ctx* c, const bsf_job* j, int x0, int y0, int wq
     A.y0 = y0;
     A.wq = wq;
     A.hq = hq;
-    A.T = (long long*)c->ws;
+    A.T = (long long*)c->slot[slot].dev;
     A.tp = (long long)tp;
     A.g = (long long*)g;
     A.g_pitch = g_pitch;
@@ -1952,6 +1942,7 @@ bsf_status bsf_preintegrate(bsf_ctx* c, const bsf_job* j, int x0, int y0, int wq
     else if (j->order == 2) bsf::launch_global<2>(A, st);
     else bsf::launch_global<3>(A, st);
     e = hipGetLastError();
+    if (e == hipSuccess) e = hipEventRecord(c->slot[slot].done, st);
     if (e != hipSuccess) return hip_fail(c, e, "pre-integration launch");
     return BSF_OK;
 }

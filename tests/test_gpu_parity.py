@@ -104,6 +104,27 @@ def test_global_preintegrate_large_windows(bsf, torch_dev, oracle_mod, n, x0, y0
     assert np.array_equal(g, ref), (n, x0, y0, wq, hq)
 
 
+def test_global_preintegrate_on_two_streams(bsf, torch_dev, oracle_mod):
+    """Calls in flight on different streams each get their own workspace."""
+    torch = torch_dev
+    rng = np.random.default_rng(106)
+    H, W = 300, 280
+    img = rng.integers(0, 256, size=(H, W)).astype(np.uint8)
+    ti = torch.from_numpy(img).cuda()
+    ctx = bsf.default_context()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    wins = [(2, -20, -10, 320, 310, s1), (3, 5, 7, 150, 260, s2), (1, 0, 0, 280, 300, s1), (2, -3, -3, 90, 40, s2)]
+    outs = []
+    for n, x0, y0, wq, hq, st in wins:
+        outs.append(bsf.preintegrate(ti, n, x0, y0, wq, hq, ctx=ctx, stream=st))
+    torch.cuda.synchronize()
+    for (n, x0, y0, wq, hq, _), g in zip(wins, outs):
+        ys = np.clip(np.arange(y0, y0 + hq), 0, H - 1)
+        xs = np.clip(np.arange(x0, x0 + wq), 0, W - 1)
+        ref = oracle_mod.preintegrate(img[np.ix_(ys, xs)].astype(np.int64), n, wrap=True)
+        assert np.array_equal(g.cpu().numpy(), ref), (n, wq, hq)
+
+
 def test_global_preintegrate_plain_workload_full_size(bsf, torch_dev, oracle_mod):
     """The paper's global stage 1 over the whole padded box of the 2048x2048 order-2 workload."""
     torch = torch_dev
