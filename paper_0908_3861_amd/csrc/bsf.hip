@@ -193,21 +193,29 @@ struct TapFrame {
     int lo_ok;         // stencil box inside the window
 };
 
+// The cell's triangle follows from the signs of u1 + u2 and u1 - u2; the quarter turn
+// R^-tri that maps it onto the reference triangle u1 >= |u2| swaps the two axes when the
+// signs differ, then negates the first coordinate when u1 + u2 < 0 and the second when
+// u1 - u2 < 0:  tri 0 (u1, u2), 1 (u2, -u1), 2 (-u1, -u2), 3 (-u2, u1).
+struct Turn {
+    bool swap, n1, n2;
+};
+__device__ __forceinline__ Turn cell_turn(double u1, double u2) {
+    const bool sp = (u1 + u2) >= 0.0, sm = (u1 - u2) >= 0.0;
+    return {sp != sm, !sp, !sm};
+}
+
 template <int N>
-__device__ __forceinline__ TapFrame<N> tap_frame(int qx, int qy, int tri, int wq, int hq) {
-    // odd n rotates about the anchor, even n about the anchor + (1/2, 1/2)
+__device__ __forceinline__ TapFrame<N> tap_frame(int qx, int qy, Turn t, int wq, int hq) {
+    // odd n rotates about the anchor, even n about the anchor + (1/2, 1/2); stencil
+    // point (jx, jy) of the reference triangle sits at (jx, jy), (e - jy, jx),
+    // (e - jx, e - jy) or (jy, e - jx) for tri = 0..3
     constexpr int e = (N & 1) ? 0 : 1;
-    int cx = 0, cy = 0, s1, s2;
-    switch (tri) {
-        case 0: s1 = 1; s2 = wq; break;                      // (jx, jy)
-        case 1: s1 = wq; s2 = -1; cx = e; break;             // (e - jy, jx)
-        case 2: s1 = -1; s2 = -wq; cx = e; cy = e; break;    // (e - jx, e - jy)
-        default: s1 = -wq; s2 = 1; cy = e; break;            // (jy, e - jx)
-    }
+    const int S1 = t.swap ? wq : 1, S2 = t.swap ? 1 : wq;
     TapFrame<N> f;
-    f.base = (qy + cy) * wq + (qx + cx);
-    f.s1 = s1;
-    f.s2 = s2;
+    f.s1 = t.n1 ? -S1 : S1;
+    f.s2 = t.n2 ? -S2 : S2;
+    f.base = (qy + (t.n1 ? e : 0)) * wq + (qx + (t.n2 ? e : 0));
     constexpr int jl = stencil_lo<N>(), jh = stencil_hi<N>();
     f.lo_ok = (qx + jl >= 0) && (qx + jh < wq) && (qy + jl >= 0) && (qy + jh < hq);
     return f;
@@ -490,17 +498,20 @@ __device__ __forceinline__ double interp_f64(const long long* S, const TapFrame<
     return P;
 }
 
-__host__ __device__ constexpr int binom(int n, int k) {
-    int r = 1;
-    for (int i = 0; i < k; ++i) r = r * (n - i) / (i + 1);
-    return r;
+// binom(N, k) for the finite-difference weights of eq. FD (N <= 3, k in 0..N)
+template <int N>
+__device__ __forceinline__ int fd_binom(int k) {
+    static_assert(N >= 1 && N <= 3, "orders 1..3");
+    if constexpr (N == 1) return 1;
+    else if constexpr (N == 2) return k == 1 ? 2 : 1;
+    else return (k == 1 || k == 2) ? 3 : 1;
 }
 
-// Triangle of the cell from the signs of u1 + u2 and u1 - u2, and the quarter turn
-// R^-tri that maps it onto the reference triangle u1 >= |u2|.
-__device__ __forceinline__ int cell_triangle(double u1, double u2) {
-    const bool sp = (u1 + u2) >= 0.0, sm = (u1 - u2) >= 0.0;
-    return sp ? (sm ? 0 : 1) : (sm ? 3 : 2);
+__device__ __forceinline__ dd dd_turn(bool swap, bool neg, dd a, dd b) {  // +-(swap ? b : a)
+    dd r = swap ? b : a;
+    r.hi = neg ? -r.hi : r.hi;
+    r.lo = neg ? -r.lo : r.lo;
+    return r;
 }
 
 // One pixel of the order-N mesh (eq. final_eqn): s[m] = sum_k c_k g_I(m + n tau - x_k),
@@ -522,10 +533,12 @@ __device__ dd mesh_dd(const long long* S, int wq, int hq, int mx, int my, float4
     cp acc = {0.0, 0.0};
     for (int k2 = k2lo; k2 <= k2hi; ++k2) {
         for (int k4 = 0; k4 <= N; ++k4) {
+            const int c24 = fd_binom<N>(k2) * fd_binom<N>(k4);
             const dd D2 = dd_mul_d(A2, (double)k2), D4 = dd_mul_d(A4, (double)k4);
             const dd B1 = dd_add(T1, dd_add(D4, dd_neg(D2)));        // n tau_1 - k2 a'2 + k4 a'4
             const dd B2 = dd_add(T2, dd_neg(dd_add(D2, D4)));         // n tau_2 - k2 a'2 - k4 a'4
             for (int k1 = 0; k1 <= N; ++k1) {
+                const int c124 = c24 * fd_binom<N>(k1);
                 const dd d1 = dd_add_d(B1, -(double)k1 * a1);
                 for (int k3 = 0; k3 <= N; ++k3) {
                     const dd d2 = dd_add_d(B2, -(double)k3 * a3);
@@ -543,21 +556,16 @@ __device__ dd mesh_dd(const long long* S, int wq, int hq, int mx, int my, float4
                     const double oc = (N & 1) ? 0.0 : 0.5;
                     const dd u1 = dd_add_d(d1, -(f1 + oc));
                     const dd u2 = dd_add_d(d2, -(f2 + oc));
-                    const int tri = cell_triangle(u1.hi, u2.hi);
-                    dd v1, v2;
-                    switch (tri) {
-                        case 0: v1 = u1; v2 = u2; break;
-                        case 1: v1 = u2; v2 = dd_neg(u1); break;
-                        case 2: v1 = dd_neg(u1); v2 = dd_neg(u2); break;
-                        default: v1 = dd_neg(u2); v2 = u1; break;
-                    }
-                    const TapFrame<N> fr = tap_frame<N>(mx + (int)f1, my + (int)f2, tri, wq, hq);
+                    const Turn t = cell_turn(u1.hi, u2.hi);
+                    const dd v1 = dd_turn(t.swap, t.n1, u1, u2);
+                    const dd v2 = dd_turn(t.swap, t.n2, u2, u1);
+                    const TapFrame<N> fr = tap_frame<N>(mx + (int)f1, my + (int)f2, t, wq, hq);
                     if (!fr.lo_ok) {
                         bad = 1;
                         continue;
                     }
                     const cp P = interp_dd<N, SRC>(S, fr, v1, v2, bad);
-                    const int c = binom(N, k1) * binom(N, k2) * binom(N, k3) * binom(N, k4);
+                    const int c = c124 * fd_binom<N>(k3);
                     const double cs = ((k1 + k2 + k3 + k4) & 1) ? -(double)c : (double)c;
                     acc = cp_axpy(acc, cs, P);
                 }
@@ -590,9 +598,11 @@ __device__ double mesh_f64(const long long* S, int wq, int hq, int mx, int my, f
     double acc = 0.0;
     for (int k2 = k2lo; k2 <= k2hi; ++k2) {
         for (int k4 = 0; k4 <= N; ++k4) {
+            const int c24 = fd_binom<N>(k2) * fd_binom<N>(k4);
             const double B1 = T1 - k2 * A2 + k4 * A4;
             const double B2 = T2 - k2 * A2 - k4 * A4;
             for (int k1 = 0; k1 <= N; ++k1) {
+                const int c124 = c24 * fd_binom<N>(k1);
                 const double d1 = B1 - k1 * a1;
                 for (int k3 = 0; k3 <= N; ++k3) {
                     const double d2 = B2 - k3 * a3;
@@ -600,21 +610,16 @@ __device__ double mesh_f64(const long long* S, int wq, int hq, int mx, int my, f
                     const double f2 = (N & 1) ? rint(d2) : floor(d2);
                     const double oc = (N & 1) ? 0.0 : 0.5;
                     const double u1 = d1 - f1 - oc, u2 = d2 - f2 - oc;
-                    const int tri = cell_triangle(u1, u2);
-                    double v1, v2;
-                    switch (tri) {
-                        case 0: v1 = u1; v2 = u2; break;
-                        case 1: v1 = u2; v2 = -u1; break;
-                        case 2: v1 = -u1; v2 = -u2; break;
-                        default: v1 = -u2; v2 = u1; break;
-                    }
-                    const TapFrame<N> fr = tap_frame<N>(mx + (int)f1, my + (int)f2, tri, wq, hq);
+                    const Turn t = cell_turn(u1, u2);
+                    const double w1 = t.swap ? u2 : u1, w2 = t.swap ? u1 : u2;
+                    const double v1 = t.n1 ? -w1 : w1, v2 = t.n2 ? -w2 : w2;
+                    const TapFrame<N> fr = tap_frame<N>(mx + (int)f1, my + (int)f2, t, wq, hq);
                     if (!fr.lo_ok) {
                         bad = 1;
                         continue;
                     }
                     const double P = interp_f64<N, SRC>(S, fr, v1, v2, bad);
-                    const int c = binom(N, k1) * binom(N, k2) * binom(N, k3) * binom(N, k4);
+                    const int c = c124 * fd_binom<N>(k3);
                     acc = __fma_rn(((k1 + k2 + k3 + k4) & 1) ? -(double)c : (double)c, P, acc);
                 }
             }
