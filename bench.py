@@ -128,8 +128,10 @@ def run_single(args, name, job, a_max, path):
     def step():
         binding.filter(img, sc, n, path=path, a_max=a_max, out=out, ctx=ctx)
 
+    ctx.counters(reset=True)
     wall, ms = time_steps(step, args.steps, args.warmup, stream)
     ctx.check_device()
+    tried, redo = ctx.counters(reset=True)
     if args.copy_probe_mib:
         # a plain device copy of known size, for scaling the profiler's byte counters
         src = torch.ones(args.copy_probe_mib << 20, dtype=torch.uint8, device=dev)
@@ -145,6 +147,11 @@ def run_single(args, name, job, a_max, path):
     alg_bytes = P * (in_bytes + 16 + (8 if path == "f64" else 4))
     extra = {"filter_ms": ms, "hbm_algorithmic_GBps": alg_bytes / (ms * 1e-3) / 1e9,
              "hbm_frac_of_8TBps": alg_bytes / (ms * 1e-3) / PEAK_HBM, "a_max": a_max}
+    if path == "f64" and n > 1:
+        # pixels whose taps were evaluated split (high-degree terms in plain float64 under
+        # an error bound), and the fraction of them evaluated again compensated
+        extra["split_eval"] = {"pixels_per_call": tried / max(1, args.steps + args.warmup),
+                               "reevaluated_frac": redo / tried if tried else None}
     return out, ms, wall, roof, extra
 
 

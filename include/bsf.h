@@ -128,6 +128,16 @@ bsf_status bsf_preintegrate(bsf_ctx* ctx, const bsf_job* job, int x0, int y0, in
  * order that occurred). */
 bsf_status bsf_get_device_error(bsf_ctx* ctx, void* stream);
 
+/* Evaluation counters of the float64 path (Section 7 mesh, eq. final_eqn), kept per
+ * context since its creation or the last reset.  A tile whose samples need a single
+ * digit evaluates each tap's interpolant with the terms of total degree above 3 in
+ * plain float64 and the rest compensated, and carries a rigorous bound on the plain
+ * terms' rounding error; a pixel whose bound exceeds 2^-44 of its value is evaluated
+ * again, compensated throughout.  Synchronises `stream` and writes the host array
+ * out[2]: out[0] = pixels evaluated split, out[1] = pixels among them evaluated again.
+ * reset != 0 clears both afterwards.  Order 1 is always compensated and not counted. */
+bsf_status bsf_get_counters(bsf_ctx* ctx, void* stream, unsigned long long* out, int reset);
+
 /* Test aid for the on-chip pre-integrator (stage 1 of Section 7, eq. RS): run only the
  * stage-1 part of the tile kernel for output tile `tile` (row-major tile index, 16x16
  * tiles) of `job` and write the box part of its restart window, int64 row-major

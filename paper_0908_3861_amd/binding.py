@@ -59,13 +59,14 @@ def load():
             lib.bsf_filter_batched.argtypes = [vp, jp, i, vp]
             lib.bsf_preintegrate.argtypes = [vp, jp, i, i, i, i, vp, ctypes.c_ssize_t, vp]
             lib.bsf_get_device_error.argtypes = [vp, vp]
+            lib.bsf_get_counters.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_ulonglong), i]
             lib.bsf_status_string.argtypes = [i]
             lib.bsf_status_string.restype = ctypes.c_char_p
             lib.bsf_last_error.argtypes = [vp]
             lib.bsf_last_error.restype = ctypes.c_char_p
             lib.bsf_debug_tile_window.argtypes = [vp, jp, i, vp, ctypes.c_longlong, vp, vp]
             for fn in ("bsf_create", "bsf_destroy", "bsf_workspace_size", "bsf_filter", "bsf_filter_batched",
-                       "bsf_preintegrate", "bsf_get_device_error", "bsf_debug_tile_window"):
+                       "bsf_preintegrate", "bsf_get_device_error", "bsf_get_counters", "bsf_debug_tile_window"):
                 getattr(lib, fn).restype = i
             _lib = lib
     return _lib
@@ -98,6 +99,12 @@ class Context:
 
     def check_device(self, stream=None):
         self._check(self.device_error(stream))
+
+    def counters(self, stream=None, reset: bool = False) -> tuple[int, int]:
+        """(pixels of the float64 path evaluated split, pixels evaluated again compensated)."""
+        out = (ctypes.c_ulonglong * 2)()
+        self._check(self.lib.bsf_get_counters(self._h, _stream_ptr(stream), out, int(reset)))
+        return int(out[0]), int(out[1])
 
     def close(self):
         if self._h:

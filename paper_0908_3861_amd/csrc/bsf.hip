@@ -43,6 +43,8 @@ struct JobDesc {
 struct Launch {
     long long lds_cap;    // int64 elements a window may use (dynamic LDS, or a scratch slice)
     unsigned* err;        // sticky error bits
+    unsigned long long* stats;  // [0] pixels of the float64 path evaluated split, [1] of
+                                //   those evaluated again compensated (null: not counted)
     unsigned* push_count; // tiles whose window does not fit go to this list for a later,
     int2* push_list;      //   larger launch: (job, tile); push_cap = 0 flags them instead
     int push_cap;
@@ -422,9 +424,78 @@ __device__ __forceinline__ void horner_chunk_dd(
     }
 }
 
-template <int N, int SRC, int ALO, int AHI, bool FIRST>
+// A coefficient's parts as one rounded double (at most two roundings).
+template <int PARTS, int SHIFT>
+__device__ __forceinline__ double join_plain(const double* g) {
+    if constexpr (PARTS == 1) return g[0];
+    else if constexpr (PARTS == 2) return __fma_rn(g[1], (double)(1ll << SHIFT), g[0]);
+    else return __fma_rn(g[2], (double)(1ll << (2 * SHIFT)), __fma_rn(g[1], (double)(1ll << SHIFT), g[0]));
+}
+
+__host__ __device__ constexpr double pow2_neg(int k) {
+    double r = 1.0;
+    for (int i = 0; i < k; ++i) r *= 0.5;
+    return r;
+}
+
+// The same polynomial split by total degree a + b.  The terms above LOW -- the high
+// differences of the pre-integrated window, small next to the low ones wherever the
+// window is smooth on the scale of the cell -- go through a plain FMA Horner at the
+// high words of v (PH); the terms up to LOW through the compensated Horner (PL).  With
+// |v1|, |v2| <= 1/2 the plain part's error is at most gamma * B, B = sum |G_ab| 2^-(a+b)
+// over its terms, where gamma covers the coefficient joins, the dropped low words of v
+// and the Horner roundings along any path (at most 3 DEG + 2 units of 2^-53).
+template <int N, int PARTS, int SHIFT, int ALO, int AHI, int LOW, bool FIRST>
+__device__ __forceinline__ void horner_chunk_split(
+    const double (&G)[PARTS][mono_index<Tab<N>::DEG>(AHI, Tab<N>::DEG - AHI) - mono_index<Tab<N>::DEG>(ALO, 0) + 1],
+    dd v1, dd v2, double& PH, cp& PL, double& B) {
+    constexpr int DEG = Tab<N>::DEG;
+    constexpr int M0 = mono_index<DEG>(ALO, 0);
+    static_assert(LOW < DEG, "the split needs a plain part");
+#pragma unroll
+    for (int a = AHI; a >= ALO; --a) {
+        double c[PARTS];
+        double qh = 0.0;
+#pragma unroll
+        for (int b = DEG - a; b >= 0; --b) {
+            if (a + b > LOW) {
+#pragma unroll
+                for (int p = 0; p < PARTS; ++p) c[p] = G[p][mono_index<DEG>(a, b) - M0];
+                const double x = join_plain<PARTS, SHIFT>(c);
+                B = __fma_rn(fabs(x), pow2_neg(a + b), B);
+                qh = (b == DEG - a) ? x : __fma_rn(qh, v2.hi, x);
+            } else {
+                qh = qh * v2.hi;
+            }
+        }
+        PH = (FIRST && a == AHI) ? qh : __fma_rn(PH, v1.hi, qh);
+        if (a <= LOW) {
+#pragma unroll
+            for (int p = 0; p < PARTS; ++p) c[p] = G[p][mono_index<DEG>(a, LOW - a) - M0];
+            cp q = join_parts<PARTS, SHIFT>(c);
+#pragma unroll
+            for (int b = LOW - a - 1; b >= 0; --b) {
+#pragma unroll
+                for (int p = 0; p < PARTS; ++p) c[p] = G[p][mono_index<DEG>(a, b) - M0];
+                if constexpr (PARTS == 1) q = cp_horner(q, v2, c[0]);
+                else q = cp_horner(q, v2, join_parts<PARTS, SHIFT>(c));
+            }
+            PL = (a == LOW) ? q : cp_horner(PL, v1, q);
+        }
+    }
+}
+
+// Split evaluation: terms of total degree up to split_low<N>() compensated, the rest
+// plain.  Order 1 (degree 2) is evaluated compensated throughout.
+template <int N>
+__host__ __device__ constexpr int split_low() { return N == 1 ? Tab<N>::DEG : 3; }
+// a1 a2 a3 a4 from which a pixel's taps are evaluated split (see process_tile)
+template <int N>
+__host__ __device__ constexpr double split_min_volume() { return N == 2 ? 81.0 : 410.0; }
+
+template <int N, int SRC, int ALO, int AHI, bool FIRST, int LOW>
 __device__ __forceinline__ void interp_chunk_dd(const long long* S, const TapFrame<N>& fr, dd v1, dd v2, cp& P,
-                                                unsigned& bad) {
+                                                double& PH, double& B, unsigned& bad) {
     using T = Tab<N>;
     constexpr int PARTS = SRC == SRC_DBL ? 1 : T::SPLIT;
     double G[PARTS][mono_index<T::DEG>(AHI, T::DEG - AHI) - mono_index<T::DEG>(ALO, 0) + 1];
@@ -434,7 +505,10 @@ __device__ __forceinline__ void interp_chunk_dd(const long long* S, const TapFra
         accumulate_chunk3<SRC, PARTS, T::SHIFT, ALO, AHI>(S, fr, G, bad);
     else
         accumulate_chunk<N, SRC, PARTS, T::SHIFT, ALO, AHI>(S, fr, G, bad);
-    horner_chunk_dd<N, PARTS, T::SHIFT, ALO, AHI, FIRST>(G, v1, v2, P);
+    if constexpr (LOW >= T::DEG)
+        horner_chunk_dd<N, PARTS, T::SHIFT, ALO, AHI, FIRST>(G, v1, v2, P);
+    else
+        horner_chunk_split<N, PARTS, T::SHIFT, ALO, AHI, LOW, FIRST>(G, v1, v2, PH, P, B);
 }
 
 // Horner over the chunk's u1-powers AHI..ALO in plain double, continuing P.
@@ -470,16 +544,21 @@ __device__ __forceinline__ void interp_chunk_f64(const long long* S, const TapFr
 // sum_j g[q+j] beta(o + u - j) = (1/DEN) sum_alpha G_alpha v^alpha: the coefficients
 // accumulated exactly, the polynomial in compensated arithmetic (order 3 in u1-chunks
 // to bound registers).
-template <int N, int SRC>
-__device__ __forceinline__ cp interp_dd(const long long* S, const TapFrame<N>& fr, dd v1, dd v2, unsigned& bad) {
+// With LOW below the degree, B receives the plain part's error weight (see
+// horner_chunk_split) and the plain part is folded into the low word of the result.
+template <int N, int SRC, int LOW>
+__device__ __forceinline__ cp interp_dd(const long long* S, const TapFrame<N>& fr, dd v1, dd v2, double& B,
+                                        unsigned& bad) {
     using T = Tab<N>;
     cp P = {0.0, 0.0};
+    double PH = 0.0;
     if constexpr (N < 3 || SRC == SRC_DBL) {
-        interp_chunk_dd<N, SRC, 0, T::DEG, true>(S, fr, v1, v2, P, bad);
+        interp_chunk_dd<N, SRC, 0, T::DEG, true, LOW>(S, fr, v1, v2, P, PH, B, bad);
     } else {  // three parts: two u1-chunks (84 and 114 accumulators)
-        interp_chunk_dd<N, SRC, 4, 10, true>(S, fr, v1, v2, P, bad);
-        interp_chunk_dd<N, SRC, 0, 3, false>(S, fr, v1, v2, P, bad);
+        interp_chunk_dd<N, SRC, 4, 10, true, LOW>(S, fr, v1, v2, P, PH, B, bad);
+        interp_chunk_dd<N, SRC, 0, 3, false, LOW>(S, fr, v1, v2, P, PH, B, bad);
     }
+    if constexpr (LOW < T::DEG) P.c += PH;
     return P;
 }
 
@@ -519,9 +598,12 @@ __device__ __forceinline__ dd dd_turn(bool swap, bool neg, dd a, dd b) {  // +-(
 // n tau per Section 7 (the shift of eq. factor, n-fold).  Window coordinates: (mx, my)
 // is the pixel relative to the window origin.  Returns s in units of the integer
 // samples (the caller applies the input quantum).
-template <int N, int SRC>
+//
+// With LOW below the polynomial degree the taps use the split evaluation and E receives
+// sum_k |c_k| B_k, which times 2^-47 bounds the error of the plain parts.
+template <int N, int SRC, int LOW = Tab<N>::DEG>
 __device__ dd mesh_dd(const long long* S, int wq, int hq, int mx, int my, float4 a, int k2lo, int k2hi,
-                      unsigned& bad) {
+                      unsigned& bad, double& E) {
     const dd isq = {kInvSqrt2Hi, kInvSqrt2Lo};
     const double a1 = a.x, a3 = a.z;
     const dd A2 = dd_mul_d(isq, (double)a.y);  // a'_2 = a2/sqrt2 (lattice units along (1,1))
@@ -564,10 +646,12 @@ __device__ dd mesh_dd(const long long* S, int wq, int hq, int mx, int my, float4
                         bad = 1;
                         continue;
                     }
-                    const cp P = interp_dd<N, SRC>(S, fr, v1, v2, bad);
+                    double Bk = 0.0;
+                    const cp P = interp_dd<N, SRC, LOW>(S, fr, v1, v2, Bk, bad);
                     const int c = c124 * fd_binom<N>(k3);
                     const double cs = ((k1 + k2 + k3 + k4) & 1) ? -(double)c : (double)c;
                     acc = cp_axpy(acc, cs, P);
+                    if constexpr (LOW < Tab<N>::DEG) E = __fma_rn((double)c, Bk, E);
                 }
             }
         }
@@ -926,16 +1010,46 @@ __device__ __forceinline__ void process_tile(const JobDesc A, int job, int tile,
                 for (int i = tid; i < g.qn; i += NT) reinterpret_cast<double*>(S)[i] = (double)S[i];
                 __syncthreads();
             }
+            bool tried = false, redo = false;
+            // The split is tried by whole waves whose pixels all have a geometric-mean
+            // scale of at least 3 (order 2) or 4.5 (order 3): the bound's ratio to |s|
+            // falls roughly as that scale's 6th (7th) power and holds there as a rule;
+            // below, a wave would mostly pay for both evaluations.
+            const bool wave_split =
+                __all(!(inside && valid) || (double)a.x * a.y * a.z * a.w >= split_min_volume<N>()) != 0;
             if (inside && valid) {
                 const double wk = ldexp(1.0, k * B);
                 if (PATH == BSF_PATH_F64) {
-                    const dd m = fast ? mesh_dd<N, SRC_DBL>(S, g.wq, g.hq, mx, my, a, k2lo, k2hi, bad)
-                                      : mesh_dd<N, SRC_INT>(S, g.wq, g.hq, mx, my, a, k2lo, k2hi, bad);
+                    dd m;
+                    double E = 0.0;
+                    bool done_m = false;
+                    if constexpr (split_low<N>() < Tab<N>::DEG) {
+                        if (K == 1 && wave_split) {
+                            tried = true;
+                            // split evaluation; a pixel whose bound on the plain parts' error,
+                            // 2^-47 E, exceeds 2^-44 |s| is evaluated again, compensated
+                            constexpr int LOW = split_low<N>();
+                            m = fast ? mesh_dd<N, SRC_DBL, LOW>(S, g.wq, g.hq, mx, my, a, k2lo, k2hi, bad, E)
+                                     : mesh_dd<N, SRC_INT, LOW>(S, g.wq, g.hq, mx, my, a, k2lo, k2hi, bad, E);
+                            done_m = E <= 8.0 * fabs(m.hi);
+                            redo = !done_m;
+                        }
+                    }
+                    if (!done_m)
+                        m = fast ? mesh_dd<N, SRC_DBL>(S, g.wq, g.hq, mx, my, a, k2lo, k2hi, bad, E)
+                                 : mesh_dd<N, SRC_INT>(S, g.wq, g.hq, mx, my, a, k2lo, k2hi, bad, E);
                     acc_dd = dd_add(acc_dd, dd_mul_d(m, wk));
                 } else {
                     const double m = fast ? mesh_f64<N, SRC_DBL>(S, g.wq, g.hq, mx, my, a, k2lo, k2hi, bad)
                                           : mesh_f64<N, SRC_INT>(S, g.wq, g.hq, mx, my, a, k2lo, k2hi, bad);
                     acc_f = __fma_rn(m, wk, acc_f);
+                }
+            }
+            if (L.stats) {  // pixels evaluated split, and those evaluated again (one atomic per wave)
+                const int t = __popcll(__ballot(tried)), r = __popcll(__ballot(redo));
+                if ((tid & 63) == 0 && t) {
+                    atomicAdd(L.stats, (unsigned long long)t);
+                    if (r) atomicAdd(L.stats + 1, (unsigned long long)r);
                 }
             }
         }
@@ -1360,6 +1474,7 @@ struct bsf_ctx {
     int cus = 256;
     size_t ws_limit = 0;
     unsigned* d_err = nullptr;
+    unsigned long long* d_stats = nullptr;  // inside the d_err allocation
     // Per-call device work areas (counters, overflow list, batch descriptors) and pinned
     // host staging, in a ring: calls on different streams may be in flight together; a
     // slot is reused only after the call that last used it has finished on the device.
@@ -1497,6 +1612,7 @@ Tiers make_tiers_at(const bsf_ctx* c, const Plan& p, unsigned* ctr, int2* la, in
     t.L1 = Launch{};
     t.L1.lds_cap = p.t1;
     t.L1.err = c->d_err;
+    t.L1.stats = c->d_stats;
     t.L2 = t.L1;
     t.L2.lds_cap = p.t2;
     t.L3 = t.L1;
@@ -1748,12 +1864,13 @@ bsf_status bsf_create(bsf_ctx** out, int hip_device, size_t workspace_limit_byte
             return BSF_ERR_HIP;
         }
     }
-    e = hipMalloc(&c->d_err, sizeof(unsigned));
+    e = hipMalloc(&c->d_err, 64);  // the error word, then the two counters at byte 8
     if (e != hipSuccess) {
         delete c;
         return BSF_ERR_HIP;
     }
-    e = hipMemset(c->d_err, 0, sizeof(unsigned));
+    c->d_stats = reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(c->d_err) + 8);
+    e = hipMemset(c->d_err, 0, 64);
     if (e != hipSuccess) {
         hipFree(c->d_err);
         delete c;
@@ -1966,6 +2083,19 @@ bsf_status bsf_get_device_error(bsf_ctx* c, void* stream) {
     if (h & kErrScale) return fail(c, BSF_ERR_SCALE_RANGE, "a scale was not finite or outside [0.5, 1e4]");
     if (h & kErrWindow) return fail(c, BSF_ERR_UNSUPPORTED, "a restart window exceeded the on-chip memory");
     if (h & kErrRange) return fail(c, BSF_ERR_RANGE, "a pre-integrated value left the int64 range");
+    return BSF_OK;
+}
+
+bsf_status bsf_get_counters(bsf_ctx* c, void* stream, unsigned long long* out, int reset) {
+    if (!c || !out) return BSF_ERR_INVALID_ARG;
+    hipError_t e = hipMemcpyAsync(out, c->d_stats, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                                  (hipStream_t)stream);
+    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+    if (e == hipSuccess && reset) {
+        e = hipMemsetAsync(c->d_stats, 0, 2 * sizeof(unsigned long long), (hipStream_t)stream);
+        if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "reading the evaluation counters");
     return BSF_OK;
 }
 

@@ -270,6 +270,35 @@ def test_parity_smallest_scales(bsf, torch_dev, oracle_mod, n, lo, hi):
     assert rel_max(s, o) < TOL_F64, (n, rel_max(s, o))
 
 
+@pytest.mark.parametrize("n", [2, 3])
+def test_split_evaluation_and_its_fallback(bsf, torch_dev, oracle_mod, n):
+    """Tiles whose samples need one digit evaluate each tap's terms of total degree above 3
+    in plain float64 under a rigorous bound on their rounding error; a pixel whose bound
+    exceeds 2^-44 of its value is evaluated again, compensated.  The scales are large
+    everywhere (every wave tries the split); the left part of the image is a blurred
+    positive image (the bound holds), the right part a +-100 checkerboard, which the
+    filter all but cancels while its high differences are the largest possible (the
+    relative bound fails there).  Both branches run, and every pixel stays within the
+    float64 tolerance."""
+    torch = torch_dev
+    rng = np.random.default_rng(130 + n)
+    H, W, cut = 37, 75, 40
+    img = synth.blurred_u8_image(rng, H, W, 3.0).astype(np.float64)
+    yy, xx = np.mgrid[0:H, cut:W]
+    img[:, cut:] = 100.0 * (1 - 2 * ((xx + yy) & 1))
+    sc = synth.smooth_scales(rng, H, W, 3.5, 6.0, 8.0) if n == 2 else synth.smooth_scales(rng, H, W, 5.0, 6.5, 8.0)
+    ctx = bsf.default_context()
+    ctx.counters(reset=True)
+    s, st = run(bsf, torch, img, sc, n)
+    assert st == 0
+    tried, redo = ctx.counters(reset=True)
+    print(f"n={n}: {tried} of {H * W} pixels split, {redo} evaluated again")
+    assert tried > 0 and 0 < redo < tried
+    o = oracle_mod.filter(img, sc, n)
+    assert rel_max(s, o) < TOL_F64, rel_max(s, o)
+    assert rel_max(s[:, :cut], o[:, :cut]) < TOL_F64
+
+
 def test_parity_order3_u8_and_float(bsf, torch_dev, oracle_mod):
     rng = np.random.default_rng(110)
     H, W = 19, 21
