@@ -10,6 +10,7 @@
 //      pixel's (n+1)^4 finite-difference taps, interpolating the pre-integrated
 //      window with the lattice box spline.
 #include <hip/hip_runtime.h>
+#include <type_traits>
 
 #include <algorithm>
 #include <cmath>
@@ -89,59 +90,116 @@ __device__ __forceinline__ long long sub_ovf(long long a, long long b, unsigned&
 __device__ __forceinline__ double add_ovf(double a, double b, unsigned&) { return a + b; }
 __device__ __forceinline__ double sub_ovf(double a, double b, unsigned&) { return a - b; }
 
-// Running sum along one line of the window: points (r0 + t*dr, c0 + t*dc), t < len.
-// tref < 0: y[t] = sum_{s<=t} x[s] (zero initial condition at the line's start, as in
-// the paper's recursions).  tref >= 0: the same recursion y[t] = y[t-1] + x[t] but
-// anchored at y[tref] = 0; the two differ by a constant along the line, which every
-// finite difference of the mesh along that direction cancels, and it keeps the
-// integers small near the tile centre.
-template <typename V>
-__device__ void scan_line(V* S, const Geo& g, int r0, int c0, int dr, int dc, int len, int tref, unsigned& ovf) {
+// Walks one line of the window point by point, keeping the LDS address up to date:
+// (r, c) moves by (dr, dc) with dr in {-1, 0, 1}; the box is row-major, triangle row r
+// starts at T(r) = qn + r (hq - 1) - r (r - 1) / 2 and holds columns wq.. of that row.
+struct LineWalk {
+    int r, c, rowbase, tr, a;
+};
+__device__ __forceinline__ LineWalk walk_at(const Geo& g, int r, int c) {
+    LineWalk w;
+    w.r = r;
+    w.c = c;
+    w.rowbase = r * g.wq;
+    w.tr = g.qn + r * (g.hq - 1) - ((r * (r - 1)) >> 1);
+    w.a = c < g.wq ? w.rowbase + c : w.tr + (c - g.wq);
+    return w;
+}
+template <int DR, int DC>
+__device__ __forceinline__ void walk_step(const Geo& g, LineWalk& w, int sgn) {  // sgn = +1 forward, -1 back
+    const int dr = DR * sgn, dc = DC * sgn;
+    if (dr > 0) w.tr += g.hq - 1 - w.r;
+    w.r += dr;
+    if (dr < 0) w.tr -= g.hq - 1 - w.r;
+    w.rowbase += dr * g.wq;
+    w.c += dc;
+    w.a = w.c < g.wq ? w.rowbase + w.c : w.tr + (w.c - g.wq);
+}
+
+// The n-fold running sum (n = NF) of one line of the window, points (r0, c0) + t (dr, dc),
+// t < len, in one pass with n running states.  tref < 0: y_k[t] = sum_{s <= t} y_{k-1}[s]
+// (zero initial condition at the line's start, as in the paper's recursions).  tref >=
+// 0: the same recursions anchored at y_k[tref] = 0; they differ from the former by a
+// polynomial of degree < n along the line, which the mesh's n-fold finite difference along
+// that direction cancels, and they keep the integers small near the tile centre.  An
+// anchored line is two independent recursions -- forward from tref (part 0) and backward
+// from it (part 1, which also zeroes tref) -- run by different threads.  CHECK: detect
+// int64 overflow (the recursions wrap modulo 2^64 either way).
+template <int NF, bool CHECK, int DR, int DC, typename V>
+__device__ void scan_line_n(V* S, const Geo& g, int r0, int c0, int len, int tref, int part, unsigned& ovf) {
     constexpr int B = 8;
-    V acc = 0;
-    int t = tref + 1;
-    for (; t + B <= len; t += B) {
-        int ad[B];
-        V v[B];
+    V y[NF];
 #pragma unroll
-        for (int i = 0; i < B; ++i) ad[i] = waddr(g, r0 + (t + i) * dr, c0 + (t + i) * dc);
-#pragma unroll
-        for (int i = 0; i < B; ++i) v[i] = S[ad[i]];
-#pragma unroll
-        for (int i = 0; i < B; ++i) {
-            acc = add_ovf(acc, v[i], ovf);
-            S[ad[i]] = acc;
-        }
-    }
-    for (; t < len; ++t) {
-        const int ad = waddr(g, r0 + t * dr, c0 + t * dc);
-        acc = add_ovf(acc, S[ad], ovf);
-        S[ad] = acc;
-    }
-    if (tref >= 0) {
-        const int aref = waddr(g, r0 + tref * dr, c0 + tref * dc);
-        V prev = S[aref];
-        acc = 0;
-        t = tref - 1;
-        for (; t - B + 1 >= 0; t -= B) {
+    for (int k = 0; k < NF; ++k) y[k] = 0;
+    auto add = [&](V a, V b) -> V {
+        if constexpr (CHECK) return add_ovf(a, b, ovf);
+        else return a + b;
+    };
+    auto sub = [&](V a, V b) -> V {
+        if constexpr (CHECK) return sub_ovf(a, b, ovf);
+        else return a - b;
+    };
+    if (part == 0) {  // forward: y_1 += x, y_k += y_{k-1}
+        int t = tref + 1;
+        if (t >= len) return;
+        LineWalk w = walk_at(g, r0 + t * DR, c0 + t * DC);
+        for (; t + B <= len; t += B) {
             int ad[B];
             V v[B];
 #pragma unroll
-            for (int i = 0; i < B; ++i) ad[i] = waddr(g, r0 + (t - i) * dr, c0 + (t - i) * dc);
+            for (int i = 0; i < B; ++i) {
+                ad[i] = w.a;
+                walk_step<DR, DC>(g, w, 1);
+            }
 #pragma unroll
             for (int i = 0; i < B; ++i) v[i] = S[ad[i]];
 #pragma unroll
             for (int i = 0; i < B; ++i) {
-                acc = sub_ovf(acc, prev, ovf);
+                y[0] = add(y[0], v[i]);
+#pragma unroll
+                for (int k = 1; k < NF; ++k) y[k] = add(y[k], y[k - 1]);
+                S[ad[i]] = y[NF - 1];
+            }
+        }
+        for (; t < len; ++t) {
+            y[0] = add(y[0], S[w.a]);
+#pragma unroll
+            for (int k = 1; k < NF; ++k) y[k] = add(y[k], y[k - 1]);
+            S[w.a] = y[NF - 1];
+            walk_step<DR, DC>(g, w, 1);
+        }
+    } else {  // backward from tref: y_k[t] = y_k[t+1] - y_{k-1}[t+1], y_0 = x
+        LineWalk w = walk_at(g, r0 + tref * DR, c0 + tref * DC);
+        const int aref = w.a;
+        V prev = S[aref];
+        int t = tref - 1;
+        walk_step<DR, DC>(g, w, -1);
+        for (; t - B + 1 >= 0; t -= B) {
+            int ad[B];
+            V v[B];
+#pragma unroll
+            for (int i = 0; i < B; ++i) {
+                ad[i] = w.a;
+                walk_step<DR, DC>(g, w, -1);
+            }
+#pragma unroll
+            for (int i = 0; i < B; ++i) v[i] = S[ad[i]];
+#pragma unroll
+            for (int i = 0; i < B; ++i) {
+#pragma unroll
+                for (int k = NF - 1; k > 0; --k) y[k] = sub(y[k], y[k - 1]);
+                y[0] = sub(y[0], prev);
                 prev = v[i];
-                S[ad[i]] = acc;
+                S[ad[i]] = y[NF - 1];
             }
         }
         for (; t >= 0; --t) {
-            const int ad = waddr(g, r0 + t * dr, c0 + t * dc);
-            acc = sub_ovf(acc, prev, ovf);
-            prev = S[ad];
-            S[ad] = acc;
+#pragma unroll
+            for (int k = NF - 1; k > 0; --k) y[k] = sub(y[k], y[k - 1]);
+            y[0] = sub(y[0], prev);
+            prev = S[w.a];
+            S[w.a] = y[NF - 1];
+            walk_step<DR, DC>(g, w, -1);
         }
         S[aref] = 0;
     }
@@ -149,40 +207,63 @@ __device__ void scan_line(V* S, const Geo& g, int r0, int c0, int dr, int dc, in
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-// Stage 1 on the window (eq. RS steps (1)-(4), n folds each).  cen: anchor every
-// line at the tile centre (cc, rc) instead of at its start.
-template <typename V>
-__device__ void preintegrate_window(V* S, const Geo& g, int n, bool cen, int cc, int rc, unsigned& ovf) {
+// Stage 1 on the window (eq. RS steps (1)-(4), n folds each, fused into one pass per
+// direction).  cen: anchor every line at the tile centre (cc, rc) instead of at its start.
+template <int NF, bool CHECK, typename V>
+__device__ void preintegrate_window_n(V* S, const Geo& g, bool cen, int cc, int rc, unsigned& ovf) {
     const int tid = threadIdx.x, nt = blockDim.x;
     const int W = g.wq, H = g.hq, Wt = W + H - 1;
-    for (int f = 0; f < n; ++f) {  // (1) along (1,0): rows
-        for (int r = tid; r < H; r += nt) scan_line(S, g, r, 0, 0, 1, Wt - r, cen ? clampi(cc, 0, Wt - r - 1) : -1, ovf);
-        __syncthreads();
+    const int parts = cen ? 2 : 1;
+    for (int it = tid; it < H * parts; it += nt) {  // (1) along (1,0): rows
+        const int part = it >= H, r = it - part * H;
+        scan_line_n<NF, CHECK, 0, 1>(S, g, r, 0, Wt - r, cen ? clampi(cc, 0, Wt - r - 1) : -1, part, ovf);
     }
-    for (int f = 0; f < n; ++f) {  // (2) along (1,1): diagonals c - r = e
-        for (int i = tid; i < Wt + H - 1; i += nt) {
-            const int e = i - (H - 1);
-            const int rs = e < 0 ? -e : 0;
-            const int re = std::min(H - 1, (W + H - 2 - e) >> 1);
-            const int len = re - rs + 1;
-            scan_line(S, g, rs, e + rs, 1, 1, len, cen ? clampi(rc - rs, 0, len - 1) : -1, ovf);
-        }
-        __syncthreads();
+    __syncthreads();
+    const int nd = Wt + H - 1;
+    for (int it = tid; it < nd * parts; it += nt) {  // (2) along (1,1): diagonals c - r = e
+        const int part = it >= nd, i = it - part * nd;
+        const int e = i - (H - 1);
+        const int rs = e < 0 ? -e : 0;
+        const int re = std::min(H - 1, (W + H - 2 - e) >> 1);
+        const int len = re - rs + 1;
+        scan_line_n<NF, CHECK, 1, 1>(S, g, rs, e + rs, len, cen ? clampi(rc - rs, 0, len - 1) : -1, part, ovf);
     }
-    for (int f = 0; f < n; ++f) {  // (3) along (0,1): columns
-        for (int c = tid; c < Wt; c += nt) {
-            const int len = std::min(H, Wt - c);
-            scan_line(S, g, 0, c, 1, 0, len, cen ? clampi(rc, 0, len - 1) : -1, ovf);
-        }
-        __syncthreads();
+    __syncthreads();
+    for (int it = tid; it < Wt * parts; it += nt) {  // (3) along (0,1): columns
+        const int part = it >= Wt, c = it - part * Wt;
+        const int len = std::min(H, Wt - c);
+        scan_line_n<NF, CHECK, 1, 0>(S, g, 0, c, len, cen ? clampi(rc, 0, len - 1) : -1, part, ovf);
     }
-    for (int f = 0; f < n; ++f) {  // (4) along (-1,1): anti-diagonals c + r = e, read down-right
-        for (int e = tid; e < Wt; e += nt) {
-            const int len = std::min(H, e + 1);
-            scan_line(S, g, 0, e, 1, -1, len, cen ? clampi(rc, 0, len - 1) : -1, ovf);
-        }
-        __syncthreads();
+    __syncthreads();
+    for (int it = tid; it < Wt * parts; it += nt) {  // (4) along (-1,1): anti-diagonals c + r = e, read down-right
+        const int part = it >= Wt, e = it - part * Wt;
+        const int len = std::min(H, e + 1);
+        scan_line_n<NF, CHECK, 1, -1>(S, g, 0, e, len, cen ? clampi(rc, 0, len - 1) : -1, part, ovf);
     }
+    __syncthreads();
+}
+
+// binom(m + n - 1, n) as a double: the largest n-fold running sum of a line of m values
+// of magnitude at most 1
+__device__ __forceinline__ double fold_gain(int m, int n) {
+    double r = 1.0;
+    for (int i = 0; i < n; ++i) r = r * (double)(m + i) / (double)(i + 1);
+    return r;
+}
+
+// Stage 1 with the overflow checks only where an a priori bound does not exclude int64
+// overflow: with |x| < 2^bits, every value of every recursion is below
+// 2^bits * gain(Wt) * gain(hq)^3 (rows are at most Wt = wq + hq - 1 long, the other lines
+// at most hq).
+template <int N, typename V>
+__device__ void preintegrate_window(V* S, const Geo& g, bool cen, int cc, int rc, int bits, unsigned& ovf) {
+    bool check = false;
+    if constexpr (std::is_integral<V>::value) {
+        const double h = fold_gain(g.hq, N);
+        check = !(ldexp(1.0, bits) * fold_gain(g.wq + g.hq - 1, N) * h * h * h < 0x1p62);
+    }
+    if (check) preintegrate_window_n<N, true>(S, g, cen, cc, rc, ovf);
+    else preintegrate_window_n<N, false>(S, g, cen, cc, rc, ovf);
 }
 
 // ---------------------------------------------------------------------------
@@ -742,6 +823,37 @@ __device__ __forceinline__ double load_sample(const JobDesc A, int x, int y) {
     return ((const double*)A.in)[off];
 }
 
+// One input sample as an exact integer v * 2^sh (u8 samples are integers already).
+__device__ __forceinline__ long long load_sample_int(const JobDesc A, int x, int y, int sh) {
+    if (A.in_dtype == BSF_U8) {
+        if (A.border == BSF_BORDER_ZERO) {
+            if (x < 0 || x >= A.width || y < 0 || y >= A.height) return 0;
+        } else {
+            x = clampi(x, 0, A.width - 1);
+            y = clampi(y, 0, A.height - 1);
+        }
+        return (long long)((const unsigned char*)A.in)[(long long)y * A.in_pitch + x];
+    }
+    return (long long)rint(ldexp(load_sample(A, x, y), sh));
+}
+
+// Visits the box elements i = tid, tid + nt, ... of a (wq x hq) window as (i, r, c)
+// without a division per element.
+template <typename F>
+__device__ __forceinline__ void for_box(const Geo& g, int tid, int nt, F f) {
+    int r = tid / g.wq, c = tid - r * g.wq;
+    const int sr = nt / g.wq, sc = nt - sr * g.wq;
+    for (int i = tid; i < g.qn; i += nt) {
+        f(i, r, c);
+        c += sc;
+        r += sr;
+        if (c >= g.wq) {
+            c -= g.wq;
+            ++r;
+        }
+    }
+}
+
 // Integer grid of a sample: top = exponent e with |v| < 2^e, fine = number of fractional
 // bits v needs to become an integer (v = M 2^(e-53) with M a 53-bit integer).
 __device__ __forceinline__ void sample_grid(double v, int& top, int& fine) {
@@ -895,14 +1007,11 @@ __device__ __forceinline__ void process_tile(const JobDesc A, int job, int tile,
         // are), the mesh in float64 from the window as it stands -- no integer grid, no
         // digits.  The error is the mesh's cancellation times a few float64 roundings.
         double* Sd = reinterpret_cast<double*>(S);
-        for (int i = tid; i < g.qn; i += NT) {
-            const int r = i / g.wq, c = i - r * g.wq;
-            Sd[i] = load_sample(A, w.x0 + c, w.y0 + r);
-        }
+        for_box(g, tid, NT, [&](int i, int r, int c) { Sd[i] = load_sample(A, w.x0 + c, w.y0 + r); });
         for (int i = tid; i < ntri; i += NT) Sd[g.qn + i] = 0.0;
         __syncthreads();
         unsigned unused = 0;
-        preintegrate_window(Sd, g, N, cen, cc, rc, unused);
+        preintegrate_window<N>(Sd, g, cen, cc, rc, 0, unused);
         __syncthreads();
         if (L.dbg_window) {  // the window as float64 bit patterns
             if (tid == 0) {
@@ -934,14 +1043,15 @@ __device__ __forceinline__ void process_tile(const JobDesc A, int job, int tile,
 
     // 3. an exact integer grid for the window: samples become v * 2^sh with at most 53
     //    significant bits (finer bits than 2^-53 of the window maximum are rounded)
-    int top = -1100, fine = 0;
-    for (int i = tid; i < g.qn; i += NT) {
-        const int r = i / g.wq, c = i - r * g.wq;
-        int t_, f_;
-        sample_grid(load_sample(A, w.x0 + c, w.y0 + r), t_, f_);
-        top = max(top, t_);
-        fine = max(fine, f_);
-    }
+    //    (u8 samples: integers below 2^8, no scan)
+    int top = A.in_dtype == BSF_U8 ? 8 : -1100, fine = 0;
+    if (A.in_dtype != BSF_U8)
+        for_box(g, tid, NT, [&](int i, int r, int c) {
+            int t_, f_;
+            sample_grid(load_sample(A, w.x0 + c, w.y0 + r), t_, f_);
+            top = max(top, t_);
+            fine = max(fine, f_);
+        });
     top = wave_max_i(top);
     fine = wave_max_i(fine);
     __syncthreads();
@@ -973,15 +1083,13 @@ __device__ __forceinline__ void process_tile(const JobDesc A, int job, int tile,
         bool overflowed = false;
         for (int k = 0; k < K; ++k) {
             __syncthreads();  // the previous digit's mesh has finished reading the window
-            for (int i = tid; i < g.qn; i += NT) {
-                const int r = i / g.wq, c = i - r * g.wq;
-                const long long iv = (long long)rint(ldexp(load_sample(A, w.x0 + c, w.y0 + r), sh));
-                S[i] = digit(iv, k, K, B);
-            }
+            for_box(g, tid, NT, [&](int i, int r, int c) {
+                S[i] = digit(load_sample_int(A, w.x0 + c, w.y0 + r, sh), k, K, B);
+            });
             for (int i = tid; i < ntri; i += NT) S[g.qn + i] = 0;
             __syncthreads();
             unsigned ovf = 0;
-            preintegrate_window(S, g, N, cen, cc, rc, ovf);
+            preintegrate_window<N>(S, g, cen, cc, rc, (K == 1 ? bits : B) + 1, ovf);
             ovf = __syncthreads_or(ovf);
             if (L.dbg_window) {
                 if (tid == 0) {
