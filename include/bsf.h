@@ -130,8 +130,9 @@ bsf_status bsf_get_device_error(bsf_ctx* ctx, void* stream);
 
 /* Evaluation counters of the float64 path (Section 7 mesh, eq. final_eqn), kept per
  * context since its creation or the last reset.  A tile whose samples need a single
- * digit evaluates each tap's interpolant with the terms of total degree above 3 in
- * plain float64 and the rest compensated, and carries a rigorous bound on the plain
+ * digit evaluates each tap's interpolant with the terms of total degree above 2 (order
+ * 2) or 3 (order 3) in plain float64 and the rest compensated (in waves whose pixels all
+ * have a1 a2 a3 a4 >= 625, resp. 410), and carries a rigorous bound on the plain
  * terms' rounding error; a pixel whose bound exceeds 2^-44 of its value is evaluated
  * again, compensated throughout.  Synchronises `stream` and writes the host array
  * out[2]: out[0] = pixels evaluated split, out[1] = pixels among them evaluated again.

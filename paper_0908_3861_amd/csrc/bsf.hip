@@ -569,10 +569,11 @@ __device__ __forceinline__ void horner_chunk_split(
 // Split evaluation: terms of total degree up to split_low<N>() compensated, the rest
 // plain.  Order 1 (degree 2) is evaluated compensated throughout.
 template <int N>
-__host__ __device__ constexpr int split_low() { return N == 1 ? Tab<N>::DEG : 3; }
-// a1 a2 a3 a4 from which a pixel's taps are evaluated split (see process_tile)
+__host__ __device__ constexpr int split_low() { return N == 1 ? Tab<N>::DEG : (N == 2 ? 2 : 3); }
+// a1 a2 a3 a4 from which a pixel's taps are evaluated split (see process_tile): a
+// geometric-mean scale of 5 (order 2) or 4.5 (order 3)
 template <int N>
-__host__ __device__ constexpr double split_min_volume() { return N == 2 ? 81.0 : 410.0; }
+__host__ __device__ constexpr double split_min_volume() { return N == 2 ? 625.0 : 410.0; }
 
 template <int N, int SRC, int ALO, int AHI, bool FIRST, int LOW>
 __device__ __forceinline__ void interp_chunk_dd(const long long* S, const TapFrame<N>& fr, dd v1, dd v2, cp& P,
@@ -1120,9 +1121,9 @@ __device__ __forceinline__ void process_tile(const JobDesc A, int job, int tile,
             }
             bool tried = false, redo = false;
             // The split is tried by whole waves whose pixels all have a geometric-mean
-            // scale of at least 3 (order 2) or 4.5 (order 3): the bound's ratio to |s|
-            // falls roughly as that scale's 6th (7th) power and holds there as a rule;
-            // below, a wave would mostly pay for both evaluations.
+            // scale of at least split_min_volume^(1/4): the bound's ratio to |s| falls
+            // roughly as that scale's 6th (order 2) or 7th (order 3) power and holds there
+            // as a rule; below, a wave would mostly pay for both evaluations.
             const bool wave_split =
                 __all(!(inside && valid) || (double)a.x * a.y * a.z * a.w >= split_min_volume<N>()) != 0;
             if (inside && valid) {

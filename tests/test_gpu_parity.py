@@ -272,8 +272,8 @@ def test_parity_smallest_scales(bsf, torch_dev, oracle_mod, n, lo, hi):
 
 @pytest.mark.parametrize("n", [2, 3])
 def test_split_evaluation_and_its_fallback(bsf, torch_dev, oracle_mod, n):
-    """Tiles whose samples need one digit evaluate each tap's terms of total degree above 3
-    in plain float64 under a rigorous bound on their rounding error; a pixel whose bound
+    """Tiles whose samples need one digit evaluate each tap's terms of total degree above 2
+    (order 2) or 3 (order 3) in plain float64 under a rigorous bound on their rounding error; a pixel whose bound
     exceeds 2^-44 of its value is evaluated again, compensated.  The scales are large
     everywhere (every wave tries the split); the left part of the image is a blurred
     positive image (the bound holds), the right part a +-100 checkerboard, which the
@@ -286,7 +286,7 @@ def test_split_evaluation_and_its_fallback(bsf, torch_dev, oracle_mod, n):
     img = synth.blurred_u8_image(rng, H, W, 3.0).astype(np.float64)
     yy, xx = np.mgrid[0:H, cut:W]
     img[:, cut:] = 100.0 * (1 - 2 * ((xx + yy) & 1))
-    sc = synth.smooth_scales(rng, H, W, 3.5, 6.0, 8.0) if n == 2 else synth.smooth_scales(rng, H, W, 5.0, 6.5, 8.0)
+    sc = synth.smooth_scales(rng, H, W, 5.5, 8.0, 8.0) if n == 2 else synth.smooth_scales(rng, H, W, 5.0, 6.5, 8.0)
     ctx = bsf.default_context()
     ctx.counters(reset=True)
     s, st = run(bsf, torch, img, sc, n)
