@@ -1837,13 +1837,25 @@ bsf_status acquire_slot(bsf_ctx* c, size_t bytes, int njobs, int& idx) {
     hipError_t e = hipEventSynchronize(sl.done);
     if (e != hipSuccess) return hip_fail(c, e, "waiting for a work slot");
     if (bytes > sl.dev_bytes) {
-        if (sl.dev) (void)hipFree(sl.dev);
-        sl.dev = nullptr;
-        sl.dev_bytes = 0;
+        // a larger work area: grow every slot of the ring now (each after its in-flight
+        // work), so that calls of this size never allocate again; only this slot when the
+        // whole ring would exceed the workspace limit
         const size_t cap = std::max(bytes, (size_t)1 << 16);
-        e = hipMalloc(&sl.dev, cap);
-        if (e != hipSuccess) return hip_fail(c, e, "work list allocation");
-        sl.dev_bytes = cap;
+        const bool all = cap * (size_t)bsf_ctx::kRing <= c->ws_limit;
+        for (int r = 0; r < bsf_ctx::kRing; ++r) {
+            bsf_ctx::Slot& o = c->slot[r];
+            if ((!all && r != idx) || o.dev_bytes >= cap) continue;
+            if (r != idx) {
+                e = hipEventSynchronize(o.done);
+                if (e != hipSuccess) return hip_fail(c, e, "waiting for a work slot");
+            }
+            if (o.dev) (void)hipFree(o.dev);
+            o.dev = nullptr;
+            o.dev_bytes = 0;
+            e = hipMalloc(&o.dev, cap);
+            if (e != hipSuccess) return hip_fail(c, e, "work list allocation");
+            o.dev_bytes = cap;
+        }
     }
     if (njobs > sl.host_cap) {
         if (sl.host) (void)hipHostFree(sl.host);
@@ -1956,7 +1968,7 @@ bsf_status bsf_create(bsf_ctx** out, int hip_device, size_t workspace_limit_byte
     int lds = 0;
     if (hipDeviceGetAttribute(&lds, hipDeviceAttributeSharedMemPerBlockOptin, hip_device) != hipSuccess || lds <= 0) {
         (void)hipGetLastError();
-        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, hip_device);
+        if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, hip_device) != hipSuccess) lds = 0;
     }
     c->lds_max_bytes = lds > 0 ? lds : 65536;
     int cus = 0;
@@ -1981,7 +1993,7 @@ bsf_status bsf_create(bsf_ctx** out, int hip_device, size_t workspace_limit_byte
     c->d_stats = reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(c->d_err) + 8);
     e = hipMemset(c->d_err, 0, 64);
     if (e != hipSuccess) {
-        hipFree(c->d_err);
+        (void)hipFree(c->d_err);
         delete c;
         return BSF_ERR_HIP;
     }
@@ -1991,7 +2003,7 @@ bsf_status bsf_create(bsf_ctx** out, int hip_device, size_t workspace_limit_byte
 
 bsf_status bsf_destroy(bsf_ctx* c) {
     if (!c) return BSF_ERR_INVALID_ARG;
-    hipSetDevice(c->device);
+    (void)hipSetDevice(c->device);
     if (c->d_err) (void)hipFree(c->d_err);
     for (int r = 0; r < bsf_ctx::kRing; ++r) {
         if (c->slot[r].dev) (void)hipFree(c->slot[r].dev);
