@@ -21,6 +21,7 @@
 
 #include "../../include/bsf.h"
 #include "bsf_device.h"
+#include "rep3_groups.h"
 
 namespace bsf {
 
@@ -395,14 +396,16 @@ __device__ __forceinline__ void accumulate_chunk(const long long* S, const TapFr
     }
 }
 
-// Order 3: the same accumulation as a runtime loop over the 36 representative stencil
+// Order 3: the same accumulation as runtime loops over the 36 representative stencil
 // points (fully unrolled, order 3 would be tens of thousands of instructions per variant,
 // and its table values up to 6e7 do not fit the literal forms of the FMA, so each would
 // first be built in registers).  The table, in constant memory, is laid out by
-// representative: its offsets, its mirror's, and its 66 weights (zeros included).  From a
-// float64 window (one part) all 66 coefficient sums are formed in one pass, so every loop
-// iteration carries 66 FMAs and the stencil is read once per tap; with three exact parts
-// the sums are formed in two passes over u1-chunks (84 and 114 accumulators).
+// representative: its offsets, its mirror's, and its 66 weights.  From a float64 window
+// (one part) all 66 coefficient sums are formed in one pass, so the stencil is read once
+// per tap.  With three exact parts the sums are formed in two passes over u1-chunks (84
+// and 114 accumulators), and the points come in groups with a common set of nonzero
+// columns (rep3_groups.h), each group with its own loop whose body touches only those
+// columns (1,882 FMAs per part and tap instead of 2,376).
 struct Rep3 {
     int jx, jy, mjx, mjy, self;
     double w[bsf_tables::kMono3];
@@ -410,12 +413,11 @@ struct Rep3 {
 struct Rep3Table {
     static constexpr int R = (bsf_tables::kStencil3 + 9) / 2;  // 9 self-mirrored points (jy = 0)
     Rep3 r[R];
-    int count;
-    constexpr Rep3Table() : r(), count(0) {
-        for (int j = 0; j < bsf_tables::kStencil3; ++j) {
-            if (!is_rep<3>(j)) continue;
+    constexpr Rep3Table() : r() {
+        for (int k = 0; k < R; ++k) {  // in the order of the groups
+            const int j = bsf_tables::kRep3Points[k];
             const int jm = mirror_of<3>(j);
-            Rep3& q = r[count++];
+            Rep3& q = r[k];
             q.jx = bsf_tables::kJ3[j][0];
             q.jy = bsf_tables::kJ3[j][1];
             q.mjx = bsf_tables::kJ3[jm][0];
@@ -427,28 +429,41 @@ struct Rep3Table {
 };
 __constant__ Rep3Table c_rep3 = Rep3Table();
 
-template <int SRC, int PARTS, int SHIFT, int ALO, int AHI>
-__device__ __forceinline__ void accumulate_chunk3(const long long* S, const TapFrame<3>& fr,
-                                                  double (&G)[PARTS][mono_index<10>(AHI, 10 - AHI) -
-                                                                     mono_index<10>(ALO, 0) + 1],
+__host__ __device__ constexpr int rep3_begin(int grp) {
+    int b = 0;
+    for (int h = 0; h < grp; ++h) b += bsf_tables::kRep3GroupSize[h];
+    return b;
+}
+__host__ __device__ constexpr bool rep3_col(int grp, int c) { return bsf_tables::kRep3Cols[grp][c]; }
+__host__ __device__ constexpr bool rep3_groups_ok() {  // every point a representative, once,
+    bool seen[bsf_tables::kStencil3] = {};              // and every nonzero weight in its columns
+    for (int grp = 0; grp < bsf_tables::kRep3Groups; ++grp)
+        for (int k = rep3_begin(grp); k < rep3_begin(grp + 1); ++k) {
+            const int j = bsf_tables::kRep3Points[k];
+            if (!is_rep<3>(j) || seen[j]) return false;
+            seen[j] = true;
+            for (int m = 0; m < bsf_tables::kMono3; ++m)
+                if (bsf_tables::kNum3[j][m] != 0.0 && !rep3_col(grp, m)) return false;
+        }
+    int reps = 0;
+    for (int j = 0; j < bsf_tables::kStencil3; ++j) reps += is_rep<3>(j) ? 1 : 0;
+    return reps == Rep3Table::R && rep3_begin(bsf_tables::kRep3Groups) == Rep3Table::R;
+}
+static_assert(rep3_groups_ok(), "rep3_groups.h does not match the order-3 table");
+
+template <int GRP, int SRC, int PARTS, int SHIFT, int M0, int CM>
+__device__ __forceinline__ void accumulate_group3(const long long* S, const TapFrame<3>& fr, double (&G)[PARTS][CM],
                                                   unsigned& bad) {
     using T = Tab<3>;
-    constexpr int M0 = mono_index<10>(ALO, 0);
-    constexpr int CM = mono_index<10>(AHI, 10 - AHI) - M0 + 1;
     const double* Sd = reinterpret_cast<const double*>(S);
-    asm volatile("" ::: "memory");  // keep each chunk's LDS reads local to the chunk
-#pragma unroll
-    for (int p = 0; p < PARTS; ++p)
-#pragma unroll
-        for (int c = 0; c < CM; ++c) G[p][c] = 0.0;
 #pragma unroll 1
-    for (int k = 0; k < Rep3Table::R; ++k) {
+    for (int k = rep3_begin(GRP); k < rep3_begin(GRP + 1); ++k) {
         const Rep3& q = c_rep3.r[k];
         const int o1 = fr.base + q.jx * fr.s1 + q.jy * fr.s2, o2 = fr.base + q.mjx * fr.s1 + q.mjy * fr.s2;
         double xs[PARTS], xd[PARTS];
         if constexpr (SRC == SRC_DBL) {
             const double g1 = Sd[o1], g2 = q.self ? 0.0 : Sd[o2];
-            xs[0] = g1 + g2;
+            xs[0] = g1 + g2;  // exact when the window values are below 2^exact_bits
             xd[0] = g1 - g2;
         } else {
             const long long g1 = S[o1], g2 = q.self ? 0ll : S[o2];
@@ -457,13 +472,34 @@ __device__ __forceinline__ void accumulate_chunk3(const long long* S, const TapF
         }
 #pragma unroll
         for (int c = 0; c < CM; ++c) {
+            if (!rep3_col(GRP, M0 + c)) continue;
             const double w = q.w[M0 + c];
 #pragma unroll
             for (int p = 0; p < PARTS; ++p) G[p][c] = __fma_rn(w, (T::mb(M0 + c) & 1) ? xd[p] : xs[p], G[p][c]);
         }
     }
+    if constexpr (GRP + 1 < bsf_tables::kRep3Groups)
+        accumulate_group3<GRP + 1, SRC, PARTS, SHIFT, M0, CM>(S, fr, G, bad);
 }
 
+template <int SRC, int PARTS, int SHIFT, int ALO, int AHI>
+__device__ __forceinline__ void accumulate_chunk3(const long long* S, const TapFrame<3>& fr,
+                                                  double (&G)[PARTS][mono_index<10>(AHI, 10 - AHI) -
+                                                                     mono_index<10>(ALO, 0) + 1],
+                                                  unsigned& bad) {
+    constexpr int M0 = mono_index<10>(ALO, 0);
+    constexpr int CM = mono_index<10>(AHI, 10 - AHI) - M0 + 1;
+    asm volatile("" ::: "memory");  // keep each chunk's LDS reads local to the chunk
+#pragma unroll
+    for (int p = 0; p < PARTS; ++p)
+#pragma unroll
+        for (int c = 0; c < CM; ++c) G[p][c] = 0.0;
+    accumulate_group3<0, SRC, PARTS, SHIFT, M0, CM>(S, fr, G, bad);
+}
+
+// From a float64 window one loop over all points with all 66 weights is faster than the
+// groups: the FMAs are a third of the multi-part ones, and the grouped loops' scattered
+// weight loads from constant memory cost more than the zeros they skip.
 __device__ __forceinline__ void accumulate_all3_dbl(const long long* S, const TapFrame<3>& fr,
                                                     double (&G)[1][bsf_tables::kMono3]) {
     using T = Tab<3>;
