@@ -399,35 +399,66 @@ __device__ __forceinline__ void accumulate_chunk(const long long* S, const TapFr
 // Order 3: the same accumulation as runtime loops over the 36 representative stencil
 // points (fully unrolled, order 3 would be tens of thousands of instructions per variant,
 // and its table values up to 6e7 do not fit the literal forms of the FMA, so each would
-// first be built in registers).  The table, in constant memory, is laid out by
-// representative: its offsets, its mirror's, and its 66 weights.  From a float64 window
-// (one part) all 66 coefficient sums are formed in one pass, so the stencil is read once
-// per tap.  With three exact parts the sums are formed in two passes over u1-chunks (84
-// and 114 accumulators), and the points come in groups with a common set of nonzero
-// columns (rep3_groups.h), each group with its own loop whose body touches only those
-// columns (1,882 FMAs per part and tap instead of 2,376).
-struct Rep3 {
-    int jx, jy, mjx, mjy, self;
-    double w[bsf_tables::kMono3];
+// first be built in registers).  The points come in four groups with a common set of
+// nonzero weight columns (rep3_groups.h); each group has a table in constant memory laid
+// out by point -- its offsets, its mirror's, and only the group's weights, contiguous, so
+// the weight loads merge -- and a loop whose body touches only those columns: 1,882 FMAs
+// per part and tap instead of 2,376.  From a float64 window (one part) all 66 coefficient
+// sums are formed in one pass, so the stencil is read once per tap; with three exact parts
+// they are formed in two passes over u1-chunks (84 and 114 accumulators).
+__host__ __device__ constexpr int rep3_ncols(int grp) {
+    int n = 0;
+    for (int m = 0; m < bsf_tables::kMono3; ++m) n += bsf_tables::kRep3Cols[grp][m] ? 1 : 0;
+    return n;
+}
+__host__ __device__ constexpr int rep3_col_at(int grp, int i) {  // i-th column of the group
+    for (int m = 0; m < bsf_tables::kMono3; ++m)
+        if (bsf_tables::kRep3Cols[grp][m] && i-- == 0) return m;
+    return -1;
+}
+template <int GRP>
+struct Rep3ColMap {  // the group's columns in order
+    int c[rep3_ncols(GRP)];
+    constexpr Rep3ColMap() : c() {
+        for (int i = 0; i < rep3_ncols(GRP); ++i) c[i] = rep3_col_at(GRP, i);
+    }
 };
-struct Rep3Table {
-    static constexpr int R = (bsf_tables::kStencil3 + 9) / 2;  // 9 self-mirrored points (jy = 0)
-    Rep3 r[R];
-    constexpr Rep3Table() : r() {
-        for (int k = 0; k < R; ++k) {  // in the order of the groups
-            const int j = bsf_tables::kRep3Points[k];
+template <int GRP>
+struct Rep3Compact {
+    static constexpr int NC = rep3_ncols(GRP);
+    struct Pt {
+        int jx, jy, mjx, mjy, self;
+        double w[NC];
+    };
+    Pt r[bsf_tables::kRep3GroupSize[GRP]];
+    constexpr Rep3Compact() : r() {
+        int b = 0;
+        for (int h = 0; h < GRP; ++h) b += bsf_tables::kRep3GroupSize[h];
+        for (int k = 0; k < bsf_tables::kRep3GroupSize[GRP]; ++k) {
+            const int j = bsf_tables::kRep3Points[b + k];
             const int jm = mirror_of<3>(j);
-            Rep3& q = r[k];
+            Pt& q = r[k];
             q.jx = bsf_tables::kJ3[j][0];
             q.jy = bsf_tables::kJ3[j][1];
             q.mjx = bsf_tables::kJ3[jm][0];
             q.mjy = bsf_tables::kJ3[jm][1];
             q.self = jm == j;
-            for (int m = 0; m < bsf_tables::kMono3; ++m) q.w[m] = bsf_tables::kNum3[j][m];
+            for (int i = 0; i < NC; ++i) q.w[i] = bsf_tables::kNum3[j][rep3_col_at(GRP, i)];
         }
     }
 };
-__constant__ Rep3Table c_rep3 = Rep3Table();
+__constant__ Rep3Compact<0> c_rep3g0 = Rep3Compact<0>();
+__constant__ Rep3Compact<1> c_rep3g1 = Rep3Compact<1>();
+__constant__ Rep3Compact<2> c_rep3g2 = Rep3Compact<2>();
+__constant__ Rep3Compact<3> c_rep3g3 = Rep3Compact<3>();
+static_assert(bsf_tables::kRep3Groups == 4, "one compact table per group");
+template <int GRP>
+__device__ __forceinline__ const Rep3Compact<GRP>& rep3_compact() {
+    if constexpr (GRP == 0) return c_rep3g0;
+    else if constexpr (GRP == 1) return c_rep3g1;
+    else if constexpr (GRP == 2) return c_rep3g2;
+    else return c_rep3g3;
+}
 
 __host__ __device__ constexpr int rep3_begin(int grp) {
     int b = 0;
@@ -447,7 +478,7 @@ __host__ __device__ constexpr bool rep3_groups_ok() {  // every point a represen
         }
     int reps = 0;
     for (int j = 0; j < bsf_tables::kStencil3; ++j) reps += is_rep<3>(j) ? 1 : 0;
-    return reps == Rep3Table::R && rep3_begin(bsf_tables::kRep3Groups) == Rep3Table::R;
+    return reps == (bsf_tables::kStencil3 + 9) / 2 && rep3_begin(bsf_tables::kRep3Groups) == reps;
 }
 static_assert(rep3_groups_ok(), "rep3_groups.h does not match the order-3 table");
 
@@ -455,10 +486,13 @@ template <int GRP, int SRC, int PARTS, int SHIFT, int M0, int CM>
 __device__ __forceinline__ void accumulate_group3(const long long* S, const TapFrame<3>& fr, double (&G)[PARTS][CM],
                                                   unsigned& bad) {
     using T = Tab<3>;
+    constexpr int NC = Rep3Compact<GRP>::NC;
+    constexpr Rep3ColMap<GRP> cols{};
+    const auto& tab = rep3_compact<GRP>();
     const double* Sd = reinterpret_cast<const double*>(S);
 #pragma unroll 1
-    for (int k = rep3_begin(GRP); k < rep3_begin(GRP + 1); ++k) {
-        const Rep3& q = c_rep3.r[k];
+    for (int k = 0; k < bsf_tables::kRep3GroupSize[GRP]; ++k) {
+        const auto& q = tab.r[k];
         const int o1 = fr.base + q.jx * fr.s1 + q.jy * fr.s2, o2 = fr.base + q.mjx * fr.s1 + q.mjy * fr.s2;
         double xs[PARTS], xd[PARTS];
         if constexpr (SRC == SRC_DBL) {
@@ -471,11 +505,12 @@ __device__ __forceinline__ void accumulate_group3(const long long* S, const TapF
             split_int<PARTS, SHIFT>(sub_ovf(g1, g2, bad), xd);
         }
 #pragma unroll
-        for (int c = 0; c < CM; ++c) {
-            if (!rep3_col(GRP, M0 + c)) continue;
-            const double w = q.w[M0 + c];
+        for (int i = 0; i < NC; ++i) {
+            const int c = cols.c[i];
+            if (c < M0 || c >= M0 + CM) continue;
 #pragma unroll
-            for (int p = 0; p < PARTS; ++p) G[p][c] = __fma_rn(w, (T::mb(M0 + c) & 1) ? xd[p] : xs[p], G[p][c]);
+            for (int p = 0; p < PARTS; ++p)
+                G[p][c - M0] = __fma_rn(q.w[i], (T::mb(c) & 1) ? xd[p] : xs[p], G[p][c - M0]);
         }
     }
     if constexpr (GRP + 1 < bsf_tables::kRep3Groups)
@@ -497,24 +532,13 @@ __device__ __forceinline__ void accumulate_chunk3(const long long* S, const TapF
     accumulate_group3<0, SRC, PARTS, SHIFT, M0, CM>(S, fr, G, bad);
 }
 
-// From a float64 window one loop over all points with all 66 weights is faster than the
-// groups: the FMAs are a third of the multi-part ones, and the grouped loops' scattered
-// weight loads from constant memory cost more than the zeros they skip.
 __device__ __forceinline__ void accumulate_all3_dbl(const long long* S, const TapFrame<3>& fr,
                                                     double (&G)[1][bsf_tables::kMono3]) {
     using T = Tab<3>;
-    const double* Sd = reinterpret_cast<const double*>(S);
 #pragma unroll
     for (int c = 0; c < T::M; ++c) G[0][c] = 0.0;
-#pragma unroll 1
-    for (int k = 0; k < Rep3Table::R; ++k) {
-        const Rep3& q = c_rep3.r[k];
-        const double g1 = Sd[fr.base + q.jx * fr.s1 + q.jy * fr.s2];
-        const double g2 = q.self ? 0.0 : Sd[fr.base + q.mjx * fr.s1 + q.mjy * fr.s2];
-        const double xs = g1 + g2, xd = g1 - g2;  // exact: window values below 2^exact_bits
-#pragma unroll
-        for (int c = 0; c < T::M; ++c) G[0][c] = __fma_rn(q.w[c], (T::mb(c) & 1) ? xd : xs, G[0][c]);
-    }
+    unsigned unused = 0;
+    accumulate_group3<0, SRC_DBL, 1, 0, 0, T::M>(S, fr, G, unused);
 }
 
 // Horner over the chunk's u1-powers AHI..ALO (compensated), continuing the running value P.

@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 import subprocess
+import sys
 
 import numpy as np
 import pytest
@@ -86,3 +87,12 @@ def test_admission_is_fifo_by_footprint_and_slots():
     adm2 = Admission(budget_bytes=10 ** 9, slots=2)
     pend = collections.deque([1, 1, 1])
     assert len(adm2.admit(pend, 8, footprint=lambda r: r)) == 2  # slot limit
+
+
+def test_rep3_groups_header_is_current(tmp_path):
+    """rep3_groups.h is what gen_rep_groups.py writes from the committed order-3 table."""
+    csrc = os.path.join(ROOT, "paper_0908_3861_amd", "csrc")
+    out = tmp_path / "rep3_groups.h"
+    subprocess.run([sys.executable, os.path.join(csrc, "gen_rep_groups.py"), "--out", str(out)], check=True,
+                   capture_output=True)
+    assert out.read_text() == open(os.path.join(csrc, "rep3_groups.h")).read()
