@@ -482,17 +482,30 @@ __host__ __device__ constexpr bool rep3_groups_ok() {  // every point a represen
 }
 static_assert(rep3_groups_ok(), "rep3_groups.h does not match the order-3 table");
 
+// The address of a group table as an opaque wave-uniform value in the constant address
+// space: accessed through the symbol, every 16-dword weight load rebuilt the address from
+// the program counter and the relocation (five scalar instructions per eight FMAs); from
+// a base register the loads take immediate offsets.
+template <int GRP>
+__device__ __forceinline__ const __attribute__((address_space(4))) typename Rep3Compact<GRP>::Pt* rep3_points() {
+    const unsigned long long a = reinterpret_cast<unsigned long long>(static_cast<const void*>(&rep3_compact<GRP>()));
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)a);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(a >> 32));
+    return reinterpret_cast<const __attribute__((address_space(4))) typename Rep3Compact<GRP>::Pt*>(
+        ((unsigned long long)hi << 32) | lo);
+}
+
 template <int GRP, int SRC, int PARTS, int SHIFT, int M0, int CM>
 __device__ __forceinline__ void accumulate_group3(const long long* S, const TapFrame<3>& fr, double (&G)[PARTS][CM],
                                                   unsigned& bad) {
     using T = Tab<3>;
     constexpr int NC = Rep3Compact<GRP>::NC;
     constexpr Rep3ColMap<GRP> cols{};
-    const auto& tab = rep3_compact<GRP>();
+    const auto* pts = rep3_points<GRP>();
     const double* Sd = reinterpret_cast<const double*>(S);
 #pragma unroll 1
     for (int k = 0; k < bsf_tables::kRep3GroupSize[GRP]; ++k) {
-        const auto& q = tab.r[k];
+        const auto& q = pts[k];
         const int o1 = fr.base + q.jx * fr.s1 + q.jy * fr.s2, o2 = fr.base + q.mjx * fr.s1 + q.mjy * fr.s2;
         double xs[PARTS], xd[PARTS];
         if constexpr (SRC == SRC_DBL) {
