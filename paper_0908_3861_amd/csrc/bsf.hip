@@ -506,7 +506,10 @@ __device__ __forceinline__ void accumulate_group3(const long long* S, const TapF
 #pragma unroll 1
     for (int k = 0; k < bsf_tables::kRep3GroupSize[GRP]; ++k) {
         const auto& q = pts[k];
-        const int o1 = fr.base + q.jx * fr.s1 + q.jy * fr.s2, o2 = fr.base + q.mjx * fr.s1 + q.mjy * fr.s2;
+        // |j| <= 3 and |s| <= wq < 2^23: the 24-bit multiply (full rate; the 32-bit one is
+        // quarter rate) is exact
+        const int o1 = fr.base + __mul24(q.jx, fr.s1) + __mul24(q.jy, fr.s2);
+        const int o2 = fr.base + __mul24(q.mjx, fr.s1) + __mul24(q.mjy, fr.s2);
         double xs[PARTS], xd[PARTS];
         if constexpr (SRC == SRC_DBL) {
             const double g1 = Sd[o1], g2 = q.self ? 0.0 : Sd[o2];
