@@ -886,48 +886,56 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
-// One input sample under the boundary rule, as a double (exact for u8, f32 and f64).
-__device__ __forceinline__ double load_sample(const JobDesc A, int x, int y) {
-    if (A.border == BSF_BORDER_ZERO) {
-        if (x < 0 || x >= A.width || y < 0 || y >= A.height) return 0.0;
-    } else {
-        x = clampi(x, 0, A.width - 1);
-        y = clampi(y, 0, A.height - 1);
-    }
-    const long long off = (long long)y * A.in_pitch + x;
-    if (A.in_dtype == BSF_U8) return (double)((const unsigned char*)A.in)[off];
-    if (A.in_dtype == BSF_F32) return (double)((const float*)A.in)[off];
-    return ((const double*)A.in)[off];
+// One input sample of type DT under the boundary rule, branch-free (the coordinates are
+// clamped; a zero border selects 0 afterwards), so that a run of these loads can all be
+// in flight at once.
+template <int DT>
+__device__ __forceinline__ double sample_at(const JobDesc& A, int x, int y) {
+    const bool out = x < 0 || x >= A.width || y < 0 || y >= A.height;
+    const long long off = (long long)clampi(y, 0, A.height - 1) * A.in_pitch + clampi(x, 0, A.width - 1);
+    double v;
+    if constexpr (DT == BSF_U8) v = (double)((const unsigned char*)A.in)[off];
+    else if constexpr (DT == BSF_F32) v = (double)((const float*)A.in)[off];
+    else v = ((const double*)A.in)[off];
+    return (out && A.border == BSF_BORDER_ZERO) ? 0.0 : v;
+}
+__device__ __forceinline__ long long sample_u8(const JobDesc& A, int x, int y) {
+    const bool out = x < 0 || x >= A.width || y < 0 || y >= A.height;
+    const long long off = (long long)clampi(y, 0, A.height - 1) * A.in_pitch + clampi(x, 0, A.width - 1);
+    const long long v = ((const unsigned char*)A.in)[off];
+    return (out && A.border == BSF_BORDER_ZERO) ? 0ll : v;
 }
 
-// One input sample as an exact integer v * 2^sh (u8 samples are integers already).
-__device__ __forceinline__ long long load_sample_int(const JobDesc A, int x, int y, int sh) {
-    if (A.in_dtype == BSF_U8) {
-        if (A.border == BSF_BORDER_ZERO) {
-            if (x < 0 || x >= A.width || y < 0 || y >= A.height) return 0;
-        } else {
-            x = clampi(x, 0, A.width - 1);
-            y = clampi(y, 0, A.height - 1);
-        }
-        return (long long)((const unsigned char*)A.in)[(long long)y * A.in_pitch + x];
-    }
-    return (long long)rint(ldexp(load_sample(A, x, y), sh));
-}
-
-// Visits the box elements i = tid, tid + nt, ... of a (wq x hq) window as (i, r, c)
-// without a division per element.
+// Calls f with the sample type as a compile-time constant.
 template <typename F>
-__device__ __forceinline__ void for_box(const Geo& g, int tid, int nt, F f) {
-    int r = tid / g.wq, c = tid - r * g.wq;
+__device__ __forceinline__ void with_dtype(int dt, F f) {
+    if (dt == BSF_U8) f(std::integral_constant<int, BSF_U8>());
+    else if (dt == BSF_F32) f(std::integral_constant<int, BSF_F32>());
+    else f(std::integral_constant<int, BSF_F64>());
+}
+
+// The box elements i = tid, tid + nt, ... of a window, BATCH loads per thread in flight
+// together: load(r, c) for all slots of a batch first (a slot past the end of the box
+// loads a valid element and is dropped), then visit(i, value).  No division per element.
+template <typename T, int BATCH = 8, typename Load, typename Visit>
+__device__ __forceinline__ void load_box(const Geo& g, int tid, int nt, Load load, Visit visit) {
     const int sr = nt / g.wq, sc = nt - sr * g.wq;
-    for (int i = tid; i < g.qn; i += nt) {
-        f(i, r, c);
-        c += sc;
-        r += sr;
-        if (c >= g.wq) {
-            c -= g.wq;
-            ++r;
+    int r = tid / g.wq, c = tid - r * g.wq;
+    for (int i0 = tid; i0 < g.qn; i0 += BATCH * nt) {
+        T v[BATCH];
+#pragma unroll
+        for (int b = 0; b < BATCH; ++b) {
+            v[b] = load(min(r, g.hq - 1), c);
+            c += sc;
+            r += sr;
+            if (c >= g.wq) {
+                c -= g.wq;
+                ++r;
+            }
         }
+#pragma unroll
+        for (int b = 0; b < BATCH; ++b)
+            if (i0 + b * nt < g.qn) visit(i0 + b * nt, v[b]);
     }
 }
 
@@ -1084,7 +1092,11 @@ __device__ __forceinline__ void process_tile(const JobDesc A, int job, int tile,
         // are), the mesh in float64 from the window as it stands -- no integer grid, no
         // digits.  The error is the mesh's cancellation times a few float64 roundings.
         double* Sd = reinterpret_cast<double*>(S);
-        for_box(g, tid, NT, [&](int i, int r, int c) { Sd[i] = load_sample(A, w.x0 + c, w.y0 + r); });
+        with_dtype(A.in_dtype, [&](auto dt) {
+            constexpr int DT = decltype(dt)::value;
+            load_box<double>(g, tid, NT, [&](int r, int c) { return sample_at<DT>(A, w.x0 + c, w.y0 + r); },
+                             [&](int i, double v) { Sd[i] = v; });
+        });
         for (int i = tid; i < ntri; i += NT) Sd[g.qn + i] = 0.0;
         __syncthreads();
         unsigned unused = 0;
@@ -1123,12 +1135,18 @@ __device__ __forceinline__ void process_tile(const JobDesc A, int job, int tile,
     //    (u8 samples: integers below 2^8, no scan)
     int top = A.in_dtype == BSF_U8 ? 8 : -1100, fine = 0;
     if (A.in_dtype != BSF_U8)
-        for_box(g, tid, NT, [&](int i, int r, int c) {
-            int t_, f_;
-            sample_grid(load_sample(A, w.x0 + c, w.y0 + r), t_, f_);
-            top = max(top, t_);
-            fine = max(fine, f_);
-        });
+        load_box<double, 1>(
+            g, tid, NT,
+            [&](int r, int c) {
+                return A.in_dtype == BSF_F32 ? sample_at<BSF_F32>(A, w.x0 + c, w.y0 + r)
+                                             : sample_at<BSF_F64>(A, w.x0 + c, w.y0 + r);
+            },
+            [&](int, double v) {
+                int t_, f_;
+                sample_grid(v, t_, f_);
+                top = max(top, t_);
+                fine = max(fine, f_);
+            });
     top = wave_max_i(top);
     fine = wave_max_i(fine);
     __syncthreads();
@@ -1160,9 +1178,21 @@ __device__ __forceinline__ void process_tile(const JobDesc A, int job, int tile,
         bool overflowed = false;
         for (int k = 0; k < K; ++k) {
             __syncthreads();  // the previous digit's mesh has finished reading the window
-            for_box(g, tid, NT, [&](int i, int r, int c) {
-                S[i] = digit(load_sample_int(A, w.x0 + c, w.y0 + r, sh), k, K, B);
-            });
+            // (u8 samples four loads in flight per thread; the other types one at a time: the
+            // kernel is at its register cap, and wider batches or one copy per type spilled)
+            if (A.in_dtype == BSF_U8)
+                load_box<long long, 4>(
+                    g, tid, NT, [&](int r, int c) { return sample_u8(A, w.x0 + c, w.y0 + r); },
+                    [&](int i, long long v) { S[i] = digit(v, k, K, B); });
+            else
+                load_box<long long, 1>(
+                    g, tid, NT,
+                    [&](int r, int c) {
+                        const double v = A.in_dtype == BSF_F32 ? sample_at<BSF_F32>(A, w.x0 + c, w.y0 + r)
+                                                               : sample_at<BSF_F64>(A, w.x0 + c, w.y0 + r);
+                        return (long long)rint(ldexp(v, sh));
+                    },
+                    [&](int i, long long v) { S[i] = digit(v, k, K, B); });
             for (int i = tid; i < ntri; i += NT) S[g.qn + i] = 0;
             __syncthreads();
             unsigned ovf = 0;
