@@ -8,7 +8,8 @@ path.  Inputs are resident in HBM before timing starts.  Prints one JSON line wi
 Mpixel/s, the roofline of the filter call (HIP events on its launch stream) and the CPU
 oracle timed on a bounded pixel sample.
 
-Other forms (not run by default): --workload small | precision | batched | serving.
+Other forms (not run by default): --workload small | precision | batched | serving | stage1 |
+ellipse (the scale field of elliptical windows, the step before the filter).
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu-baseline]
 """
@@ -375,6 +376,84 @@ def workload_stage1(args):
     return record(r["Mpixel_per_s"], wall, args.steps, args.warmup, "int64", config, roof, None, r)
 
 
+def time_queued(launch, reps: int, stream) -> float:
+    """Device milliseconds per launch of a short kernel: the launches are queued behind a
+    spin kernel, so the GPU runs them back to back between the two events (events around
+    each launch would time the host's launch overhead too)."""
+    import torch
+    torch.cuda.synchronize()
+    torch.cuda._sleep(50_000_000)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        launch()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def workload_ellipse(args):
+    """The scale field of elliptical windows (bsf_scales_from_ellipses), the step before
+    the filter: 12 B read and 16 B written per pixel, bound by HBM."""
+    import torch
+    from paper_0908_3861_amd import binding
+    import oracle.ellipse as OE
+    H = W = args.size
+    rng = np.random.default_rng(synth.CONFIGS["ellipse"]["seed"])
+    ell_np = synth.ellipse_field(rng, H, W)
+    dev = torch.device("cuda:0")
+    ell = torch.from_numpy(ell_np).to(dev)
+    out = torch.empty((H, W, 4), dtype=torch.float32, device=dev)
+    ctx = binding.default_context(0)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        binding.scales_from_ellipses(ell, 2, out=out, ctx=ctx, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    reps = max(args.steps, 1)
+    t0 = time.perf_counter()
+    ms = time_queued(step, reps, stream)
+    wall = time.perf_counter() - t0
+    ctx.check_device()
+    if args.copy_probe_mib:  # a plain device copy of known size, for scaling the byte counters
+        src = torch.ones(args.copy_probe_mib << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+    P = H * W
+    alg = P * (12 + 16)
+    key = kernel_source_key()
+    roof = {"bound": "hbm", "achieved": alg / (ms * 1e-3) / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+            "frac": alg / (ms * 1e-3) / PEAK_HBM, "traffic": MEASURED_TRAFFIC.get(key, {}).get(("ellipse", "f32"))}
+    extra = {"kernel_ms": ms, "algorithmic_bytes": alg}
+    cpu = None
+    if not args.no_cpu_baseline:
+        g = out.cpu().numpy().reshape(-1, 4).astype(np.float64)
+        pr = np.random.default_rng(12346)
+        probe = pr.choice(P, size=16, replace=False)
+        t0 = time.perf_counter()
+        OE.scales_from_ellipses(ell_np.reshape(-1, 3)[probe], 2)
+        tp = max(time.perf_counter() - t0, 1e-3)
+        count = int(min(P, max(32, 16 * args.cpu_seconds / tp)))
+        pix = np.sort(pr.choice(P, size=count, replace=False))
+        t0 = time.perf_counter()
+        ref = OE.scales_from_ellipses(ell_np.reshape(-1, 3)[pix], 2)
+        tc = time.perf_counter() - t0
+        ref32 = ref.astype(np.float32).astype(np.float64)
+        extra["err_vs_oracle"] = {"max_ulp32": float(np.max(np.abs(g[pix] - ref32) / (np.abs(ref32) * 2.0 ** -23))),
+                                  "compared": int(count)}
+        cpu = {"value": count / tc / 1e6, "unit": "Mpixel/s", "cores": 1, "kind": "oracle",
+               "sample": f"{count} random pixels of the same {W}x{H} field (brute-force active sets, numpy, "
+                         f"one thread), {tc:.1f} s"}
+    config = {"workload": f"ellipse: {W}x{H} field of (s_major in [1,8], elongation in [1,4], orientation in "
+                          f"[0,pi)), smooth sigma=32 fields -> order-2 scales", "pixels": P, "order": 2}
+    extra["wall_s"] = wall
+    return record(P / (ms * 1e-3) / 1e6, ms * 1e-3 * reps, reps, args.warmup, "f64-compute/f32-io", config, roof,
+                  cpu, extra)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -385,7 +464,7 @@ def main():
     ap.add_argument("--path", default="f64", choices=["f64", "f32tiled"])
     ap.add_argument("--size", type=int, default=2048)
     ap.add_argument("--workload", default="plain",
-                    choices=["plain", "small", "precision", "batched", "serving", "stage1"])
+                    choices=["plain", "small", "precision", "batched", "serving", "stage1", "ellipse"])
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--duration", type=float, default=60.0)
     ap.add_argument("--rate", type=float, default=0.0)
@@ -400,7 +479,8 @@ def main():
               "every workload here fits one MI355X.", file=sys.stderr)
         sys.exit(2)
     fn = {"plain": workload_plain, "small": workload_small, "precision": workload_precision,
-          "batched": workload_batched, "serving": workload_serving, "stage1": workload_stage1}[args.workload]
+          "batched": workload_batched, "serving": workload_serving, "stage1": workload_stage1,
+          "ellipse": workload_ellipse}[args.workload]
     print(json.dumps(fn(args)), flush=True)
 
 

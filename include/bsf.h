@@ -128,6 +128,24 @@ bsf_status bsf_preintegrate(bsf_ctx* ctx, const bsf_job* job, int x0, int y0, in
  * order that occurred). */
 bsf_status bsf_get_device_error(bsf_ctx* ctx, void* stream);
 
+/* Scale field of elliptical windows (the step before the filter; the paper controls each
+ * window through the box spline's covariance, Section 4, and leaves this map open).
+ * For every pixel, ellipses[3*(y*ellipse_pitch + x) + {0,1,2}] = (s_major, s_minor, phi):
+ * the standard deviations of the window along its two axes, in pixels, and the angle of
+ * the first axis from the first lattice axis (x, columns) toward the second (y, rows), in
+ * radians.  scales[4*(y*scale_pitch + x) + k] receives a_(k+1): the scales whose order-n
+ * box spline has the covariance (n/12) sum_k a_k^2 r_k r_k^T closest in the Frobenius norm
+ * to R(phi) diag(s_major^2, s_minor^2) R(phi)^T, with every a_k >= 0.5 (the filter's
+ * smallest scale) and the least sum a_k^4 among equally close ones; an isotropic window
+ * of deviation sigma gets a_k = sigma sqrt(6/n) (Theorem 4.3's scales).  Elongated windows
+ * between the lattice directions are not reachable exactly and get the closest
+ * covariance.  The output is the filter's scale format (bsf_job.scales).  Both buffers
+ * are device memory owned by the caller; pitches count pixels; scales must be 16-byte
+ * aligned.  Non-finite or non-positive deviations give NaN scales and the sticky
+ * BSF_ERR_SCALE_RANGE flag.  Asynchronous on `stream`. */
+bsf_status bsf_scales_from_ellipses(bsf_ctx* ctx, const float* ellipses, ptrdiff_t ellipse_pitch, int width,
+                                    int height, int order, float* scales, ptrdiff_t scale_pitch, void* stream);
+
 /* Evaluation counters of the float64 path (Section 7 mesh, eq. final_eqn), kept per
  * context since its creation or the last reset.  A tile whose samples need a single
  * digit evaluates each tap's interpolant with the terms of total degree above 2 (order

@@ -60,13 +60,15 @@ def load():
             lib.bsf_preintegrate.argtypes = [vp, jp, i, i, i, i, vp, ctypes.c_ssize_t, vp]
             lib.bsf_get_device_error.argtypes = [vp, vp]
             lib.bsf_get_counters.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_ulonglong), i]
+            lib.bsf_scales_from_ellipses.argtypes = [vp, vp, ctypes.c_ssize_t, i, i, i, vp, ctypes.c_ssize_t, vp]
             lib.bsf_status_string.argtypes = [i]
             lib.bsf_status_string.restype = ctypes.c_char_p
             lib.bsf_last_error.argtypes = [vp]
             lib.bsf_last_error.restype = ctypes.c_char_p
             lib.bsf_debug_tile_window.argtypes = [vp, jp, i, vp, ctypes.c_longlong, vp, vp]
             for fn in ("bsf_create", "bsf_destroy", "bsf_workspace_size", "bsf_filter", "bsf_filter_batched",
-                       "bsf_preintegrate", "bsf_get_device_error", "bsf_get_counters", "bsf_debug_tile_window"):
+                       "bsf_preintegrate", "bsf_get_device_error", "bsf_get_counters", "bsf_scales_from_ellipses",
+                       "bsf_debug_tile_window"):
                 getattr(lib, fn).restype = i
             _lib = lib
     return _lib
@@ -220,6 +222,27 @@ def filter_batched(items, ctx: Context | None = None, stream=None, check: bool =
     if check:
         ctx.check_device(stream)
     return outs
+
+
+def scales_from_ellipses(ell, order: int, out=None, ctx: Context | None = None, stream=None):
+    """[H, W, 3] float32 device tensor of (s_major, s_minor, phi) -> [H, W, 4] float32 scales
+    for an order-`order` filter (bsf_scales_from_ellipses).  Rows may be padded (views)."""
+    import torch
+    ctx = ctx or default_context(ell.device.index)
+    if ell.dtype != torch.float32 or ell.dim() != 3 or ell.shape[2] != 3 or ell.stride(2) != 1 or ell.stride(1) != 3:
+        raise ValueError("ellipses must be a float32 [H, W, 3] tensor with contiguous pixels")
+    if ell.stride(0) % 3:
+        raise ValueError("the row pitch of the ellipses must be a whole number of pixels")
+    H, W, _ = ell.shape
+    if out is None:
+        with _on(stream):
+            out = torch.empty((H, W, 4), dtype=torch.float32, device=ell.device)
+    if out.shape != (H, W, 4) or out.dtype != torch.float32 or out.stride(2) != 1 or out.stride(1) != 4 \
+            or out.stride(0) % 4:
+        raise ValueError("out must be a float32 [H, W, 4] tensor with contiguous pixels")
+    ctx._check(ctx.lib.bsf_scales_from_ellipses(ctx.handle, ell.data_ptr(), ell.stride(0) // 3, W, H, int(order),
+                                                out.data_ptr(), out.stride(0) // 4, _stream_ptr(stream)))
+    return out
 
 
 def preintegrate(img, order: int, x0: int, y0: int, wq: int, hq: int, border: str = "clamp",

@@ -1679,6 +1679,75 @@ void launch_global(const GlobalArgs& A, hipStream_t st) {
     hipLaunchKernelGGL((gpre_pass<N, 4, unsigned char>), dim3(nc), dim3(64), 0, st, A, nc);
 }
 
+// ---------------------------------------------------------------------------
+// Scale field of elliptical windows.  The order-n box spline with scales a has the
+// covariance (n/12) sum_k a_k^2 r_k r_k^T (each segment of length a_k along r_k is a
+// uniform density of variance a_k^2/12; Section 4); the scales of a pixel are those whose
+// covariance is closest in the Frobenius norm to the ellipse's R diag(s1^2, s2^2) R^T,
+// with a_k >= kScaleMin and the least sum a_k^4 among ties (isotropic ellipses give the
+// scales of Theorem 4.3).  In the units S = (12/n) Sigma and with w = a^2 the model is
+//   [[w1 + t, d], [d, w3 + t]],  t = (w2 + w4)/2,  d = (w2 - w4)/2,
+// so with lb = kScaleMin^2, q = |S_xy| and m <= M the two diagonal entries minus 2 lb:
+// * q <= m: exact, t in [lb + q, lb + m], the least sum of squares at t = (Sxx + Syy)/4;
+// * else the closest: t = lb + u, |d| = u (one of w2, w4 at the bound), u >= 0 minimising
+//   max(0, u - m)^2 + max(0, u - M)^2 + 2 (u - q)^2, i.e. (m + 2q)/3 up to M, else
+//   (m + M + 2q)/4; then w1 = max(lb, Sxx - t), w3 = max(lb, Syy - t).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float4 ellipse_scales(float s1, float s2, float ph, int n) {
+    const double v1 = (double)s1 * s1, v2 = (double)s2 * s2;
+    double sn, cs;
+    sincos(2.0 * (double)ph, &sn, &cs);
+    const double k = 12.0 / n, hs = 0.5 * (v1 + v2), hd = 0.5 * (v1 - v2);
+    const double Sxx = k * (hs + hd * cs), Syy = k * (hs - hd * cs), Sxy = k * hd * sn;
+    const double lb = kScaleMin * kScaleMin;
+    const double q = fabs(Sxy), A = Sxx - 2.0 * lb, B = Syy - 2.0 * lb;
+    const double m = fmin(A, B), M = fmax(A, B);
+    double t, d;
+    if (q <= m) {
+        t = fmin(fmax(0.25 * (Sxx + Syy), lb + q), lb + m);
+        d = Sxy;
+    } else {
+        double u = (m + 2.0 * q) / 3.0;
+        if (u > M) u = 0.25 * (m + M + 2.0 * q);
+        u = fmax(u, 0.0);
+        t = lb + u;
+        d = copysign(u, Sxy);
+    }
+    const double w1 = fmax(lb, Sxx - t), w2 = fmax(lb, t + d), w3 = fmax(lb, Syy - t), w4 = fmax(lb, t - d);
+    return make_float4((float)sqrt(w1), (float)sqrt(w2), (float)sqrt(w3), (float)sqrt(w4));
+}
+
+// Two adjacent pixels per thread (two independent float64 chains in flight); a block
+// covers 512 consecutive pixels of one row.
+__global__ __launch_bounds__(256) void ellipse_scales_kernel(const float* __restrict__ ell, long long ell_pitch, int width,
+                                                             int blocks_per_row, int n, float* __restrict__ scales,
+                                                             long long scale_pitch, unsigned* err) {
+    const int y = blockIdx.x / blocks_per_row;
+    const int x0 = (blockIdx.x - y * blocks_per_row) * 512 + 2 * threadIdx.x;
+    bool bad = false;
+    if (x0 < width) {
+        const float* e = ell + 3 * ((long long)y * ell_pitch + x0);
+        float* o = scales + 4 * ((long long)y * scale_pitch + x0);
+        const bool two = x0 + 1 < width;
+        float v[6];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) v[i] = e[i];
+#pragma unroll
+        for (int i = 3; i < 6; ++i) v[i] = two ? e[i] : 1.0f;
+        const float nan = __builtin_nanf("");
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            const float s1 = v[3 * p], s2 = v[3 * p + 1], ph = v[3 * p + 2];
+            const bool ok = isfinite(s1) && isfinite(s2) && isfinite(ph) && s1 > 0.f && s2 > 0.f;
+            bad |= !ok;
+            const float4 a = ok ? ellipse_scales(s1, s2, ph, n) : make_float4(nan, nan, nan, nan);
+            if (p == 0 || two) *reinterpret_cast<float4*>(o + 4 * p) = a;
+        }
+    }
+    const unsigned long long b = __ballot(bad);  // one flag per wave
+    if (b && (int)(threadIdx.x & 63) == __ffsll((long long)b) - 1) atomicOr(err, kErrScale);
+}
+
 }  // namespace bsf
 
 // ===========================================================================
@@ -2323,6 +2392,24 @@ bsf_status bsf_get_counters(bsf_ctx* c, void* stream, unsigned long long* out, i
         if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
     }
     if (e != hipSuccess) return hip_fail(c, e, "reading the evaluation counters");
+    return BSF_OK;
+}
+
+bsf_status bsf_scales_from_ellipses(bsf_ctx* c, const float* ellipses, ptrdiff_t ellipse_pitch, int width,
+                                    int height, int order, float* scales, ptrdiff_t scale_pitch, void* stream) {
+    if (!c) return BSF_ERR_INVALID_ARG;
+    if (!ellipses || !scales || width < 1 || height < 1 || ellipse_pitch < width || scale_pitch < width)
+        return fail(c, BSF_ERR_INVALID_ARG, "bad ellipse or scale buffer");
+    if (order < 1 || order > 3) return fail(c, BSF_ERR_INVALID_ARG, "order must be 1, 2 or 3");
+    if ((reinterpret_cast<uintptr_t>(scales) & 15) != 0) return fail(c, BSF_ERR_INVALID_ARG, "scales must be 16-byte aligned");
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+    const int bpr = (width + 511) / 512;
+    if ((long long)bpr * height > 0x7fffffffll) return fail(c, BSF_ERR_INVALID_ARG, "image too large");
+    hipLaunchKernelGGL(bsf::ellipse_scales_kernel, dim3(bpr * height), dim3(256), 0, (hipStream_t)stream, ellipses,
+                       (long long)ellipse_pitch, width, bpr, order, scales, (long long)scale_pitch, c->d_err);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(c, e, "ellipse kernel launch");
     return BSF_OK;
 }
 

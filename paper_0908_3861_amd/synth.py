@@ -91,7 +91,26 @@ CONFIGS = {
                          "scales U{1..8}, orders U{1,2,3}", seed=4),
     "serving": dict(desc="Poisson stream, square sides log-uniform [128,4096], f32/f64 50/50, "
                          "integer scales U{1..8}, orders U{1,2,3}", seed=5),
+    "ellipse": dict(desc="2048x2048 ellipse field: smooth s_major in [1,8], elongation in [1,4], "
+                         "orientation in [0,pi) (sigma=32 fields), order 2", seed=6),
 }
+
+
+def ellipse_field(rng: np.random.Generator, h: int, w: int, s_lo: float = 1.0, s_hi: float = 8.0,
+                  elong_hi: float = 4.0, sigma: float = 32.0) -> np.ndarray:
+    """[h, w, 3] float32 (s_major, s_minor, phi) of an adaptive elliptical filter: three
+    independent smooth fields (U[0,1) noise, Gaussian sigma, wrap, min-max) mapped to
+    s_major in [s_lo, s_hi], elongation s_major/s_minor in [1, elong_hi] and orientation in
+    [0, pi)."""
+    t = []
+    for _ in range(3):
+        b = _gaussian(rng.random((h, w)), sigma, "wrap")
+        t.append((b - b.min()) / max(b.max() - b.min(), 1e-300))
+    out = np.empty((h, w, 3), np.float32)
+    out[..., 0] = s_lo + (s_hi - s_lo) * t[0]
+    out[..., 1] = out[..., 0] / (1.0 + (elong_hi - 1.0) * t[1])
+    out[..., 2] = np.pi * t[2]
+    return out
 
 
 def config_job(name: str, size: tuple[int, int] | None = None, seed: int | None = None) -> Job:
