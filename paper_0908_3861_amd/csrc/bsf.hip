@@ -1714,7 +1714,10 @@ __device__ __forceinline__ float4 ellipse_scales(float s1, float s2, float ph, i
         d = copysign(u, Sxy);
     }
     const double w1 = fmax(lb, Sxx - t), w2 = fmax(lb, t + d), w3 = fmax(lb, Syy - t), w4 = fmax(lb, t - d);
-    return make_float4((float)sqrt(w1), (float)sqrt(w2), (float)sqrt(w3), (float)sqrt(w4));
+    // a = sqrt(w) in float32, correctly rounded from the float32-rounded w: within one float32
+    // ulp of the rounded float64 root (its error is below 0.75 ulp of a), at a fraction of the
+    // float64 square root's cost
+    return make_float4(__fsqrt_rn((float)w1), __fsqrt_rn((float)w2), __fsqrt_rn((float)w3), __fsqrt_rn((float)w4));
 }
 
 // Two adjacent pixels per thread (two independent float64 chains in flight); a block
