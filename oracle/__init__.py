@@ -13,6 +13,9 @@ with the HIP path (``paper_0908_3861_amd``) and never imports it.
   non-negative, so plain float64 is accurate to a few ulps.
 * ``preintegrate(window, n)`` -- stage 1 alone: the recursion of Section 7
   (eq. RS, steps (1)-(4)), n times per direction, unit weights, exact integers.
+
+Sibling modules: ``oracle.ellipse`` (the scale field of elliptical windows) and
+``oracle.filter1d`` (the one-dimensional scale-adaptive filter of Section 3, exact rationals).
 """
 from __future__ import annotations
 
