@@ -146,6 +146,47 @@ bsf_status bsf_get_device_error(bsf_ctx* ctx, void* stream);
 bsf_status bsf_scales_from_ellipses(bsf_ctx* ctx, const float* ellipses, ptrdiff_t ellipse_pitch, int width,
                                     int height, int order, float* scales, ptrdiff_t scale_pitch, void* stream);
 
+/* One-dimensional scale-adaptive filter (Section 3) on a batch of signals.  Sample m of
+ * signal b gets the projection of the signal's continuous model onto the B-spline of degree
+ * order-1 and scale a = scales[b*scale_pitch + m] centred at m (Section 3, the projections
+ * s[m]; eq. definition for the scaled B-spline):
+ *     s[m] = sum_k c_ext[k] (beta^model * beta_a^(order-1))(m - k),
+ * where the model f(x) = sum_k c[k] beta^model(x - k) has degree model = -1 (impulses at the
+ * samples, the model of the two-dimensional filter), 0 or 1 (for these the interpolation
+ * filter is the unit impulse, so c = the samples), and c_ext extends each signal by its end
+ * values (clamp) or zeros.  Computed by Proposition 3.1: order running sums (eq. RS, unit
+ * scale), then per sample the finite-difference mask Delta_a^order (eq. FD) applied to the
+ * running sums interpolated with the B-spline of degree model + order, on restart windows of
+ * 512 outputs.  The running sums, the interpolation and the mask carry a compensation term,
+ * so the result matches the exact projection to a few float64 ulps of its largest terms. */
+typedef struct {
+    int length, count;              /* samples per signal, number of signals (>= 1)       */
+    bsf_dtype in_dtype;             /* u8, f32 or f64                                      */
+    const void* in;                 /* [count][in_pitch] samples                           */
+    ptrdiff_t in_pitch;             /* >= length, in elements                              */
+    const float* scales;            /* [count][scale_pitch] scales a                        */
+    ptrdiff_t scale_pitch;          /* >= length                                           */
+    int order;                      /* number of running sums, 1..3 (B-spline degree + 1)  */
+    int model;                      /* degree of the signal model: -1, 0 or 1              */
+    bsf_border border;
+    float a_max;                    /* upper bound on every scale (sizes the on-chip windows;
+                                       0 = the largest bsf_filter1d_max_scale allows)      */
+    double* out;                    /* [count][out_pitch] float64                          */
+    ptrdiff_t out_pitch;            /* >= length                                           */
+} bsf_job1d;
+
+/* out[b][m] = s[m] of signal b for every sample.  All pointers are device memory owned by
+ * the caller; asynchronous on `stream`; no workspace.  Scales must lie in [0.5, a_max]:
+ * others (NaN included) give NaN outputs and the sticky BSF_ERR_SCALE_RANGE flag
+ * (bsf_get_device_error).  BSF_ERR_UNSUPPORTED, synchronously, if a_max exceeds
+ * bsf_filter1d_max_scale. */
+bsf_status bsf_filter1d(bsf_ctx* ctx, const bsf_job1d* job, void* stream);
+
+/* The largest a_max bsf_filter1d accepts for this order and model (its restart window,
+ * (3 + model + order) * 16 bytes per sample of 512 + about order * a_max samples, must fit
+ * the on-chip memory of one workgroup).  Host only. */
+bsf_status bsf_filter1d_max_scale(bsf_ctx* ctx, int order, int model, float* a_max);
+
 /* Evaluation counters of the float64 path (Section 7 mesh, eq. final_eqn), kept per
  * context since its creation or the last reset.  A tile whose samples need a single
  * digit evaluates each tap's interpolant with the terms of total degree above 2 (order

@@ -39,6 +39,17 @@ class Job(ctypes.Structure):
     ]
 
 
+class Job1d(ctypes.Structure):
+    _fields_ = [
+        ("length", ctypes.c_int), ("count", ctypes.c_int),
+        ("in_dtype", ctypes.c_int), ("in_", ctypes.c_void_p), ("in_pitch", ctypes.c_ssize_t),
+        ("scales", ctypes.c_void_p), ("scale_pitch", ctypes.c_ssize_t),
+        ("order", ctypes.c_int), ("model", ctypes.c_int), ("border", ctypes.c_int),
+        ("a_max", ctypes.c_float),
+        ("out", ctypes.c_void_p), ("out_pitch", ctypes.c_ssize_t),
+    ]
+
+
 _lib = None
 _lock = threading.Lock()
 
@@ -61,6 +72,8 @@ def load():
             lib.bsf_get_device_error.argtypes = [vp, vp]
             lib.bsf_get_counters.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_ulonglong), i]
             lib.bsf_scales_from_ellipses.argtypes = [vp, vp, ctypes.c_ssize_t, i, i, i, vp, ctypes.c_ssize_t, vp]
+            lib.bsf_filter1d.argtypes = [vp, ctypes.POINTER(Job1d), vp]
+            lib.bsf_filter1d_max_scale.argtypes = [vp, i, i, ctypes.POINTER(ctypes.c_float)]
             lib.bsf_status_string.argtypes = [i]
             lib.bsf_status_string.restype = ctypes.c_char_p
             lib.bsf_last_error.argtypes = [vp]
@@ -68,7 +81,7 @@ def load():
             lib.bsf_debug_tile_window.argtypes = [vp, jp, i, vp, ctypes.c_longlong, vp, vp]
             for fn in ("bsf_create", "bsf_destroy", "bsf_workspace_size", "bsf_filter", "bsf_filter_batched",
                        "bsf_preintegrate", "bsf_get_device_error", "bsf_get_counters", "bsf_scales_from_ellipses",
-                       "bsf_debug_tile_window"):
+                       "bsf_debug_tile_window", "bsf_filter1d", "bsf_filter1d_max_scale"):
                 getattr(lib, fn).restype = i
             _lib = lib
     return _lib
@@ -242,6 +255,56 @@ def scales_from_ellipses(ell, order: int, out=None, ctx: Context | None = None, 
         raise ValueError("out must be a float32 [H, W, 4] tensor with contiguous pixels")
     ctx._check(ctx.lib.bsf_scales_from_ellipses(ctx.handle, ell.data_ptr(), ell.stride(0) // 3, W, H, int(order),
                                                 out.data_ptr(), out.stride(0) // 4, _stream_ptr(stream)))
+    return out
+
+
+def filter1d_max_scale(order: int, model: int = -1, ctx: Context | None = None) -> float:
+    """The largest scale bound bsf_filter1d accepts for this order and model."""
+    ctx = ctx or default_context()
+    v = ctypes.c_float()
+    ctx._check(ctx.lib.bsf_filter1d_max_scale(ctx.handle, int(order), int(model), ctypes.byref(v)))
+    return float(v.value)
+
+
+def filter1d(signals, scales, order: int, model: int = -1, border: str = "clamp", a_max: float | None = None,
+             out=None, ctx: Context | None = None, stream=None, check: bool = False):
+    """One-dimensional scale-adaptive filter (bsf_filter1d) of device tensors ``signals``
+    [count, length] (uint8/float32/float64) with per-sample float32 ``scales`` [count, length];
+    returns float64 [count, length].  Rows may be padded (contiguous samples within a row).
+    ``a_max`` defaults to the largest scale (one device reduction and a host sync)."""
+    import torch
+    ctx = ctx or default_context(signals.device.index)
+    if signals.dim() != 2 or scales.dim() != 2 or tuple(scales.shape) != tuple(signals.shape):
+        raise ValueError("expected signals and scales of the same shape [count, length]")
+    if not (signals.is_cuda and scales.is_cuda):
+        raise ValueError("signals and scales must be device tensors")
+    if scales.dtype != torch.float32 or scales.stride(1) != 1 or signals.stride(1) != 1:
+        raise ValueError("scales must be float32; samples within a row must be contiguous")
+    count, length = signals.shape
+    if out is None:
+        with _on(stream):
+            out = torch.empty((count, length), dtype=torch.float64, device=signals.device)
+    elif out.dtype != torch.float64 or tuple(out.shape) != (count, length) or out.stride(1) != 1:
+        raise ValueError("bad output tensor")
+    if a_max is None:
+        with _on(stream):
+            a_max = float(scales.max().item())
+    j = Job1d()
+    j.length, j.count = length, count
+    j.in_dtype = _dtype_code(signals)
+    j.in_ = signals.data_ptr()
+    j.in_pitch = signals.stride(0)
+    j.scales = scales.data_ptr()
+    j.scale_pitch = scales.stride(0)
+    j.order = int(order)
+    j.model = int(model)
+    j.border = BORDERS[border]
+    j.a_max = float(a_max)
+    j.out = out.data_ptr()
+    j.out_pitch = out.stride(0)
+    ctx._check(ctx.lib.bsf_filter1d(ctx.handle, ctypes.byref(j), _stream_ptr(stream)))
+    if check:
+        ctx.check_device(stream)
     return out
 
 

@@ -21,6 +21,7 @@
 
 #include "../../include/bsf.h"
 #include "bsf_device.h"
+#include "filter1d.h"
 #include "rep3_groups.h"
 
 namespace bsf {
@@ -2110,6 +2111,53 @@ hipError_t dispatch_batch_group(const bsf_ctx* c, int v, const JobDesc* djobs, i
 
 }  // namespace
 
+namespace {
+
+template <int N, int D>
+hipError_t launch_filter1d(const bsf::f1d::Args& A, int blocks, long long lds, hipStream_t st) {
+    static bool opted = false;
+    if (!opted) {
+        allow_big_lds(bsf::f1d::filter1d_kernel<N, D>);
+        opted = true;
+    }
+    hipLaunchKernelGGL((bsf::f1d::filter1d_kernel<N, D>), dim3(blocks), dim3(bsf::f1d::kThreads), (size_t)lds, st, A);
+    return hipGetLastError();
+}
+
+hipError_t dispatch_filter1d(int n, int D, const bsf::f1d::Args& A, int blocks, long long lds, hipStream_t st) {
+    switch (n * 8 + D) {
+        case 1 * 8 + 0: return launch_filter1d<1, 0>(A, blocks, lds, st);
+        case 1 * 8 + 1: return launch_filter1d<1, 1>(A, blocks, lds, st);
+        case 1 * 8 + 2: return launch_filter1d<1, 2>(A, blocks, lds, st);
+        case 2 * 8 + 1: return launch_filter1d<2, 1>(A, blocks, lds, st);
+        case 2 * 8 + 2: return launch_filter1d<2, 2>(A, blocks, lds, st);
+        case 2 * 8 + 3: return launch_filter1d<2, 3>(A, blocks, lds, st);
+        case 3 * 8 + 2: return launch_filter1d<3, 2>(A, blocks, lds, st);
+        case 3 * 8 + 3: return launch_filter1d<3, 3>(A, blocks, lds, st);
+        default: return launch_filter1d<3, 4>(A, blocks, lds, st);
+    }
+}
+
+// Largest scale bound whose window fits the LDS a workgroup may hold (0 if none does).
+double filter1d_max_scale(const bsf_ctx* c, int n, int D) {
+    const long long cap = std::min<long long>(c->lds_max_bytes, 163840 - 1024);
+    double lo = 0.0, hi = 1e4;
+    auto fits = [&](double a) {
+        const int W = bsf::f1d::window_len(n, D, a);
+        return W <= bsf::f1d::kThreads * bsf::f1d::kChunkMax && bsf::f1d::lds_bytes(D, W) <= cap;
+    };
+    if (!fits(0.5)) return 0.0;
+    if (fits(hi)) return hi;
+    lo = 0.5;
+    for (int i = 0; i < 60; ++i) {
+        const double mid = 0.5 * (lo + hi);
+        (fits(mid) ? lo : hi) = mid;
+    }
+    return std::floor(lo * 8.0) / 8.0;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* bsf_status_string(bsf_status s) {
@@ -2413,6 +2461,59 @@ bsf_status bsf_scales_from_ellipses(bsf_ctx* c, const float* ellipses, ptrdiff_t
                        (long long)ellipse_pitch, width, bpr, order, scales, (long long)scale_pitch, c->d_err);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(c, e, "ellipse kernel launch");
+    return BSF_OK;
+}
+
+bsf_status bsf_filter1d_max_scale(bsf_ctx* c, int order, int model, float* a_max) {
+    if (!c) return BSF_ERR_INVALID_ARG;
+    if (order < 1 || order > 3 || model < -1 || model > 1 || !a_max)
+        return fail(c, BSF_ERR_INVALID_ARG, "order must be 1..3 and model -1..1");
+    *a_max = (float)filter1d_max_scale(c, order, order + model);
+    return BSF_OK;
+}
+
+bsf_status bsf_filter1d(bsf_ctx* c, const bsf_job1d* j, void* stream) {
+    if (!c) return BSF_ERR_INVALID_ARG;
+    if (!j) return fail(c, BSF_ERR_INVALID_ARG, "job is null");
+    if (j->length < 1 || j->count < 1) return fail(c, BSF_ERR_INVALID_ARG, "length and count must be >= 1");
+    if (!j->in || !j->scales || !j->out) return fail(c, BSF_ERR_INVALID_ARG, "null buffer");
+    if (j->in_pitch < j->length || j->scale_pitch < j->length || j->out_pitch < j->length)
+        return fail(c, BSF_ERR_INVALID_ARG, "pitches must be >= length");
+    if (j->in_dtype != BSF_U8 && j->in_dtype != BSF_F32 && j->in_dtype != BSF_F64)
+        return fail(c, BSF_ERR_INVALID_ARG, "bad input dtype");
+    if (j->border != BSF_BORDER_CLAMP && j->border != BSF_BORDER_ZERO) return fail(c, BSF_ERR_INVALID_ARG, "bad border");
+    if (j->order < 1 || j->order > 3) return fail(c, BSF_ERR_INVALID_ARG, "order must be 1, 2 or 3");
+    if (j->model < -1 || j->model > 1) return fail(c, BSF_ERR_INVALID_ARG, "model degree must be -1, 0 or 1");
+    const int n = j->order, D = j->order + j->model;
+    const double limit = filter1d_max_scale(c, n, D);
+    double a_max = j->a_max;
+    if (!(a_max == 0.0 || (a_max >= 0.5 && a_max <= 1e4)))
+        return fail(c, BSF_ERR_INVALID_ARG, "a_max must be 0 or lie in [0.5, 1e4]");
+    if (a_max == 0.0) a_max = limit;
+    if (a_max > limit)
+        return fail(c, BSF_ERR_UNSUPPORTED, "a_max " + std::to_string(a_max) + " exceeds the largest scale whose window fits on chip (" +
+                                                std::to_string(limit) + ")");
+    const long long tiles = (j->length + bsf::f1d::kT - 1) / bsf::f1d::kT;
+    if (tiles * j->count > 0x7fffffffll) return fail(c, BSF_ERR_INVALID_ARG, "batch too large");
+    bsf::f1d::Args A{};
+    A.in = j->in;
+    A.in_pitch = j->in_pitch;
+    A.scales = j->scales;
+    A.sc_pitch = j->scale_pitch;
+    A.out = j->out;
+    A.out_pitch = j->out_pitch;
+    A.length = j->length;
+    A.tiles = (int)tiles;
+    A.dtype = (int)j->in_dtype;
+    A.border = (int)j->border;
+    A.left = bsf::f1d::window_left(n, D, a_max);
+    A.W = bsf::f1d::window_len(n, D, a_max);
+    A.a_max = (float)a_max;
+    A.err = c->d_err;
+    hipError_t e = hipSetDevice(c->device);
+    if (e == hipSuccess)
+        e = dispatch_filter1d(n, D, A, (int)(tiles * j->count), bsf::f1d::lds_bytes(D, A.W), (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "filter1d launch");
     return BSF_OK;
 }
 

@@ -1,0 +1,243 @@
+// One-dimensional scale-adaptive filter (Section 3, Proposition 3.1) for batches of signals.
+//
+// Every output sample m is the projection of the signal's continuous model onto the
+// B-spline of degree n-1 and scale a[m] centred at m.  The model is
+// f(x) = sum_k c[k] beta^{n1}(x - k) with n1 in {-1, 0, 1} (n1 = -1: impulses at the samples;
+// n1 = 0, 1: the interpolation filter is the unit impulse, c = f).  Proposition 3.1 computes
+// it in two steps:
+//   1. non-adaptive: g = n-fold running sum of c (the filter u_1^n, eq. RS with b = 1);
+//   2. adaptive: F(x) = sum_k g[k] beta^D(x + tau - k) with D = n1 + n, tau = (a-1) n / 2,
+//      and s[m] = Delta_a^n F(m) = a^-n sum_j (-1)^j C(n,j) F(m - a j) (eq. FD).
+//
+// Layout of the work.  A workgroup owns kT consecutive outputs of one signal and runs step 1
+// on a restart window that holds every sample their masks reach: the running sums start from
+// zero at the window's left edge, which changes g there by a polynomial of degree n-1; the
+// degree-D interpolation reproduces it and the n-th difference annihilates it, so the result
+// is the same in exact arithmetic, and the magnitudes the mask cancels stay bounded by the
+// window length instead of the signal's.  The sums run in registers, each thread on a
+// contiguous chunk of the window, with the chunk totals combined across the workgroup.
+// The interpolant of F on the cell (p-1, p] is a polynomial in t = x + tau + (D+1)/2 - p:
+//   F = sum_e t^e G_e[p],   D! G_e[p] = sum_{l=0}^{D} A[l][e] g[p - l],
+// with integer A (the piece of beta^D on [l, l+1], times D!).  The workgroup tabulates
+// G_0..G_D for every window position in LDS once; each output then needs n+1 table reads and
+// n+1 Horner evaluations.  All sums carry a compensation term (a float64 value plus its
+// rounding error), since the mask cancels magnitudes of order (window length)^n.
+#pragma once
+
+namespace bsf {
+namespace f1d {
+
+constexpr int kThreads = 256;
+constexpr int kPerThread = 2;
+constexpr int kT = kThreads * kPerThread;  // outputs per workgroup
+constexpr int kChunkMax = 16;              // window elements per thread: W <= 4096
+
+__host__ __device__ constexpr long long ipow(long long b, int e) {
+    long long r = 1;
+    for (int i = 0; i < e; ++i) r *= b;
+    return r;
+}
+__host__ __device__ constexpr long long binom(int n, int k) {
+    long long r = 1;
+    for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+    return r;
+}
+__host__ __device__ constexpr long long factorial(int n) { return n <= 1 ? 1 : n * factorial(n - 1); }
+
+// D! times the coefficient of t^e in beta^D(t + l - (D+1)/2), t in (0, 1]: from the
+// truncated-power form of the B-spline, only the terms i <= l are active on that piece.
+__host__ __device__ constexpr long long lattice_coef(int D, int l, int e) {
+    long long s = 0;
+    for (int i = 0; i <= l; ++i) s += ((i & 1) ? -1 : 1) * binom(D + 1, i) * ipow(l - i, D - e);
+    return binom(D, e) * s;
+}
+
+// Window geometry for outputs [m0, m0 + kT) with every scale in [0.5, a_max]: the window
+// starts at m0 - left and holds W samples.  Cell index p = ceil(u) - 1 of the mask point
+// u = (m - P) + tau + (D+1)/2 - a j runs over [D, W - 1].
+__host__ inline int window_left(int n, int D, double a_max) {
+    return (int)std::ceil((a_max + 1.0) * n * 0.5 + 0.5 * (D + 1)) + 1;
+}
+__host__ inline int window_len(int n, int D, double a_max) {
+    const int right = (int)std::ceil(std::max(a_max - 1.0, 0.0) * n * 0.5 + 0.5 * (D + 1)) + 1;
+    return kT + window_left(n, D, a_max) + right;
+}
+__host__ inline long long lds_bytes(int D, int W) { return 16ll * W * (D + 2) + 16ll * (kThreads / 64); }
+
+struct cpair {
+    double s, c;
+};
+__device__ __forceinline__ cpair cp_sum(cpair a, cpair b) {
+    const dd t = two_sum(a.s, b.s);
+    return {t.hi, (a.c + b.c) + t.lo};
+}
+// acc * t + coef for an exact double t (compensated Horner step)
+__device__ __forceinline__ cpair cp_fma(cpair acc, double t, cpair coef) {
+    const double p = acc.s * t;
+    const double pe = __fma_rn(acc.s, t, -p);
+    const dd q = two_sum(p, coef.s);
+    return {q.hi, __fma_rn(acc.c, t, (pe + q.lo) + coef.c)};
+}
+// acc + w * v for a small integer w
+__device__ __forceinline__ cpair cp_axpy_i(cpair acc, double w, cpair v) {
+    const dd h = two_prod(v.s, w);
+    const dd t = two_sum(acc.s, h.hi);
+    return {t.hi, acc.c + ((t.lo + h.lo) + v.c * w)};
+}
+__device__ __forceinline__ cpair shfl_up_cp(cpair v, int d) {
+    return {__shfl_up(v.s, d, 64), __shfl_up(v.c, d, 64)};
+}
+
+struct Args {
+    const void* in;
+    long long in_pitch;
+    const float* scales;
+    long long sc_pitch;
+    double* out;
+    long long out_pitch;
+    int length, tiles, dtype, border, left, W;
+    float a_max;
+    unsigned* err;
+};
+
+template <int N, int D>
+__global__ __launch_bounds__(kThreads) void filter1d_kernel(Args A) {
+    extern __shared__ double4 f1d_lds[];
+    const int W = A.W;
+    double2* tab = reinterpret_cast<double2*>(f1d_lds);  // [D+1][W] (s, c) of G_e
+    double2* gbuf = tab + (D + 1) * W;                    // [W] running sums
+    double2* red = gbuf + W;                              // [4] wave totals
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int b = blockIdx.x / A.tiles;
+    const int tile = blockIdx.x - b * A.tiles;
+    const long long m0 = (long long)tile * kT;
+    const long long P = m0 - A.left;  // signal index of window position 0
+    const long long L = A.length;
+
+    // ---- step 1: n running sums over the window, in registers -----------------------------
+    const int C = (W + kThreads - 1) / kThreads;
+    const long long first = (long long)tid * C;
+    cpair v[kChunkMax];
+    {
+        const bool zero_border = A.border != 0;
+        auto fetch = [&](auto* row) {
+#pragma unroll
+            for (int r = 0; r < kChunkMax; ++r) {
+                double x = 0.0;
+                const long long idx = first + r;
+                if (r < C && idx < W) {
+                    long long k = P + idx;
+                    const bool inside = k >= 0 && k < L;
+                    k = k < 0 ? 0 : (k >= L ? L - 1 : k);
+                    x = (zero_border && !inside) ? 0.0 : (double)row[k];
+                }
+                v[r] = {x, 0.0};
+            }
+        };
+        const long long off = (long long)b * A.in_pitch;
+        const int dt = A.dtype;  // 0 u8, 1 f32, 2 f64
+        if (dt == 0) fetch(static_cast<const unsigned char*>(A.in) + off);
+        else if (dt == 1) fetch(static_cast<const float*>(A.in) + off);
+        else fetch(static_cast<const double*>(A.in) + off);
+    }
+#pragma unroll 1
+    for (int fold = 0; fold < N; ++fold) {
+#pragma unroll
+        for (int r = 1; r < kChunkMax; ++r)
+            if (r < C) v[r] = cp_sum(v[r - 1], v[r]);
+        cpair tot = v[0];
+#pragma unroll
+        for (int r = 1; r < kChunkMax; ++r)
+            if (r == C - 1) tot = v[r];
+        // inclusive scan of the chunk totals within the wave
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const cpair o = shfl_up_cp(tot, d);
+            if (lane >= d) tot = cp_sum(o, tot);
+        }
+        if (lane == 63) red[wave] = make_double2(tot.s, tot.c);
+        __syncthreads();
+        cpair pre = shfl_up_cp(tot, 1);
+        if (lane == 0) pre = {0.0, 0.0};
+        for (int w = 0; w < wave; ++w) {
+            const double2 x = red[w];
+            pre = cp_sum(pre, {x.x, x.y});
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kChunkMax; ++r)
+            if (r < C) v[r] = cp_sum(pre, v[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < kChunkMax; ++r) {
+        const long long idx = first + r;
+        if (r < C && idx < W) gbuf[idx] = make_double2(v[r].s, v[r].c);
+    }
+    __syncthreads();
+
+    // ---- lattice tables G_e[p] = (1/D!) sum_l A[l][e] g[p - l] (the 1/D! is applied last) ----
+    for (int p = tid + D; p < W; p += kThreads) {
+        cpair G[D + 1];
+#pragma unroll
+        for (int e = 0; e <= D; ++e) G[e] = {0.0, 0.0};
+#pragma unroll
+        for (int l = 0; l <= D; ++l) {
+            const double2 x = gbuf[p - l];
+            const cpair gl = {x.x, x.y};
+#pragma unroll
+            for (int e = 0; e <= D; ++e) {
+                const double w = (double)lattice_coef(D, l, e);
+                if (w != 0.0) G[e] = cp_axpy_i(G[e], w, gl);
+            }
+        }
+#pragma unroll
+        for (int e = 0; e <= D; ++e) tab[e * W + p] = make_double2(G[e].s, G[e].c);
+    }
+    __syncthreads();
+
+    // ---- step 2: the finite-difference mask at each output's own scale ----------------------
+    bool bad = false;
+#pragma unroll
+    for (int q = 0; q < kPerThread; ++q) {
+        const long long m = m0 + tid + q * kThreads;
+        if (m >= L) continue;
+        const float af = A.scales[(long long)b * A.sc_pitch + m];
+        double* dst = A.out + (long long)b * A.out_pitch + m;
+        if (!(af >= 0.5f && af <= A.a_max)) {  // false for NaN
+            bad = true;
+            *dst = __builtin_nan("");
+            continue;
+        }
+        const double a = af;
+        const double u0 = (double)(m - P) + (a - 1.0) * (0.5 * N) + 0.5 * (D + 1);
+        cpair acc = {0.0, 0.0};
+#pragma unroll
+        for (int j = 0; j <= N; ++j) {
+            const double u = u0 - a * j;  // exact: a has 24 significant bits
+            const double pc = ceil(u) - 1.0;
+            const double t = u - pc;      // in (0, 1]
+            int p = (int)pc;
+            p = p < D ? D : (p > W - 1 ? W - 1 : p);
+            double2 x = tab[D * W + p];
+            cpair val = {x.x, x.y};
+#pragma unroll
+            for (int e = D - 1; e >= 0; --e) {
+                x = tab[e * W + p];
+                val = cp_fma(val, t, {x.x, x.y});
+            }
+            const double w = (double)(((j & 1) ? -1 : 1) * binom(N, j));
+            acc = cp_axpy_i(acc, w, val);
+        }
+        double r = acc.s + acc.c;
+        if (D > 1) r /= (double)factorial(D);
+#pragma unroll
+        for (int i = 0; i < N; ++i) r /= a;
+        *dst = r;
+    }
+    const unsigned long long bb = __ballot(bad);
+    if (bb && lane == __ffsll((long long)bb) - 1) atomicOr(A.err, kErrScale);
+}
+
+}  // namespace f1d
+}  // namespace bsf

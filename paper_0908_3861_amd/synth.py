@@ -16,6 +16,9 @@ Recipes
 * ``uniform_scales``: every entry i.i.d. real U[lo, hi].
 * ``smooth_scales``: four independent fields, U[0,1) noise blurred with
   (sigma, wrap, truncate 4), min-max to t in [0, 1], a = lo + (hi - lo) t.
+* ``smooth_scales_1d``: per signal, U[0,1) knots every ``period`` samples joined by
+  smoothstep interpolation, min-max per signal to t in [0, 1], a = lo + (hi - lo) t:
+  float32 [count, length] scales of the one-dimensional filter.
 """
 from __future__ import annotations
 
@@ -26,7 +29,7 @@ import numpy as np
 
 __all__ = [
     "unit_grid_image", "blurred_u8_image", "integer_scales", "uniform_scales",
-    "smooth_scales", "Job", "config_job", "batch_jobs", "serving_requests", "CONFIGS",
+    "smooth_scales", "smooth_scales_1d", "Job", "config_job", "batch_jobs", "serving_requests", "CONFIGS",
 ]
 
 
@@ -79,6 +82,20 @@ class Job:
         return int(self.image.shape[0] * self.image.shape[1])
 
 
+def smooth_scales_1d(rng: np.random.Generator, count: int, length: int, lo: float = 1.0, hi: float = 16.0,
+                     period: int = 256) -> np.ndarray:
+    nk = length // period + 2
+    knots = rng.random((count, nk))
+    pos = np.arange(length, dtype=np.float64) / period
+    i = np.floor(pos).astype(np.int64)
+    u = pos - i
+    u = u * u * (3.0 - 2.0 * u)  # smoothstep between neighbouring knots
+    b = knots[:, i] * (1.0 - u) + knots[:, i + 1] * u
+    bmin, bmax = b.min(axis=1, keepdims=True), b.max(axis=1, keepdims=True)
+    t = (b - bmin) / np.maximum(bmax - bmin, 1e-300)
+    return (lo + (hi - lo) * t).astype(np.float32)
+
+
 # The five workload shapes.  "small" is the parity case the oracle finishes in
 # seconds; "plain" is the throughput workload; the others are the precision,
 # batched and serving forms.
@@ -93,6 +110,8 @@ CONFIGS = {
                          "integer scales U{1..8}, orders U{1,2,3}", seed=5),
     "ellipse": dict(desc="2048x2048 ellipse field: smooth s_major in [1,8], elongation in [1,4], "
                          "orientation in [0,pi) (sigma=32 fields), order 2", seed=6),
+    "signal1d": dict(desc="1024 signals x 65536 samples, f32 unit-grid samples, smooth real scales "
+                          "[1,16] (knots every 256 samples), order 3, impulse model, clamp", seed=7),
 }
 
 
