@@ -9,7 +9,8 @@ Mpixel/s, the roofline of the filter call (HIP events on its launch stream) and 
 oracle timed on a bounded pixel sample.
 
 Other forms (not run by default): --workload small | precision | batched | serving | stage1 |
-ellipse (the scale field of elliptical windows, the step before the filter).
+ellipse (the scale field of elliptical windows, the step before the filter) | signal1d (the
+one-dimensional scale-adaptive filter of Section 3 on a batch of signals).
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu-baseline]
 """
@@ -44,9 +45,14 @@ MEASURED_VALU_ISSUE = {"eeff05e894219a68": {("plain", "f64"): 0.86}}
 
 
 def kernel_source_key() -> str:
+    """sha256 prefix over every source the kernels are compiled from."""
+    import glob
     import hashlib
-    src = os.path.join(ROOT, "paper_0908_3861_amd", "csrc", "bsf.hip")
-    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_0908_3861_amd", "csrc")
+    for f in [os.path.join(csrc, "bsf.hip")] + sorted(glob.glob(os.path.join(csrc, "*.h"))):
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def mesh_flops_per_pixel(order: int) -> float:
@@ -106,8 +112,8 @@ def errors(s, o) -> dict:
             "compared": int(len(o))}
 
 
-def record(value, wall, steps, warmup, dtype, config, roofline, cpu, extra):
-    return {"metric": METRIC, "value": value, "unit": "Mpixel/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
+def record(value, wall, steps, warmup, dtype, config, roofline, cpu, extra, unit="Mpixel/s"):
+    return {"metric": METRIC, "value": value, "unit": unit, "n_gpus": 1, "steps": steps, "warmup": warmup,
             "ms_per_step": wall / steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": dtype, "data": "synthetic", "config": config, "roofline": roofline, "cpu_baseline": cpu,
             "extra": extra}
@@ -454,6 +460,73 @@ def workload_ellipse(args):
                   cpu, extra)
 
 
+def workload_signal1d(args):
+    """The one-dimensional scale-adaptive filter (bsf_filter1d, Section 3): 1024 signals of
+    65536 float32 samples, smooth scales in [1, 16], order 3, impulse model.  One step = one
+    bsf_filter1d call (running sums on restart windows, interpolant tables, the mask);
+    algorithmic HBM bytes per sample: 4 in + 4 scale + 8 out."""
+    import torch
+    from paper_0908_3861_amd import binding
+    import oracle.filter1d as OF
+    count, L, order, model = args.signals, args.length, 3, -1
+    rng = np.random.default_rng(synth.CONFIGS["signal1d"]["seed"])
+    sig_np = synth.unit_grid_image(rng, count, L, np.float32)
+    sc_np = synth.smooth_scales_1d(rng, count, L, 1.0, 16.0)
+    dev = torch.device("cuda:0")
+    sig = torch.from_numpy(sig_np).to(dev)
+    sc = torch.from_numpy(sc_np).to(dev)
+    out = torch.empty((count, L), dtype=torch.float64, device=dev)
+    ctx = binding.default_context(0)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        binding.filter1d(sig, sc, order, model, "clamp", a_max=16.0, out=out, ctx=ctx, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    reps = max(args.steps, 1)
+    t0 = time.perf_counter()
+    ms = time_queued(step, reps, stream)
+    wall = time.perf_counter() - t0
+    ctx.check_device()
+    if args.copy_probe_mib:
+        src = torch.ones(args.copy_probe_mib << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+    N = count * L
+    alg = N * (4 + 4 + 8)
+    key = kernel_source_key()
+    roof = {"bound": "hbm", "achieved": alg / (ms * 1e-3) / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+            "frac": alg / (ms * 1e-3) / PEAK_HBM,
+            "traffic": MEASURED_TRAFFIC.get(key, {}).get(("signal1d", "f64"))}
+    extra = {"kernel_ms": ms, "algorithmic_bytes": alg,
+             "executed_valu_issue_frac": MEASURED_VALU_ISSUE.get(key, {}).get(("signal1d", "f64"))}
+    cpu = None
+    if not args.no_cpu_baseline:
+        s = out.cpu().numpy()
+        pr = np.random.default_rng(12347)
+        probe = [(int(b), int(m)) for b, m in zip(pr.integers(0, count, 64), pr.integers(0, L, 64))]
+        t0 = time.perf_counter()
+        OF.filter1d_batch(sig_np, sc_np, order, model, "clamp", probe)
+        tp = max(time.perf_counter() - t0, 1e-3)
+        k = int(min(N, max(64, 64 * args.cpu_seconds / tp)))
+        pts = [(int(b), int(m)) for b, m in zip(pr.integers(0, count, k), pr.integers(0, L, k))]
+        t0 = time.perf_counter()
+        ref = OF.filter1d_batch(sig_np, sc_np, order, model, "clamp", pts)
+        tc = time.perf_counter() - t0
+        extra["err_vs_oracle"] = errors(np.array([s[b, m] for b, m in pts]), ref)
+        cpu = {"value": k / tc / 1e6, "unit": "Msample/s", "cores": 1, "kind": "oracle",
+               "sample": f"{k} random samples of the same {count}x{L} batch (exact rational sums, Python, "
+                         f"one thread), {tc:.1f} s"}
+    config = {"workload": f"signal1d: {count} signals x {L} f32 unit-grid samples, smooth scales [1,16] "
+                          f"(knots every 256 samples), order {order}, impulse model, clamp",
+              "samples": N, "order": order, "model": model}
+    extra["wall_s"] = wall
+    return record(N / (ms * 1e-3) / 1e6, ms * 1e-3 * reps, reps, args.warmup, "f64", config, roof, cpu, extra,
+                  unit="Msample/s")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -464,7 +537,9 @@ def main():
     ap.add_argument("--path", default="f64", choices=["f64", "f32tiled"])
     ap.add_argument("--size", type=int, default=2048)
     ap.add_argument("--workload", default="plain",
-                    choices=["plain", "small", "precision", "batched", "serving", "stage1", "ellipse"])
+                    choices=["plain", "small", "precision", "batched", "serving", "stage1", "ellipse", "signal1d"])
+    ap.add_argument("--signals", type=int, default=1024)
+    ap.add_argument("--length", type=int, default=65536)
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--duration", type=float, default=60.0)
     ap.add_argument("--rate", type=float, default=0.0)
@@ -480,7 +555,7 @@ def main():
         sys.exit(2)
     fn = {"plain": workload_plain, "small": workload_small, "precision": workload_precision,
           "batched": workload_batched, "serving": workload_serving, "stage1": workload_stage1,
-          "ellipse": workload_ellipse}[args.workload]
+          "ellipse": workload_ellipse, "signal1d": workload_signal1d}[args.workload]
     print(json.dumps(fn(args)), flush=True)
 
 

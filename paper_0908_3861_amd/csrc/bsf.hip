@@ -2144,7 +2144,7 @@ double filter1d_max_scale(const bsf_ctx* c, int n, int D) {
     double lo = 0.0, hi = 1e4;
     auto fits = [&](double a) {
         const int W = bsf::f1d::window_len(n, D, a);
-        return W <= bsf::f1d::kThreads * bsf::f1d::kChunkMax && bsf::f1d::lds_bytes(D, W) <= cap;
+        return W <= bsf::f1d::kWindowMax && bsf::f1d::lds_bytes(D, W) <= cap;
     };
     if (!fits(0.5)) return 0.0;
     if (fits(hi)) return hi;
@@ -2476,6 +2476,7 @@ bsf_status bsf_filter1d(bsf_ctx* c, const bsf_job1d* j, void* stream) {
     if (!c) return BSF_ERR_INVALID_ARG;
     if (!j) return fail(c, BSF_ERR_INVALID_ARG, "job is null");
     if (j->length < 1 || j->count < 1) return fail(c, BSF_ERR_INVALID_ARG, "length and count must be >= 1");
+    if (j->length > 0x7fffffff - 2 * bsf::f1d::kWindowMax) return fail(c, BSF_ERR_INVALID_ARG, "signal too long");
     if (!j->in || !j->scales || !j->out) return fail(c, BSF_ERR_INVALID_ARG, "null buffer");
     if (j->in_pitch < j->length || j->scale_pitch < j->length || j->out_pitch < j->length)
         return fail(c, BSF_ERR_INVALID_ARG, "pitches must be >= length");

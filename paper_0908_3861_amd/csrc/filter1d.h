@@ -14,8 +14,8 @@
 // zero at the window's left edge, which changes g there by a polynomial of degree n-1; the
 // degree-D interpolation reproduces it and the n-th difference annihilates it, so the result
 // is the same in exact arithmetic, and the magnitudes the mask cancels stay bounded by the
-// window length instead of the signal's.  The sums run in registers, each thread on a
-// contiguous chunk of the window, with the chunk totals combined across the workgroup.
+// window length instead of the signal's.  One wave runs the sums, each lane on a contiguous
+// chunk of the window in LDS, with the chunk totals combined across the wave.
 // The interpolant of F on the cell (p-1, p] is a polynomial in t = x + tau + (D+1)/2 - p:
 //   F = sum_e t^e G_e[p],   D! G_e[p] = sum_{l=0}^{D} A[l][e] g[p - l],
 // with integer A (the piece of beta^D on [l, l+1], times D!).  The workgroup tabulates
@@ -30,7 +30,7 @@ namespace f1d {
 constexpr int kThreads = 256;
 constexpr int kPerThread = 2;
 constexpr int kT = kThreads * kPerThread;  // outputs per workgroup
-constexpr int kChunkMax = 16;              // window elements per thread: W <= 4096
+constexpr int kWindowMax = 4096;           // longest restart window
 
 __host__ __device__ constexpr long long ipow(long long b, int e) {
     long long r = 1;
@@ -62,7 +62,7 @@ __host__ inline int window_len(int n, int D, double a_max) {
     const int right = (int)std::ceil(std::max(a_max - 1.0, 0.0) * n * 0.5 + 0.5 * (D + 1)) + 1;
     return kT + window_left(n, D, a_max) + right;
 }
-__host__ inline long long lds_bytes(int D, int W) { return 16ll * W * (D + 2) + 16ll * (kThreads / 64); }
+__host__ inline long long lds_bytes(int D, int W) { return 16ll * W * (D + 2); }
 
 struct cpair {
     double s, c;
@@ -100,95 +100,143 @@ struct Args {
     unsigned* err;
 };
 
+// acc + w * v for an integer weight w known at compile time after unrolling: powers of two
+// (the common case, +-1 and +-2) scale exactly and need no two-product.
+__device__ __forceinline__ bool pow2_weight(long long w) {
+    const long long a = w < 0 ? -w : w;
+    return a != 0 && (a & (a - 1)) == 0;
+}
+__device__ __forceinline__ cpair cp_add_weighted(cpair acc, long long w, cpair v) {
+    if (pow2_weight(w)) return cp_sum(acc, {v.s * (double)w, v.c * (double)w});
+    return cp_axpy_i(acc, (double)w, v);
+}
+// w * v as the first term of a sum
+__device__ __forceinline__ cpair cp_weighted(long long w, cpair v) {
+    if (pow2_weight(w)) return {v.s * (double)w, v.c * (double)w};
+    const dd h = two_prod(v.s, (double)w);
+    return {h.hi, h.lo + v.c * (double)w};
+}
+
+template <typename T>
+__device__ __forceinline__ void load_window(const Args& A, const T* row, int P, double2* gbuf) {
+    const int L = A.length;
+    const bool zero_border = A.border != 0;
+    // four samples per thread in flight at a time
+    for (int base = threadIdx.x; base < A.W; base += 4 * kThreads) {
+        double x[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int idx = base + r * kThreads;
+            const int k = P + idx;
+            const bool inside = k >= 0 && k < L;
+            const int kc = k < 0 ? 0 : (k >= L ? L - 1 : k);
+            x[r] = (idx < A.W && !(zero_border && !inside)) ? (double)row[kc] : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int idx = base + r * kThreads;
+            if (idx < A.W) gbuf[idx] = make_double2(x[r], 0.0);
+        }
+    }
+}
+
 template <int N, int D>
 __global__ __launch_bounds__(kThreads) void filter1d_kernel(Args A) {
     extern __shared__ double4 f1d_lds[];
     const int W = A.W;
     double2* tab = reinterpret_cast<double2*>(f1d_lds);  // [D+1][W] (s, c) of G_e
-    double2* gbuf = tab + (D + 1) * W;                    // [W] running sums
-    double2* red = gbuf + W;                              // [4] wave totals
+    double2* gbuf = tab + (D + 1) * W;                    // [W] samples, then running sums
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
     const int b = blockIdx.x / A.tiles;
     const int tile = blockIdx.x - b * A.tiles;
-    const long long m0 = (long long)tile * kT;
-    const long long P = m0 - A.left;  // signal index of window position 0
-    const long long L = A.length;
+    const int m0 = tile * kT;
+    const int P = m0 - A.left;  // signal index of window position 0
+    const int L = A.length;
 
-    // ---- step 1: n running sums over the window, in registers -----------------------------
-    const int C = (W + kThreads - 1) / kThreads;
-    const long long first = (long long)tid * C;
-    cpair v[kChunkMax];
+    // the outputs' scales, fetched first so that their latency overlaps step 1
+    float af[kPerThread];
+#pragma unroll
+    for (int q = 0; q < kPerThread; ++q) {
+        const int m = m0 + tid + q * kThreads;
+        af[q] = m < L ? A.scales[(long long)b * A.sc_pitch + m] : 1.0f;
+    }
+
+    // ---- the window's samples, coalesced, into LDS ----------------------------------------
     {
-        const bool zero_border = A.border != 0;
-        auto fetch = [&](auto* row) {
-#pragma unroll
-            for (int r = 0; r < kChunkMax; ++r) {
-                double x = 0.0;
-                const long long idx = first + r;
-                if (r < C && idx < W) {
-                    long long k = P + idx;
-                    const bool inside = k >= 0 && k < L;
-                    k = k < 0 ? 0 : (k >= L ? L - 1 : k);
-                    x = (zero_border && !inside) ? 0.0 : (double)row[k];
-                }
-                v[r] = {x, 0.0};
-            }
-        };
         const long long off = (long long)b * A.in_pitch;
-        const int dt = A.dtype;  // 0 u8, 1 f32, 2 f64
-        if (dt == 0) fetch(static_cast<const unsigned char*>(A.in) + off);
-        else if (dt == 1) fetch(static_cast<const float*>(A.in) + off);
-        else fetch(static_cast<const double*>(A.in) + off);
-    }
-#pragma unroll 1
-    for (int fold = 0; fold < N; ++fold) {
-#pragma unroll
-        for (int r = 1; r < kChunkMax; ++r)
-            if (r < C) v[r] = cp_sum(v[r - 1], v[r]);
-        cpair tot = v[0];
-#pragma unroll
-        for (int r = 1; r < kChunkMax; ++r)
-            if (r == C - 1) tot = v[r];
-        // inclusive scan of the chunk totals within the wave
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const cpair o = shfl_up_cp(tot, d);
-            if (lane >= d) tot = cp_sum(o, tot);
-        }
-        if (lane == 63) red[wave] = make_double2(tot.s, tot.c);
-        __syncthreads();
-        cpair pre = shfl_up_cp(tot, 1);
-        if (lane == 0) pre = {0.0, 0.0};
-        for (int w = 0; w < wave; ++w) {
-            const double2 x = red[w];
-            pre = cp_sum(pre, {x.x, x.y});
-        }
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < kChunkMax; ++r)
-            if (r < C) v[r] = cp_sum(pre, v[r]);
-    }
-#pragma unroll
-    for (int r = 0; r < kChunkMax; ++r) {
-        const long long idx = first + r;
-        if (r < C && idx < W) gbuf[idx] = make_double2(v[r].s, v[r].c);
+        if (A.dtype == 0) load_window(A, static_cast<const unsigned char*>(A.in) + off, P, gbuf);
+        else if (A.dtype == 1) load_window(A, static_cast<const float*>(A.in) + off, P, gbuf);
+        else load_window(A, static_cast<const double*>(A.in) + off, P, gbuf);
     }
     __syncthreads();
 
-    // ---- lattice tables G_e[p] = (1/D!) sum_l A[l][e] g[p - l] (the 1/D! is applied last) ----
+    // ---- step 1: n running sums over the window, by one wave --------------------------------
+    // Lane i owns the chunk [i C, i C + C) (C odd: 16-byte LDS accesses at an odd multiple of
+    // 16 bytes apart do not collide).  Each pass scans its chunk, then adds the exclusive
+    // prefix of the chunk totals; the prefix of fold k is added while fold k+1 scans.
+    // The wave that runs them rotates with the workgroup index: the waves of a workgroup are
+    // spread over the CU's four SIMDs in the same order for every workgroup, and the sums are
+    // the longest phase, so a fixed choice would load one SIMD with every workgroup's sums.
+    if ((tid >> 6) == (int)(blockIdx.x & 3)) {
+        const int C = ((W + 63) / 64) | 1;
+        const int lo = lane * C < W ? lane * C : W;
+        const int hi = lo + C < W ? lo + C : W;
+        cpair pre = {0.0, 0.0};
+#pragma unroll 1
+        for (int fold = 0; fold < N; ++fold) {
+            cpair s = {0.0, 0.0};
+            // four elements per batch: their LDS reads are in flight together
+            for (int i0 = lo; i0 < hi; i0 += 4) {
+                double2 x[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) x[r] = i0 + r < hi ? gbuf[i0 + r] : make_double2(0.0, 0.0);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    if (i0 + r < hi) {
+                        // finish the previous fold (its prefix), then scan this one
+                        s = cp_sum(s, fold == 0 ? cpair{x[r].x, 0.0} : cp_sum(pre, {x[r].x, x[r].y}));
+                        gbuf[i0 + r] = make_double2(s.s, s.c);
+                    }
+                }
+            }
+            cpair tot = s;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const cpair o = shfl_up_cp(tot, d);
+                if (lane >= d) tot = cp_sum(o, tot);
+            }
+            pre = shfl_up_cp(tot, 1);
+            if (lane == 0) pre = {0.0, 0.0};
+        }
+        for (int i = lo; i < hi; ++i) {
+            const double2 x = gbuf[i];
+            const cpair g = cp_sum(pre, {x.x, x.y});
+            gbuf[i] = make_double2(g.s, g.c);
+        }
+    }
+    __syncthreads();
+
+    // ---- lattice tables G_e[p] = sum_l A[l][e] g[p - l] (the 1/D! is applied last) ---------
+#pragma unroll 2
     for (int p = tid + D; p < W; p += kThreads) {
         cpair G[D + 1];
+        bool seeded[D + 1];
 #pragma unroll
-        for (int e = 0; e <= D; ++e) G[e] = {0.0, 0.0};
+        for (int e = 0; e <= D; ++e) {
+            G[e] = {0.0, 0.0};
+            seeded[e] = false;
+        }
 #pragma unroll
         for (int l = 0; l <= D; ++l) {
             const double2 x = gbuf[p - l];
             const cpair gl = {x.x, x.y};
 #pragma unroll
             for (int e = 0; e <= D; ++e) {
-                const double w = (double)lattice_coef(D, l, e);
-                if (w != 0.0) G[e] = cp_axpy_i(G[e], w, gl);
+                const long long w = lattice_coef(D, l, e);
+                if (w == 0) continue;
+                G[e] = seeded[e] ? cp_add_weighted(G[e], w, gl) : cp_weighted(w, gl);
+                seeded[e] = true;
             }
         }
 #pragma unroll
@@ -200,21 +248,20 @@ __global__ __launch_bounds__(kThreads) void filter1d_kernel(Args A) {
     bool bad = false;
 #pragma unroll
     for (int q = 0; q < kPerThread; ++q) {
-        const long long m = m0 + tid + q * kThreads;
+        const int m = m0 + tid + q * kThreads;
         if (m >= L) continue;
-        const float af = A.scales[(long long)b * A.sc_pitch + m];
         double* dst = A.out + (long long)b * A.out_pitch + m;
-        if (!(af >= 0.5f && af <= A.a_max)) {  // false for NaN
+        if (!(af[q] >= 0.5f && af[q] <= A.a_max)) {  // false for NaN
             bad = true;
             *dst = __builtin_nan("");
             continue;
         }
-        const double a = af;
+        const double a = af[q];
         const double u0 = (double)(m - P) + (a - 1.0) * (0.5 * N) + 0.5 * (D + 1);
         cpair acc = {0.0, 0.0};
 #pragma unroll
         for (int j = 0; j <= N; ++j) {
-            const double u = u0 - a * j;  // exact: a has 24 significant bits
+            const double u = __fma_rn(-a, (double)j, u0);  // exact: a has 24 significant bits
             const double pc = ceil(u) - 1.0;
             const double t = u - pc;      // in (0, 1]
             int p = (int)pc;
@@ -226,14 +273,14 @@ __global__ __launch_bounds__(kThreads) void filter1d_kernel(Args A) {
                 x = tab[e * W + p];
                 val = cp_fma(val, t, {x.x, x.y});
             }
-            const double w = (double)(((j & 1) ? -1 : 1) * binom(N, j));
-            acc = cp_axpy_i(acc, w, val);
+            acc = j == 0 ? val : cp_add_weighted(acc, ((j & 1) ? -1 : 1) * binom(N, j), val);
         }
-        double r = acc.s + acc.c;
-        if (D > 1) r /= (double)factorial(D);
+        // a^n D!: a^2 is exact (48 bits), a^3 and the factorial round once each
+        double den = a;
 #pragma unroll
-        for (int i = 0; i < N; ++i) r /= a;
-        *dst = r;
+        for (int i = 1; i < N; ++i) den *= a;
+        den *= (double)factorial(D);
+        *dst = (acc.s + acc.c) / den;
     }
     const unsigned long long bb = __ballot(bad);
     if (bb && lane == __ffsll((long long)bb) - 1) atomicOr(A.err, kErrScale);

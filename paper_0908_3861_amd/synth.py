@@ -93,7 +93,7 @@ def smooth_scales_1d(rng: np.random.Generator, count: int, length: int, lo: floa
     b = knots[:, i] * (1.0 - u) + knots[:, i + 1] * u
     bmin, bmax = b.min(axis=1, keepdims=True), b.max(axis=1, keepdims=True)
     t = (b - bmin) / np.maximum(bmax - bmin, 1e-300)
-    return (lo + (hi - lo) * t).astype(np.float32)
+    return np.ascontiguousarray((lo + (hi - lo) * t).astype(np.float32))
 
 
 # The five workload shapes.  "small" is the parity case the oracle finishes in

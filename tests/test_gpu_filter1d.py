@@ -138,6 +138,26 @@ def test_scale_errors(torch_dev):
         run(torch, sig, np.ones_like(sc), 4, -1)  # order 4 is not provided
 
 
+@pytest.mark.parametrize("n,n1", [(1, -1), (3, 1), (2, 0)])
+def test_largest_windows(torch_dev, n, n1):
+    """Scales up to the largest bound the on-chip window allows (a 4096-sample window at
+    order 1, the whole LDS at order 3 with the linear model), on sampled outputs."""
+    torch = torch_dev
+    from paper_0908_3861_amd import binding
+    lim = binding.filter1d_max_scale(n, n1)
+    rng = np.random.default_rng(994 + n)
+    count, L = 2, 1300
+    sig = synth.unit_grid_image(rng, count, L, np.float64)
+    sc = rng.uniform(0.75 * lim, lim, size=(count, L)).astype(np.float32)
+    sc[0, :3] = np.float32(lim)
+    s = run(torch, sig, sc, n, n1, "zero", a_max=lim)
+    pr = np.random.default_rng(6)
+    pts = [(0, 0), (0, 1), (1, L - 1), (1, 511), (1, 512)]
+    pts += [(int(b), int(m)) for b, m in zip(pr.integers(0, count, 40), pr.integers(0, L, 40))]
+    o = F.filter1d_batch(sig, sc, n, n1, "zero", pts)
+    assert rel_max(np.array([s[b, m] for b, m in pts]), o) < TOL
+
+
 def test_full_size_sampled(torch_dev):
     """The full throughput workload (1024 signals x 65536 samples, f32, smooth scales [1,16],
     order 3, impulse model), in the launch the bench times, on sampled outputs."""
