@@ -157,7 +157,7 @@ bsf_status bsf_scales_from_ellipses(bsf_ctx* ctx, const float* ellipses, ptrdiff
  * values (clamp) or zeros.  Computed by Proposition 3.1: order running sums (eq. RS, unit
  * scale), then per sample the finite-difference mask Delta_a^order (eq. FD) applied to the
  * running sums interpolated with the B-spline of degree model + order, on restart windows of
- * 512 outputs.  The running sums, the interpolation and the mask carry a compensation term,
+ * 256 outputs.  The running sums, the interpolation and the mask carry a compensation term,
  * so the result matches the exact projection to a few float64 ulps of its largest terms. */
 typedef struct {
     int length, count;              /* samples per signal, number of signals (>= 1)       */
@@ -183,7 +183,7 @@ typedef struct {
 bsf_status bsf_filter1d(bsf_ctx* ctx, const bsf_job1d* job, void* stream);
 
 /* The largest a_max bsf_filter1d accepts for this order and model (its restart window,
- * (3 + model + order) * 16 bytes per sample of 512 + about order * a_max samples, must fit
+ * (3 + model + order) * 16 bytes per sample of 256 + about order * a_max samples, must fit
  * the on-chip memory of one workgroup).  Host only. */
 bsf_status bsf_filter1d_max_scale(bsf_ctx* ctx, int order, int model, float* a_max);
 

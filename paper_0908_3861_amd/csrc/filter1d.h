@@ -9,7 +9,7 @@
 //   2. adaptive: F(x) = sum_k g[k] beta^D(x + tau - k) with D = n1 + n, tau = (a-1) n / 2,
 //      and s[m] = Delta_a^n F(m) = a^-n sum_j (-1)^j C(n,j) F(m - a j) (eq. FD).
 //
-// Layout of the work.  A workgroup owns kT consecutive outputs of one signal and runs step 1
+// Layout of the work.  A workgroup owns kT = 256 consecutive outputs of one signal and runs step 1
 // on a restart window that holds every sample their masks reach: the running sums start from
 // zero at the window's left edge, which changes g there by a polynomial of degree n-1; the
 // degree-D interpolation reproduces it and the n-th difference annihilates it, so the result
@@ -28,7 +28,7 @@ namespace bsf {
 namespace f1d {
 
 constexpr int kThreads = 256;
-constexpr int kPerThread = 2;
+constexpr int kPerThread = 1;
 constexpr int kT = kThreads * kPerThread;  // outputs per workgroup
 constexpr int kWindowMax = 4096;           // longest restart window
 

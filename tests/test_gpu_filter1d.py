@@ -3,7 +3,7 @@ exact oracle (oracle/filter1d.py), through the C ABI.
 
 Error measure: rel_max = max|s - O| / max|O| over the compared samples, bar 1e-12 (the
 float64 bar of the two-dimensional path); the oracle is the correctly rounded exact
-projection.  Sizes span several 512-output tiles with a ragged tail.
+projection.  Sizes span several 256-output tiles with a ragged tail.
 """
 import numpy as np
 import pytest
@@ -41,7 +41,7 @@ def run(torch, sig, sc, n, n1, border="clamp", a_max=None, check=True):
 @pytest.mark.parametrize("n,n1", MODELS)
 def test_parity_every_order_and_model(torch_dev, n, n1):
     rng = np.random.default_rng(900 + 3 * n + n1)
-    count, L = 2, 1100  # two full tiles and a ragged one per signal
+    count, L = 2, 1100  # four full tiles and a ragged one per signal
     sig = synth.unit_grid_image(rng, count, L, np.float64)
     sc = rng.uniform(0.5, 12.0, size=(count, L)).astype(np.float32)
     s = run(torch_dev, sig, sc, n, n1)
@@ -84,7 +84,7 @@ def test_edge_cases(torch_dev):
     sc = rng.integers(1, 9, size=(2, 600)).astype(np.float32)
     sc[:, ::7] = 8.0
     assert rel_max(run(torch, sig, sc, 3, -1, a_max=8.0), F.filter1d_batch(sig, sc, 3, -1)) < TOL
-    # exactly one tile
+    # exactly two tiles
     sig = synth.unit_grid_image(rng, 1, 512, np.float64)
     sc = rng.uniform(1, 6, size=(1, 512)).astype(np.float32)
     assert rel_max(run(torch, sig, sc, 2, 0), F.filter1d_batch(sig, sc, 2, 0)) < TOL
@@ -152,7 +152,7 @@ def test_largest_windows(torch_dev, n, n1):
     sc[0, :3] = np.float32(lim)
     s = run(torch, sig, sc, n, n1, "zero", a_max=lim)
     pr = np.random.default_rng(6)
-    pts = [(0, 0), (0, 1), (1, L - 1), (1, 511), (1, 512)]
+    pts = [(0, 0), (0, 1), (1, L - 1), (1, 255), (1, 256), (1, 511), (1, 512)]
     pts += [(int(b), int(m)) for b, m in zip(pr.integers(0, count, 40), pr.integers(0, L, 40))]
     o = F.filter1d_batch(sig, sc, n, n1, "zero", pts)
     assert rel_max(np.array([s[b, m] for b, m in pts]), o) < TOL
@@ -169,7 +169,7 @@ def test_full_size_sampled(torch_dev):
     s = run(torch, sig, sc, 3, -1, a_max=16.0)
     pr = np.random.default_rng(5)
     pts = [(int(b), int(m)) for b, m in zip(pr.integers(0, count, 1500), pr.integers(0, L, 1500))]
-    pts += [(0, 0), (count - 1, L - 1), (5, 511), (5, 512), (7, L - 513)]  # ends and tile seams
+    pts += [(0, 0), (count - 1, L - 1), (5, 255), (5, 256), (7, L - 257)]  # ends and tile seams
     o = F.filter1d_batch(sig, sc, 3, -1, "clamp", pts)
     got = np.array([s[b, m] for b, m in pts])
     err = rel_max(got, o)
