@@ -470,18 +470,20 @@ def workload_signal1d(args):
     from paper_0908_3861_amd import binding
     import oracle.filter1d as OF
     count, L, order, model = args.signals, args.length, 3, -1
+    path = args.path
+    ob = 8 if path == "f64" else 4
     rng = np.random.default_rng(synth.CONFIGS["signal1d"]["seed"])
     sig_np = synth.unit_grid_image(rng, count, L, np.float32)
     sc_np = synth.smooth_scales_1d(rng, count, L, 1.0, 16.0)
     dev = torch.device("cuda:0")
     sig = torch.from_numpy(sig_np).to(dev)
     sc = torch.from_numpy(sc_np).to(dev)
-    out = torch.empty((count, L), dtype=torch.float64, device=dev)
+    out = torch.empty((count, L), dtype=torch.float64 if path == "f64" else torch.float32, device=dev)
     ctx = binding.default_context(0)
     stream = torch.cuda.current_stream()
 
     def step():
-        binding.filter1d(sig, sc, order, model, "clamp", a_max=16.0, out=out, ctx=ctx, stream=stream)
+        binding.filter1d(sig, sc, order, model, "clamp", a_max=16.0, out=out, ctx=ctx, stream=stream, path=path)
 
     for _ in range(args.warmup):
         step()
@@ -496,16 +498,16 @@ def workload_signal1d(args):
         dst.copy_(src)
         torch.cuda.synchronize()
     N = count * L
-    alg = N * (4 + 4 + 8)
+    alg = N * (4 + 4 + ob)
     key = kernel_source_key()
     roof = {"bound": "hbm", "achieved": alg / (ms * 1e-3) / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
             "frac": alg / (ms * 1e-3) / PEAK_HBM,
-            "traffic": MEASURED_TRAFFIC.get(key, {}).get(("signal1d", "f64"))}
+            "traffic": MEASURED_TRAFFIC.get(key, {}).get(("signal1d", path))}
     extra = {"kernel_ms": ms, "algorithmic_bytes": alg,
-             "executed_valu_issue_frac": MEASURED_VALU_ISSUE.get(key, {}).get(("signal1d", "f64"))}
+             "executed_valu_issue_frac": MEASURED_VALU_ISSUE.get(key, {}).get(("signal1d", path))}
     cpu = None
     if not args.no_cpu_baseline:
-        s = out.cpu().numpy()
+        s = out.cpu().numpy().astype(np.float64)
         pr = np.random.default_rng(12347)
         probe = [(int(b), int(m)) for b, m in zip(pr.integers(0, count, 64), pr.integers(0, L, 64))]
         t0 = time.perf_counter()
@@ -521,11 +523,11 @@ def workload_signal1d(args):
                "sample": f"{k} random samples of the same {count}x{L} batch (exact rational sums, Python, "
                          f"one thread), {tc:.1f} s"}
     config = {"workload": f"signal1d: {count} signals x {L} f32 unit-grid samples, smooth scales [1,16] "
-                          f"(knots every 256 samples), order {order}, impulse model, clamp",
-              "samples": N, "order": order, "model": model}
+                          f"(knots every 256 samples), order {order}, impulse model, clamp, {path} path",
+              "samples": N, "order": order, "model": model, "path": path}
     extra["wall_s"] = wall
-    return record(N / (ms * 1e-3) / 1e6, ms * 1e-3 * reps, reps, args.warmup, "f64", config, roof, cpu, extra,
-                  unit="Msample/s")
+    return record(N / (ms * 1e-3) / 1e6, ms * 1e-3 * reps, reps, args.warmup,
+                  "f64" if path == "f64" else "f64-compute/f32-out", config, roof, cpu, extra, unit="Msample/s")
 
 
 def main():

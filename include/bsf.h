@@ -157,8 +157,11 @@ bsf_status bsf_scales_from_ellipses(bsf_ctx* ctx, const float* ellipses, ptrdiff
  * values (clamp) or zeros.  Computed by Proposition 3.1: order running sums (eq. RS, unit
  * scale), then per sample the finite-difference mask Delta_a^order (eq. FD) applied to the
  * running sums interpolated with the B-spline of degree model + order, on restart windows of
- * 256 outputs.  The running sums, the interpolation and the mask carry a compensation term,
- * so the result matches the exact projection to a few float64 ulps of its largest terms. */
+ * 256 outputs.  BSF_PATH_F64: the running sums, the interpolation and the mask carry a
+ * compensation term, so the float64 result matches the exact projection to a few ulps of its
+ * largest terms.  BSF_PATH_F32_TILED: the running sums are compensated, the interpolation and
+ * the mask plain float64, the result float32; its error is below 1e-5 of the output's
+ * magnitude (tested at orders 1-3, all models, scales 0.5 to the largest window). */
 typedef struct {
     int length, count;              /* samples per signal, number of signals (>= 1)       */
     bsf_dtype in_dtype;             /* u8, f32 or f64                                      */
@@ -168,10 +171,11 @@ typedef struct {
     ptrdiff_t scale_pitch;          /* >= length                                           */
     int order;                      /* number of running sums, 1..3 (B-spline degree + 1)  */
     int model;                      /* degree of the signal model: -1, 0 or 1              */
+    bsf_path path;                  /* F64: float64 output; F32_TILED: float32 output       */
     bsf_border border;
     float a_max;                    /* upper bound on every scale (sizes the on-chip windows;
                                        0 = the largest bsf_filter1d_max_scale allows)      */
-    double* out;                    /* [count][out_pitch] float64                          */
+    void* out;                      /* [count][out_pitch] float64 (F64) / float32 (F32)    */
     ptrdiff_t out_pitch;            /* >= length                                           */
 } bsf_job1d;
 
@@ -182,9 +186,9 @@ typedef struct {
  * bsf_filter1d_max_scale. */
 bsf_status bsf_filter1d(bsf_ctx* ctx, const bsf_job1d* job, void* stream);
 
-/* The largest a_max bsf_filter1d accepts for this order and model (its restart window,
- * (3 + model + order) * 16 bytes per sample of 256 + about order * a_max samples, must fit
- * the on-chip memory of one workgroup).  Host only. */
+/* The largest a_max bsf_filter1d accepts for this order and model, on either path (the
+ * restart window of 256 + about order * a_max samples, at (3 + model + order) * 16 bytes per
+ * sample, must fit the on-chip memory of one workgroup).  Host only. */
 bsf_status bsf_filter1d_max_scale(bsf_ctx* ctx, int order, int model, float* a_max);
 
 /* Evaluation counters of the float64 path (Section 7 mesh, eq. final_eqn), kept per

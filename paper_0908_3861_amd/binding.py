@@ -44,7 +44,7 @@ class Job1d(ctypes.Structure):
         ("length", ctypes.c_int), ("count", ctypes.c_int),
         ("in_dtype", ctypes.c_int), ("in_", ctypes.c_void_p), ("in_pitch", ctypes.c_ssize_t),
         ("scales", ctypes.c_void_p), ("scale_pitch", ctypes.c_ssize_t),
-        ("order", ctypes.c_int), ("model", ctypes.c_int), ("border", ctypes.c_int),
+        ("order", ctypes.c_int), ("model", ctypes.c_int), ("path", ctypes.c_int), ("border", ctypes.c_int),
         ("a_max", ctypes.c_float),
         ("out", ctypes.c_void_p), ("out_pitch", ctypes.c_ssize_t),
     ]
@@ -259,7 +259,7 @@ def scales_from_ellipses(ell, order: int, out=None, ctx: Context | None = None, 
 
 
 def filter1d_max_scale(order: int, model: int = -1, ctx: Context | None = None) -> float:
-    """The largest scale bound bsf_filter1d accepts for this order and model."""
+    """The largest scale bound bsf_filter1d accepts for this order and model (either path)."""
     ctx = ctx or default_context()
     v = ctypes.c_float()
     ctx._check(ctx.lib.bsf_filter1d_max_scale(ctx.handle, int(order), int(model), ctypes.byref(v)))
@@ -267,10 +267,10 @@ def filter1d_max_scale(order: int, model: int = -1, ctx: Context | None = None) 
 
 
 def filter1d(signals, scales, order: int, model: int = -1, border: str = "clamp", a_max: float | None = None,
-             out=None, ctx: Context | None = None, stream=None, check: bool = False):
+             out=None, ctx: Context | None = None, stream=None, check: bool = False, path: str = "f64"):
     """One-dimensional scale-adaptive filter (bsf_filter1d) of device tensors ``signals``
     [count, length] (uint8/float32/float64) with per-sample float32 ``scales`` [count, length];
-    returns float64 [count, length].  Rows may be padded (contiguous samples within a row).
+    returns [count, length], float64 (path "f64") or float32 (path "f32tiled").  Rows may be padded (contiguous samples within a row).
     ``a_max`` defaults to the largest scale (one device reduction and a host sync)."""
     import torch
     ctx = ctx or default_context(signals.device.index)
@@ -281,10 +281,11 @@ def filter1d(signals, scales, order: int, model: int = -1, border: str = "clamp"
     if scales.dtype != torch.float32 or scales.stride(1) != 1 or signals.stride(1) != 1:
         raise ValueError("scales must be float32; samples within a row must be contiguous")
     count, length = signals.shape
+    odt = torch.float64 if path == "f64" else torch.float32
     if out is None:
         with _on(stream):
-            out = torch.empty((count, length), dtype=torch.float64, device=signals.device)
-    elif out.dtype != torch.float64 or tuple(out.shape) != (count, length) or out.stride(1) != 1:
+            out = torch.empty((count, length), dtype=odt, device=signals.device)
+    elif out.dtype != odt or tuple(out.shape) != (count, length) or out.stride(1) != 1:
         raise ValueError("bad output tensor")
     if a_max is None:
         with _on(stream):
@@ -298,6 +299,7 @@ def filter1d(signals, scales, order: int, model: int = -1, border: str = "clamp"
     j.scale_pitch = scales.stride(0)
     j.order = int(order)
     j.model = int(model)
+    j.path = PATHS[path]
     j.border = BORDERS[border]
     j.a_max = float(a_max)
     j.out = out.data_ptr()

@@ -2113,38 +2113,48 @@ hipError_t dispatch_batch_group(const bsf_ctx* c, int v, const JobDesc* djobs, i
 
 namespace {
 
-template <int N, int D>
+template <int N, int D, int PATH>
 hipError_t launch_filter1d(const bsf::f1d::Args& A, int blocks, long long lds, hipStream_t st) {
     static bool opted = false;
     if (!opted) {
-        allow_big_lds(bsf::f1d::filter1d_kernel<N, D>);
+        allow_big_lds(bsf::f1d::filter1d_kernel<N, D, PATH>);
         opted = true;
     }
-    hipLaunchKernelGGL((bsf::f1d::filter1d_kernel<N, D>), dim3(blocks), dim3(bsf::f1d::kThreads), (size_t)lds, st, A);
+    hipLaunchKernelGGL((bsf::f1d::filter1d_kernel<N, D, PATH>), dim3(blocks), dim3(bsf::f1d::kThreads), (size_t)lds,
+                       st, A);
     return hipGetLastError();
 }
 
-hipError_t dispatch_filter1d(int n, int D, const bsf::f1d::Args& A, int blocks, long long lds, hipStream_t st) {
+template <int PATH>
+hipError_t dispatch_filter1d_path(int n, int D, const bsf::f1d::Args& A, int blocks, long long lds, hipStream_t st) {
     switch (n * 8 + D) {
-        case 1 * 8 + 0: return launch_filter1d<1, 0>(A, blocks, lds, st);
-        case 1 * 8 + 1: return launch_filter1d<1, 1>(A, blocks, lds, st);
-        case 1 * 8 + 2: return launch_filter1d<1, 2>(A, blocks, lds, st);
-        case 2 * 8 + 1: return launch_filter1d<2, 1>(A, blocks, lds, st);
-        case 2 * 8 + 2: return launch_filter1d<2, 2>(A, blocks, lds, st);
-        case 2 * 8 + 3: return launch_filter1d<2, 3>(A, blocks, lds, st);
-        case 3 * 8 + 2: return launch_filter1d<3, 2>(A, blocks, lds, st);
-        case 3 * 8 + 3: return launch_filter1d<3, 3>(A, blocks, lds, st);
-        default: return launch_filter1d<3, 4>(A, blocks, lds, st);
+        case 1 * 8 + 0: return launch_filter1d<1, 0, PATH>(A, blocks, lds, st);
+        case 1 * 8 + 1: return launch_filter1d<1, 1, PATH>(A, blocks, lds, st);
+        case 1 * 8 + 2: return launch_filter1d<1, 2, PATH>(A, blocks, lds, st);
+        case 2 * 8 + 1: return launch_filter1d<2, 1, PATH>(A, blocks, lds, st);
+        case 2 * 8 + 2: return launch_filter1d<2, 2, PATH>(A, blocks, lds, st);
+        case 2 * 8 + 3: return launch_filter1d<2, 3, PATH>(A, blocks, lds, st);
+        case 3 * 8 + 2: return launch_filter1d<3, 2, PATH>(A, blocks, lds, st);
+        case 3 * 8 + 3: return launch_filter1d<3, 3, PATH>(A, blocks, lds, st);
+        default: return launch_filter1d<3, 4, PATH>(A, blocks, lds, st);
     }
 }
 
+hipError_t dispatch_filter1d(int n, int D, int path, const bsf::f1d::Args& A, int blocks, long long lds,
+                             hipStream_t st) {
+    return path == 1 ? dispatch_filter1d_path<1>(n, D, A, blocks, lds, st)
+                     : dispatch_filter1d_path<0>(n, D, A, blocks, lds, st);
+}
+
 // Largest scale bound whose window fits the LDS a workgroup may hold (0 if none does).
+// Both paths take the float64 path's window: it bounds the magnitudes the float32 path's plain
+// mask cancels as well as the LDS of either path.
 double filter1d_max_scale(const bsf_ctx* c, int n, int D) {
     const long long cap = std::min<long long>(c->lds_max_bytes, 163840 - 1024);
     double lo = 0.0, hi = 1e4;
     auto fits = [&](double a) {
         const int W = bsf::f1d::window_len(n, D, a);
-        return W <= bsf::f1d::kWindowMax && bsf::f1d::lds_bytes(D, W) <= cap;
+        return W <= bsf::f1d::kWindowMax && bsf::f1d::lds_bytes(D, W, 0) <= cap;
     };
     if (!fits(0.5)) return 0.0;
     if (fits(hi)) return hi;
@@ -2485,7 +2495,8 @@ bsf_status bsf_filter1d(bsf_ctx* c, const bsf_job1d* j, void* stream) {
     if (j->border != BSF_BORDER_CLAMP && j->border != BSF_BORDER_ZERO) return fail(c, BSF_ERR_INVALID_ARG, "bad border");
     if (j->order < 1 || j->order > 3) return fail(c, BSF_ERR_INVALID_ARG, "order must be 1, 2 or 3");
     if (j->model < -1 || j->model > 1) return fail(c, BSF_ERR_INVALID_ARG, "model degree must be -1, 0 or 1");
-    const int n = j->order, D = j->order + j->model;
+    if (j->path != BSF_PATH_F64 && j->path != BSF_PATH_F32_TILED) return fail(c, BSF_ERR_INVALID_ARG, "bad path");
+    const int n = j->order, D = j->order + j->model, path = (int)j->path;
     const double limit = filter1d_max_scale(c, n, D);
     double a_max = j->a_max;
     if (!(a_max == 0.0 || (a_max >= 0.5 && a_max <= 1e4)))
@@ -2513,7 +2524,8 @@ bsf_status bsf_filter1d(bsf_ctx* c, const bsf_job1d* j, void* stream) {
     A.err = c->d_err;
     hipError_t e = hipSetDevice(c->device);
     if (e == hipSuccess)
-        e = dispatch_filter1d(n, D, A, (int)(tiles * j->count), bsf::f1d::lds_bytes(D, A.W), (hipStream_t)stream);
+        e = dispatch_filter1d(n, D, path, A, (int)(tiles * j->count), bsf::f1d::lds_bytes(D, A.W, path),
+                              (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(c, e, "filter1d launch");
     return BSF_OK;
 }

@@ -62,7 +62,11 @@ __host__ inline int window_len(int n, int D, double a_max) {
     const int right = (int)std::ceil(std::max(a_max - 1.0, 0.0) * n * 0.5 + 0.5 * (D + 1)) + 1;
     return kT + window_left(n, D, a_max) + right;
 }
-__host__ inline long long lds_bytes(int D, int W) { return 16ll * W * (D + 2); }
+// LDS of a workgroup: the running sums (a pair per position), then the interpolant tables:
+// D+1 pairs per position on the float64 path, D+1 doubles on the float32-output path.
+__host__ inline long long lds_bytes(int D, int W, int path) {
+    return 16ll * W + (path == 0 ? 16ll : 8ll) * W * (D + 1);
+}
 
 struct cpair {
     double s, c;
@@ -93,7 +97,7 @@ struct Args {
     long long in_pitch;
     const float* scales;
     long long sc_pitch;
-    double* out;
+    void* out;  // float64 (path 0) or float32 (path 1)
     long long out_pitch;
     int length, tiles, dtype, border, left, W;
     float a_max;
@@ -140,12 +144,16 @@ __device__ __forceinline__ void load_window(const Args& A, const T* row, int P, 
     }
 }
 
-template <int N, int D>
+// PATH 0: float64 output, every step compensated.  PATH 1: float32 output; the running sums
+// stay compensated (they carry the largest magnitudes), the tables and the mask are plain
+// float64 (their rounding errors are of order 2^-53 of the sums, far below float32).
+template <int N, int D, int PATH>
 __global__ __launch_bounds__(kThreads) void filter1d_kernel(Args A) {
     extern __shared__ double4 f1d_lds[];
     const int W = A.W;
-    double2* tab = reinterpret_cast<double2*>(f1d_lds);  // [D+1][W] (s, c) of G_e
-    double2* gbuf = tab + (D + 1) * W;                    // [W] samples, then running sums
+    double2* gbuf = reinterpret_cast<double2*>(f1d_lds);  // [W] samples, then running sums
+    double2* tab = gbuf + W;                               // PATH 0: [D+1][W] (s, c) of G_e
+    double* tabd = reinterpret_cast<double*>(gbuf + W);    // PATH 1: [D+1][W] G_e
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int b = blockIdx.x / A.tiles;
@@ -208,6 +216,15 @@ __global__ __launch_bounds__(kThreads) void filter1d_kernel(Args A) {
             }
             pre = shfl_up_cp(tot, 1);
             if (lane == 0) pre = {0.0, 0.0};
+            // Anchor this fold at the window centre: subtract its value at position ctr (the
+            // owner lane's prefix plus its local sum there) from every prefix.  The later folds
+            // turn that constant into a polynomial of degree < n, which the mask annihilates;
+            // the sums the mask cancels shrink by about 2^n.
+            const int ctr = W / 2 - 1;
+            const double2 xc = gbuf[ctr];
+            const cpair owner_pre = {__shfl(pre.s, ctr / C, 64), __shfl(pre.c, ctr / C, 64)};
+            const cpair anchor = cp_sum(owner_pre, {xc.x, xc.y});
+            pre = cp_sum(pre, {-anchor.s, -anchor.c});
         }
         for (int i = lo; i < hi; ++i) {
             const double2 x = gbuf[i];
@@ -218,29 +235,50 @@ __global__ __launch_bounds__(kThreads) void filter1d_kernel(Args A) {
     __syncthreads();
 
     // ---- lattice tables G_e[p] = sum_l A[l][e] g[p - l] (the 1/D! is applied last) ---------
-#pragma unroll 2
-    for (int p = tid + D; p < W; p += kThreads) {
-        cpair G[D + 1];
-        bool seeded[D + 1];
+    if (PATH == 1) {
+        for (int p = tid + D; p < W; p += kThreads) {
+            double g[D + 1];
 #pragma unroll
-        for (int e = 0; e <= D; ++e) {
-            G[e] = {0.0, 0.0};
-            seeded[e] = false;
-        }
-#pragma unroll
-        for (int l = 0; l <= D; ++l) {
-            const double2 x = gbuf[p - l];
-            const cpair gl = {x.x, x.y};
+            for (int l = 0; l <= D; ++l) {
+                const double2 x = gbuf[p - l];
+                g[l] = x.x + x.y;
+            }
 #pragma unroll
             for (int e = 0; e <= D; ++e) {
-                const long long w = lattice_coef(D, l, e);
-                if (w == 0) continue;
-                G[e] = seeded[e] ? cp_add_weighted(G[e], w, gl) : cp_weighted(w, gl);
-                seeded[e] = true;
+                double G = 0.0;
+#pragma unroll
+                for (int l = 0; l <= D; ++l) {
+                    const long long w = lattice_coef(D, l, e);
+                    if (w != 0) G = __fma_rn((double)w, g[l], G);
+                }
+                tabd[e * W + p] = G;
             }
         }
+    } else {
+#pragma unroll 2
+        for (int p = tid + D; p < W; p += kThreads) {
+            cpair G[D + 1];
+            bool seeded[D + 1];
 #pragma unroll
-        for (int e = 0; e <= D; ++e) tab[e * W + p] = make_double2(G[e].s, G[e].c);
+            for (int e = 0; e <= D; ++e) {
+                G[e] = {0.0, 0.0};
+                seeded[e] = false;
+            }
+#pragma unroll
+            for (int l = 0; l <= D; ++l) {
+                const double2 x = gbuf[p - l];
+                const cpair gl = {x.x, x.y};
+#pragma unroll
+                for (int e = 0; e <= D; ++e) {
+                    const long long w = lattice_coef(D, l, e);
+                    if (w == 0) continue;
+                    G[e] = seeded[e] ? cp_add_weighted(G[e], w, gl) : cp_weighted(w, gl);
+                    seeded[e] = true;
+                }
+            }
+#pragma unroll
+            for (int e = 0; e <= D; ++e) tab[e * W + p] = make_double2(G[e].s, G[e].c);
+        }
     }
     __syncthreads();
 
@@ -250,14 +288,37 @@ __global__ __launch_bounds__(kThreads) void filter1d_kernel(Args A) {
     for (int q = 0; q < kPerThread; ++q) {
         const int m = m0 + tid + q * kThreads;
         if (m >= L) continue;
-        double* dst = A.out + (long long)b * A.out_pitch + m;
+        const long long o = (long long)b * A.out_pitch + m;
         if (!(af[q] >= 0.5f && af[q] <= A.a_max)) {  // false for NaN
             bad = true;
-            *dst = __builtin_nan("");
+            if (PATH == 1) static_cast<float*>(A.out)[o] = __builtin_nanf("");
+            else static_cast<double*>(A.out)[o] = __builtin_nan("");
             continue;
         }
         const double a = af[q];
         const double u0 = (double)(m - P) + (a - 1.0) * (0.5 * N) + 0.5 * (D + 1);
+        // a^n D!: a^2 is exact (48 bits), a^3 and the factorial round once each
+        double den = a;
+#pragma unroll
+        for (int i = 1; i < N; ++i) den *= a;
+        den *= (double)factorial(D);
+        if (PATH == 1) {
+            double acc = 0.0;
+#pragma unroll
+            for (int j = 0; j <= N; ++j) {
+                const double u = __fma_rn(-a, (double)j, u0);
+                const double pc = ceil(u) - 1.0;
+                const double t = u - pc;
+                int p = (int)pc;
+                p = p < D ? D : (p > W - 1 ? W - 1 : p);
+                double val = tabd[D * W + p];
+#pragma unroll
+                for (int e = D - 1; e >= 0; --e) val = __fma_rn(val, t, tabd[e * W + p]);
+                acc = j == 0 ? val : __fma_rn((double)(((j & 1) ? -1 : 1) * binom(N, j)), val, acc);
+            }
+            static_cast<float*>(A.out)[o] = (float)(acc / den);
+            continue;
+        }
         cpair acc = {0.0, 0.0};
 #pragma unroll
         for (int j = 0; j <= N; ++j) {
@@ -275,12 +336,7 @@ __global__ __launch_bounds__(kThreads) void filter1d_kernel(Args A) {
             }
             acc = j == 0 ? val : cp_add_weighted(acc, ((j & 1) ? -1 : 1) * binom(N, j), val);
         }
-        // a^n D!: a^2 is exact (48 bits), a^3 and the factorial round once each
-        double den = a;
-#pragma unroll
-        for (int i = 1; i < N; ++i) den *= a;
-        den *= (double)factorial(D);
-        *dst = (acc.s + acc.c) / den;
+        static_cast<double*>(A.out)[o] = (acc.s + acc.c) / den;
     }
     const unsigned long long bb = __ballot(bad);
     if (bb && lane == __ffsll((long long)bb) - 1) atomicOr(A.err, kErrScale);

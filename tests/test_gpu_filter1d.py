@@ -14,6 +14,7 @@ from paper_0908_3861_amd import synth
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-12
+F32_TOL = 1e-5  # the float32-output path's stated bound
 MODELS = [(n, n1) for n in (1, 2, 3) for n1 in (-1, 0, 1)]
 
 
@@ -30,12 +31,13 @@ def rel_max(s, o):
     return float(np.abs(s - o).max() / max(np.abs(o).max(), 1e-300))
 
 
-def run(torch, sig, sc, n, n1, border="clamp", a_max=None, check=True):
+def run(torch, sig, sc, n, n1, border="clamp", a_max=None, check=True, path="f64"):
     from paper_0908_3861_amd import binding
     dev = torch.device("cuda:0")
     out = binding.filter1d(torch.from_numpy(np.ascontiguousarray(sig)).to(dev),
-                           torch.from_numpy(np.ascontiguousarray(sc)).to(dev), n, n1, border, a_max, check=check)
-    return out.cpu().numpy()
+                           torch.from_numpy(np.ascontiguousarray(sc)).to(dev), n, n1, border, a_max, check=check,
+                           path=path)
+    return out.cpu().numpy().astype(np.float64)
 
 
 @pytest.mark.parametrize("n,n1", MODELS)
@@ -156,6 +158,67 @@ def test_largest_windows(torch_dev, n, n1):
     pts += [(int(b), int(m)) for b, m in zip(pr.integers(0, count, 40), pr.integers(0, L, 40))]
     o = F.filter1d_batch(sig, sc, n, n1, "zero", pts)
     assert rel_max(np.array([s[b, m] for b, m in pts]), o) < TOL
+
+
+@pytest.mark.parametrize("n,n1", MODELS)
+def test_f32_path_every_order_and_model(torch_dev, n, n1):
+    """The float32-output path (compensated running sums, plain float64 mask) against the
+    same exact oracle, at its stated bound; smallest scales (the mask's largest gain) and
+    scales up to 12 on ragged signals."""
+    rng = np.random.default_rng(1900 + 3 * n + n1)
+    count, L = 2, 1100
+    sig = synth.unit_grid_image(rng, count, L, np.float32)
+    sc = rng.uniform(0.5, 12.0, size=(count, L)).astype(np.float32)
+    sc[0, :300] = 0.5
+    s = run(torch_dev, sig, sc, n, n1, path="f32tiled")
+    o = F.filter1d_batch(sig, sc, n, n1, "clamp")
+    err = rel_max(s, o)
+    print(f"f32 path, order {n} model {n1}: rel_max {err:.2e}")
+    assert err < F32_TOL
+
+
+@pytest.mark.parametrize("n,n1", [(1, -1), (3, 1), (3, -1)])
+def test_f32_path_largest_windows(torch_dev, n, n1):
+    torch = torch_dev
+    from paper_0908_3861_amd import binding
+    lim = binding.filter1d_max_scale(n, n1)
+    rng = np.random.default_rng(1994 + n + n1)
+    count, L = 2, 1300
+    sig = rng.integers(0, 256, size=(count, L)).astype(np.uint8)
+    sc = rng.uniform(0.5, lim, size=(count, L)).astype(np.float32)
+    sc[1, :5] = np.float32(lim)
+    s = run(torch, sig, sc, n, n1, "zero", a_max=lim, path="f32tiled")
+    pr = np.random.default_rng(7)
+    pts = [(1, 0), (1, 4), (0, L - 1), (0, 255), (0, 256)]
+    pts += [(int(b), int(m)) for b, m in zip(pr.integers(0, count, 40), pr.integers(0, L, 40))]
+    o = F.filter1d_batch(sig, sc, n, n1, "zero", pts)
+    err = rel_max(np.array([s[b, m] for b, m in pts]), o)
+    print(f"f32 path, largest windows, order {n} model {n1}: rel_max {err:.2e}")
+    assert err < F32_TOL
+
+
+def test_f32_path_scale_errors_and_padding(torch_dev):
+    torch = torch_dev
+    from paper_0908_3861_amd import binding
+    rng = np.random.default_rng(1995)
+    count, L, pitch = 2, 700, 768
+    sig = synth.unit_grid_image(rng, count, pitch, np.float64)
+    sc = rng.uniform(1.0, 6.0, size=(count, pitch)).astype(np.float32)
+    sc[1, 77] = np.inf
+    dev = torch.device("cuda:0")
+    out = torch.full((count, pitch), 3.0, dtype=torch.float32, device=dev)
+    ctx = binding.default_context(0)
+    binding.filter1d(torch.from_numpy(sig).to(dev)[:, :L], torch.from_numpy(sc).to(dev)[:, :L], 2, 0, "clamp",
+                     a_max=6.0, out=out[:, :L], path="f32tiled")
+    assert ctx.device_error() == 5
+    got = out.cpu().numpy().astype(np.float64)
+    assert np.all(got[:, L:] == 3.0) and np.isnan(got[1, 77])
+    good = sc[:, :L].copy()
+    good[1, 77] = 1.0
+    o = F.filter1d_batch(sig[:, :L], good, 2, 0, "clamp")
+    mask = np.ones((count, L), bool)
+    mask[1, 77] = False
+    assert rel_max(got[:, :L][mask], o[mask]) < F32_TOL
 
 
 def test_full_size_sampled(torch_dev):
