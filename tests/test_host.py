@@ -96,3 +96,28 @@ def test_rep3_groups_header_is_current(tmp_path):
     subprocess.run([sys.executable, os.path.join(csrc, "gen_rep_groups.py"), "--out", str(out)], check=True,
                    capture_output=True)
     assert out.read_text() == open(os.path.join(csrc, "rep3_groups.h")).read()
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """The ctypes job structures have the C layout of include/bsf.h (field offsets and size),
+    checked by compiling the header with gcc."""
+    from paper_0908_3861_amd import binding
+    structs = {"bsf_job": binding.Job, "bsf_job1d": binding.Job1d}
+    rename = {"in_": "in"}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", f'#include "{HDR}"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            c = rename.get(fname, fname)
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {c}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-o", str(exe), str(src)], check=True, capture_output=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
