@@ -253,3 +253,30 @@ def test_full_size_reproduces_linear_signals(torch_dev):
         inner = slice(64, L - 64)
         err = np.abs(s[:, inner] - ramp[:, inner]).max() / np.abs(ramp).max()
         assert err < TOL, (n, n1, err)
+
+
+def test_distinct_pitches_and_many_short_signals(torch_dev):
+    """Signals, scales and output with three different row pitches; then 3000 signals of 7
+    samples (one tile each, the signal index taken from the workgroup index)."""
+    torch = torch_dev
+    from paper_0908_3861_amd import binding
+    rng = np.random.default_rng(996)
+    dev = torch.device("cuda:0")
+    count, L = 3, 600
+    sig = synth.unit_grid_image(rng, count, 1000, np.float32)
+    sc = rng.uniform(0.5, 9.0, size=(count, 1024)).astype(np.float32)
+    out = torch.full((count, 960), -1.0, dtype=torch.float64, device=dev)
+    binding.filter1d(torch.from_numpy(sig).to(dev)[:, :L], torch.from_numpy(sc).to(dev)[:, :L], 2, 1, "zero",
+                     a_max=9.0, out=out[:, :L], check=True)
+    got = out.cpu().numpy()
+    assert np.all(got[:, L:] == -1.0)
+    assert rel_max(got[:, :L], F.filter1d_batch(sig[:, :L], sc[:, :L], 2, 1, "zero")) < TOL
+    count, L = 3000, 7
+    sig = synth.unit_grid_image(rng, count, L, np.float64)
+    sc = rng.uniform(0.5, 4.0, size=(count, L)).astype(np.float32)
+    s = run(torch, sig, sc, 3, -1, a_max=4.0)
+    rows = [0, 1, 1234, 2999]
+    o = F.filter1d_batch(sig[rows], sc[rows], 3, -1, "clamp")
+    assert rel_max(s[rows], o) < TOL
+    s32 = run(torch, sig, sc, 3, -1, a_max=4.0, path="f32tiled")
+    assert rel_max(s32[rows], o) < F32_TOL
