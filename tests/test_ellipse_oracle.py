@@ -2,6 +2,7 @@
 compute itself: the box spline's own moments, Theorem 4.3's isotropic scales, a library
 bounded least-squares solver, and the symmetries of the direction set."""
 import math
+import warnings
 
 import numpy as np
 import pytest
@@ -99,3 +100,43 @@ def test_symmetries_of_the_direction_set():
         c = E.scales_from_ellipse(s1, s2, phi + math.pi, n)
         assert np.allclose(b, [a[2], a[1], a[0], a[3]], rtol=1e-9, atol=1e-12)
         assert np.allclose(c, a, rtol=1e-9, atol=1e-12)
+
+
+def test_tie_break_least_sum_of_fourth_powers_on_anisotropic_ellipses():
+    """A reachable ellipse fixes three moments of four scales: the exact solutions form a
+    segment (one free parameter, t = (w2 + w4)/2 in w = a^2).  The oracle must return the
+    point of that segment with the least sum a_k^4 = sum w_k^2, subject to a_k >= 0.5.  Pinned
+    against a general-purpose constrained minimiser (SciPy SLSQP on sum w^2 under the three
+    moment equalities and the bounds), on anisotropic ellipses at many angles, including ones
+    where the bound a_k >= 0.5 is active and ones where it is not."""
+    from scipy.optimize import minimize
+    rng = np.random.default_rng(10)
+    checked = active = 0
+    for _ in range(60):
+        n = int(rng.integers(1, 4))
+        s1 = float(rng.uniform(1.0, 9.0))
+        s2 = s1 * float(rng.uniform(0.35, 0.95))
+        phi = float(rng.uniform(0, math.pi))
+        S = E.target_covariance(s1, s2, phi)
+        t = (n / 12.0) * E.direction_tensors()
+        b = np.array([S[0, 0], S[0, 1], S[1, 1]])
+        a = E.scales_from_ellipse(s1, s2, phi, n)
+        C = E.covariance_of_scales(a, n)
+        if np.abs(C - S).max() > 1e-10 * np.abs(S).max():
+            continue  # not reachable: the projection is pinned elsewhere
+        # in units of the target's size, so that the solver's tolerances are relative
+        unit = float(np.trace(S)) * 12.0 / n
+        tt, bb = t * 12.0 / n, b * 12.0 / (n * unit)
+        with warnings.catch_warnings():
+            warnings.simplefilter("ignore", RuntimeWarning)  # SLSQP clips its trial steps to the bounds
+            res = minimize(lambda w: float(np.dot(w, w)), np.full(4, 0.5), jac=lambda w: 2.0 * w, method="SLSQP",
+                           bounds=[(0.25 / unit, None)] * 4,
+                           constraints=[{"type": "eq", "fun": lambda w: tt @ w - bb, "jac": lambda w: tt}],
+                           options={"ftol": 1e-14, "maxiter": 1000})
+        assert res.success, res.message
+        assert np.abs(tt @ res.x - bb).max() < 1e-9
+        w = a * a / unit
+        assert np.allclose(w, res.x, rtol=1e-6, atol=1e-7), (s1, s2, phi, n, w, res.x)
+        checked += 1
+        active += int(np.min(a) < 0.5 * (1 + 1e-9))
+    assert checked >= 30 and active >= 1 and checked - active >= 5, (checked, active)

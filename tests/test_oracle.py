@@ -188,6 +188,46 @@ def test_filter_mirror_and_transpose(oracle_mod):
         assert np.abs(sz - s).max() > 1e-3
 
 
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_zero_border_is_clamp_on_a_zero_frame(oracle_mod, n):
+    """The zero border rule, pinned through the clamp rule: embedding the image in a frame of
+    zeros wider than every pixel's support makes clamp-to-edge read zeros wherever the zero
+    rule would, and only there.  A wrong edge index, a one-sided or off-by-one zero region in
+    the zero branch, would break the equality (it is exact: the same terms in the same order)."""
+    rng = np.random.default_rng(40 + n)
+    H, W = 9, 11
+    img = rng.uniform(0.5, 1.5, size=(H, W))
+    sc = rng.uniform(0.5, 3.5, size=(H, W, 4)).astype(np.float32)
+    R = int(math.ceil(0.5 * n * (3.5 + 2 * 3.5 / S2))) + 2   # beyond every support radius
+    big = np.zeros((H + 2 * R, W + 2 * R))
+    big[R:R + H, R:R + W] = img
+    bsc = np.ones((H + 2 * R, W + 2 * R, 4), np.float32)
+    bsc[R:R + H, R:R + W] = sc
+    sz = oracle_mod.filter(img, sc, n, "zero")
+    sc_frame = oracle_mod.filter(big, bsc, n, "clamp")[R:R + H, R:R + W]
+    assert np.array_equal(sz, sc_frame)
+    # and the zero rule really differs from clamp at the edges (so the frame matters)
+    assert np.abs(sz - oracle_mod.filter(img, sc, n, "clamp")).max() > 1e-2
+
+
+def test_zero_border_mirror_and_transpose(oracle_mod):
+    """The symmetries of the filter hold under the zero rule too: mirroring k1 swaps the two
+    diagonal scales, transposing swaps a1 and a3 (the direction set maps onto itself); the
+    zero frame is symmetric, so an asymmetric zero region would break them."""
+    rng = np.random.default_rng(44)
+    H, W = 7, 10
+    img = rng.uniform(0, 1, size=(H, W))
+    sc = rng.uniform(0.5, 3, size=(H, W, 4)).astype(np.float32)
+    for n in (1, 2, 3):
+        s = oracle_mod.filter(img, sc, n, "zero")
+        sm = oracle_mod.filter(img[:, ::-1].copy(), sc[:, ::-1][..., [0, 3, 2, 1]].copy(), n, "zero")
+        assert np.abs(sm[:, ::-1] - s).max() < 1e-14
+        st = oracle_mod.filter(img.T.copy(), sc.transpose(1, 0, 2)[..., [2, 1, 0, 3]].copy(), n, "zero")
+        assert np.abs(st.T - s).max() < 1e-14
+        s180 = oracle_mod.filter(img[::-1, ::-1].copy(), sc[::-1, ::-1].copy(), n, "zero")
+        assert np.abs(s180[::-1, ::-1] - s).max() < 1e-14
+
+
 def test_filter_sampled_pixels_match_full(oracle_mod):
     rng = np.random.default_rng(11)
     img = rng.uniform(0, 1, size=(12, 13))
