@@ -55,8 +55,7 @@ typedef enum {
     BSF_ERR_HIP = 3,           /* a HIP runtime call failed; bsf_last_error has the text  */
     BSF_ERR_UNSUPPORTED = 4,   /* a restart window does not fit the on-chip memory        */
     BSF_ERR_SCALE_RANGE = 5,   /* a scale is not finite or lies outside [0.5, 1e4]        */
-    BSF_ERR_RANGE = 6,         /* a pre-integrated value left the exact integer range     */
-    BSF_ERR_INEXACT_INPUT = 7  /* reserved (not raised)                                     */
+    BSF_ERR_RANGE = 6          /* a pre-integrated value left the exact integer range     */
 } bsf_status;
 
 typedef enum { BSF_U8 = 0, BSF_F32 = 1, BSF_F64 = 2 } bsf_dtype;
@@ -91,14 +90,21 @@ typedef struct {
 } bsf_job;
 
 /* Create a context on HIP device `hip_device`.  `workspace_limit_bytes` caps the device
- * memory the context may allocate for its own workspace (0 = 16 GiB).  The context owns
- * its workspace and a small sticky error word; it is used by one host thread at a time. */
+ * memory the context may hold for its own workspace (0 = 16 GiB): a ring of eight work
+ * areas, so that calls on different streams can be in flight together, whose total stays
+ * within the limit.  A call whose own work area would exceed the limit returns
+ * BSF_ERR_OUT_OF_MEMORY.  The context owns its workspace and a small sticky error word; it
+ * is used by one host thread at a time. */
 bsf_status bsf_create(bsf_ctx** ctx, int hip_device, size_t workspace_limit_bytes);
 
 /* Release everything the context owns.  Waits for nothing: synchronise first. */
 bsf_status bsf_destroy(bsf_ctx* ctx);
 
-/* Device workspace one bsf_filter call on `job` needs, in bytes (host only). */
+/* Device work area one bsf_filter call on `job` needs, in bytes (host only, no device
+ * needed).  It is computed with the launch plan bsf_filter makes, taking the LDS of an
+ * MI355X conservatively, so it is never below what the call asks of its context's
+ * workspace on such a device (0 when every tile's window fits half of a workgroup's LDS).
+ * A workspace limit of at least this size lets the call run. */
 bsf_status bsf_workspace_size(const bsf_job* job, size_t* bytes);
 
 /* out[m] = s[m] for every pixel (Section 6 projections computed by the two steps of

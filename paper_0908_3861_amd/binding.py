@@ -19,7 +19,7 @@ U8, F32, F64 = 0, 1, 2
 PATHS = {"f64": 0, "f32tiled": 1}
 BORDERS = {"clamp": 0, "zero": 1}
 STATUS = {0: "ok", 1: "invalid argument", 2: "out of memory", 3: "HIP error", 4: "unsupported",
-          5: "scale out of range", 6: "integer range exceeded", 7: "inexact float input"}
+          5: "scale out of range", 6: "integer range exceeded"}
 
 
 class BsfError(RuntimeError):

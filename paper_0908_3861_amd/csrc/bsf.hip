@@ -22,6 +22,7 @@
 #include "../../include/bsf.h"
 #include "bsf_device.h"
 #include "filter1d.h"
+#include "plan.h"
 #include "rep3_groups.h"
 
 namespace bsf {
@@ -1778,6 +1779,13 @@ struct bsf_ctx {
     long long lds_max_bytes = 0;   // LDS a workgroup may hold
     long long lds_static[4] = {1024, 1024, 1024, 1024};  // per order: the largest static LDS of its kernels, plus a margin
     std::string last;
+    bsf_plan::Limits limits() const {
+        bsf_plan::Limits L{};
+        L.lds_max = lds_max_bytes;
+        for (int n = 0; n < 4; ++n) L.lds_static[n] = lds_static[n];
+        L.cus = cus;
+        return L;
+    }
 };
 
 namespace {
@@ -1812,7 +1820,7 @@ bsf_status validate(bsf_ctx* c, const bsf_job* j, bool need_out) {
     if (j->out_pitch < j->width) return fail(c, BSF_ERR_INVALID_ARG, "out_pitch < width");
     if (j->path != BSF_PATH_F64 && j->path != BSF_PATH_F32_TILED)
         return fail(c, BSF_ERR_INVALID_ARG, "unknown path");
-    if (!(j->a_max >= 0.0f) || j->a_max > (float)kScaleMax)
+    if (!(j->a_max == 0.0f || (j->a_max >= (float)kScaleMin && j->a_max <= (float)kScaleMax)))
         return fail(c, BSF_ERR_INVALID_ARG, "a_max must be 0 or a bound in [0.5, 1e4]");
     return BSF_OK;
 }
@@ -1840,48 +1848,15 @@ void allow_big_lds(K* kernel) {
     (void)hipGetLastError();
 }
 
-// Window capacities of the three launch tiers: tier 1 half the LDS (two workgroups per
-// CU), tier 2 the full LDS, tier 3 a per-workgroup slice of global scratch.
-struct Plan {
-    long long t1 = 0, t2 = 0, t3 = 0;
-    bool use2 = false, use3 = false;
-};
+using bsf_plan::Plan;
+using bsf_plan::WorkLayout;
 
-Plan plan_tiers(const bsf_ctx* c, long long need, int order) {
-    const long long full = (c->lds_max_bytes - c->lds_static[order]) / 8;
-    const long long half = (c->lds_max_bytes / 2 - c->lds_static[order]) / 8;
-    Plan p;
-    if (need <= half) {
-        p.t1 = need;
-    } else if (need <= full) {
-        p.t1 = half;
-        p.t2 = need;
-        p.use2 = true;
-    } else {
-        p.t1 = half;
-        p.t2 = full;
-        p.t3 = need;
-        p.use2 = p.use3 = true;
-    }
-    return p;
-}
+Plan plan_tiers(const bsf_ctx* c, long long need, int order) { return bsf_plan::plan_tiers(c->limits(), need, order); }
 
-int per_cu(const bsf_ctx* c, long long elems, int order) {
-    return (int)std::max(1ll, c->lds_max_bytes / (elems * 8 + c->lds_static[order]));
-}
-
-// Device work area of one call: counters | list A | list B | job descriptors | scratch.
-struct WorkLayout {
-    size_t lists_off = 256, listb_off = 0, jobs_off = 0, scratch_off = 0, total = 0;
-};
+int per_cu(const bsf_ctx* c, long long elems, int order) { return bsf_plan::per_cu(c->limits(), elems, order); }
 
 WorkLayout work_layout(long long items, int njobs, size_t scratch_bytes) {
-    WorkLayout w;
-    w.listb_off = w.lists_off + (size_t)items * sizeof(int2);
-    w.jobs_off = ((w.listb_off + (size_t)items * sizeof(int2)) + 63) & ~(size_t)63;
-    w.scratch_off = ((w.jobs_off + (size_t)njobs * sizeof(JobDesc)) + 255) & ~(size_t)255;
-    w.total = w.scratch_off + scratch_bytes;
-    return w;
+    return bsf_plan::work_layout(items, njobs, sizeof(JobDesc), scratch_bytes);
 }
 
 struct Tiers {
@@ -1895,7 +1870,7 @@ struct Tiers {
 // whose counters are ctr[0..4]: [0] list A count, [1] list A cursor, [2] tier-1 cursor,
 // [3] list B count, [4] list B cursor.
 Tiers make_tiers_at(const bsf_ctx* c, const Plan& p, unsigned* ctr, int2* la, int2* lb, long long* scratch,
-                    long long items, int order) {
+                    long long items, int order, long long grid3 = 0) {
     Tiers t;
     t.L1 = Launch{};
     t.L1.lds_cap = p.t1;
@@ -1917,16 +1892,17 @@ Tiers make_tiers_at(const bsf_ctx* c, const Plan& p, unsigned* ctr, int2* la, in
         t.L2.push_list = lb;
         t.L2.push_cap = (int)items;
         t.inB = ItemList{ctr + 3, lb, ctr + 4, (int)items};
-        t.grid3 = (int)std::min<long long>(items, (long long)c->cus * 2);
+        t.grid3 = (int)(grid3 > 0 ? grid3 : bsf_plan::grid3_of(c->limits(), items));
         t.scratch = scratch;
     }
     return t;
 }
 
-Tiers make_tiers(const bsf_ctx* c, const Plan& p, char* work, const WorkLayout& w, long long items, int order) {
+Tiers make_tiers(const bsf_ctx* c, const Plan& p, char* work, const WorkLayout& w, long long items, int order,
+                 long long grid3 = 0) {
     if (!work) return make_tiers_at(c, p, nullptr, nullptr, nullptr, nullptr, items, order);  // tier 1 only
     return make_tiers_at(c, p, (unsigned*)work, (int2*)(work + w.lists_off), (int2*)(work + w.listb_off),
-                         (long long*)(work + w.scratch_off), items, order);
+                         (long long*)(work + w.scratch_off), items, order, grid3);
 }
 
 template <int N, int PATH>
@@ -2007,23 +1983,28 @@ long long job_window_need(const bsf_ctx* c, const bsf_job* j) {
 }
 
 // Take the next ring slot, wait until its previous call has finished on the device,
-// and make sure it holds `bytes` of device memory and `njobs` pinned descriptors.
+// and make sure it holds `bytes` of device memory and `njobs` pinned descriptors.  The
+// ring's device memory never exceeds the context's workspace limit (bsf_plan::ring_growth):
+// a slot that grows takes the other slots along while the limit allows, and releases them
+// when it does not.
 bsf_status acquire_slot(bsf_ctx* c, size_t bytes, int njobs, int& idx) {
-    if (bytes > c->ws_limit) return fail(c, BSF_ERR_OUT_OF_MEMORY, "tile work list exceeds the workspace limit");
     idx = c->slot_next;
+    size_t cur[bsf_ctx::kRing], target[bsf_ctx::kRing];
+    for (int r = 0; r < bsf_ctx::kRing; ++r) cur[r] = c->slot[r].dev_bytes;
+    if (!bsf_plan::ring_growth(cur, idx, bytes, c->ws_limit, target))
+        return fail(c, BSF_ERR_OUT_OF_MEMORY,
+                    "the call needs " + std::to_string(bytes) + " bytes of workspace, more than the context's limit of " +
+                        std::to_string(c->ws_limit));
     c->slot_next = (idx + 1) % bsf_ctx::kRing;
     bsf_ctx::Slot& sl = c->slot[idx];
     hipError_t e = hipEventSynchronize(sl.done);
     if (e != hipSuccess) return hip_fail(c, e, "waiting for a work slot");
-    if (bytes > sl.dev_bytes) {
-        // a larger work area: grow every slot of the ring now (each after its in-flight
-        // work), so that calls of this size never allocate again; only this slot when the
-        // whole ring would exceed the workspace limit
-        const size_t cap = std::max(bytes, (size_t)1 << 16);
-        const bool all = cap * (size_t)bsf_ctx::kRing <= c->ws_limit;
+    // shrink first (so the total stays within the limit at every step), then grow
+    for (int pass = 0; pass < 2; ++pass)
         for (int r = 0; r < bsf_ctx::kRing; ++r) {
             bsf_ctx::Slot& o = c->slot[r];
-            if ((!all && r != idx) || o.dev_bytes >= cap) continue;
+            const bool shrink = target[r] < o.dev_bytes, grow = target[r] > o.dev_bytes;
+            if (!(pass == 0 ? shrink : grow)) continue;
             if (r != idx) {
                 e = hipEventSynchronize(o.done);
                 if (e != hipSuccess) return hip_fail(c, e, "waiting for a work slot");
@@ -2031,11 +2012,12 @@ bsf_status acquire_slot(bsf_ctx* c, size_t bytes, int njobs, int& idx) {
             if (o.dev) (void)hipFree(o.dev);
             o.dev = nullptr;
             o.dev_bytes = 0;
-            e = hipMalloc(&o.dev, cap);
-            if (e != hipSuccess) return hip_fail(c, e, "work list allocation");
-            o.dev_bytes = cap;
+            if (target[r] > 0) {
+                e = hipMalloc(&o.dev, target[r]);
+                if (e != hipSuccess) return hip_fail(c, e, "work area allocation");
+                o.dev_bytes = target[r];
+            }
         }
-    }
     if (njobs > sl.host_cap) {
         if (sl.host) (void)hipHostFree(sl.host);
         sl.host = nullptr;
@@ -2046,8 +2028,6 @@ bsf_status acquire_slot(bsf_ctx* c, size_t bytes, int njobs, int& idx) {
     }
     return BSF_OK;
 }
-
-
 
 template <typename K>
 void static_lds(K* kernel, long long& mx) {
@@ -2179,7 +2159,6 @@ const char* bsf_status_string(bsf_status s) {
         case BSF_ERR_UNSUPPORTED: return "unsupported (window exceeds on-chip memory, or order)";
         case BSF_ERR_SCALE_RANGE: return "scale out of range";
         case BSF_ERR_RANGE: return "pre-integrated value out of the exact integer range";
-        case BSF_ERR_INEXACT_INPUT: return "reserved";
     }
     return "unknown status";
 }
@@ -2254,15 +2233,12 @@ bsf_status bsf_workspace_size(const bsf_job* job, size_t* bytes) {
     if (!bytes) return BSF_ERR_INVALID_ARG;
     bsf_status s = validate(nullptr, job, true);
     if (s != BSF_OK) return s;
-    // the windows live on chip; the only device memory is the work list of tiles that
-    // need the second, larger-LDS launch
+    // the plan bsf_filter makes, with the limits of an MI355X taken conservatively (a
+    // larger static-LDS reserve moves windows to the next tier sooner, never later)
+    const bsf_plan::Limits L = bsf_plan::gfx950_bound();
     const long long tiles = (long long)((job->width + kTile - 1) / kTile) * ((job->height + kTile - 1) / kTile);
-    // an MI355X workgroup holds at most 160 KiB of LDS; larger windows use global scratch
-    // slices for up to two workgroups per CU (256 CUs)
-    const long long full = (163840 - 1024) / 8;
-    const long long need = job->a_max > 0.0f ? window_bound(job->order, job->a_max) + 64 : full;
-    const size_t scratch = need > full ? (size_t)std::min<long long>(tiles, 512) * (size_t)need * 8 : 0;
-    *bytes = work_layout(tiles, 0, scratch).total;
+    const long long need = job->a_max > 0.0f ? window_bound(job->order, job->a_max) + 64 : bsf_plan::full_cap(L, job->order);
+    *bytes = bsf_plan::single_call_bytes(L, bsf_plan::plan_tiers(L, need, job->order), tiles);
     return BSF_OK;
 }
 
@@ -2271,6 +2247,8 @@ bsf_status bsf_filter(bsf_ctx* c, const bsf_job* j, void* stream) {
     bsf_status s = validate(c, j, true);
     if (s != BSF_OK) return s;
     const Plan p = plan_tiers(c, job_window_need(c, j), j->order);
+    if (!bsf_plan::plan_fits(c->limits(), p, j->order))
+        return fail(c, BSF_ERR_UNSUPPORTED, "the launch's LDS exceeds the device's limit");
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
@@ -2279,8 +2257,8 @@ bsf_status bsf_filter(bsf_ctx* c, const bsf_job* j, void* stream) {
     Tiers t;
     int slot = -1;
     if (p.use2) {
-        const int grid3 = (int)std::min<long long>(tiles, (long long)c->cus * 2);
-        const WorkLayout w = work_layout(tiles, 0, p.use3 ? (size_t)grid3 * (size_t)p.t3 * 8 : 0);
+        const WorkLayout w =
+            work_layout(tiles, 0, p.use3 ? (size_t)bsf_plan::grid3_of(c->limits(), tiles) * (size_t)p.t3 * 8 : 0);
         s = acquire_slot(c, w.total, 0, slot);
         if (s != BSF_OK) return s;
         t = make_tiers(c, p, (char*)c->slot[slot].dev, w, tiles, j->order);
@@ -2348,8 +2326,10 @@ bsf_status bsf_filter_batched(bsf_ctx* c, const bsf_job* jobs, int njobs, void* 
             }
             g.count = items - g.first;
             g.p = plan_tiers(c, need[g.v], g.v / 2 + 1);
+            if (!bsf_plan::plan_fits(c->limits(), g.p, g.v / 2 + 1))
+                return fail(c, BSF_ERR_UNSUPPORTED, "the launch's LDS exceeds the device's limit");
             if (g.p.use3) {
-                const long long grid3 = std::min<long long>(g.count, (long long)c->cus * 2);
+                const long long grid3 = bsf_plan::grid3_of(c->limits(), g.count);
                 scratch_bytes = std::max(scratch_bytes, (size_t)grid3 * (size_t)g.p.t3 * 8);
             }
             groups.push_back(g);
@@ -2544,6 +2524,8 @@ bsf_status bsf_debug_tile_window(bsf_ctx* c, const bsf_job* j, int tile, int64_t
     const long long full = (c->lds_max_bytes - c->lds_static[j->order]) / 8;
     Launch L{};
     L.lds_cap = std::min(job_window_need(c, j), full);
+    if (!bsf_plan::launch_fits(c->limits(), j->order, L.lds_cap * 8))
+        return fail(c, BSF_ERR_UNSUPPORTED, "the launch's LDS exceeds the device's limit");
     L.err = c->d_err;
     L.dbg_window = (long long*)window;
     L.dbg_geom = geom;

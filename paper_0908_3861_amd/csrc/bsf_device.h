@@ -25,7 +25,7 @@ constexpr double kScaleMin = 0.5;
 constexpr double kScaleMax = 1e4;
 
 // sticky device error bits
-enum : unsigned { kErrScale = 1u, kErrWindow = 2u, kErrRange = 4u, kErrInexact = 8u };
+enum : unsigned { kErrScale = 1u, kErrWindow = 2u, kErrRange = 4u };
 
 // 1/sqrt2 as an unevaluated sum hi + lo (hi = round(1/sqrt2), lo = the rest)
 constexpr double kInvSqrt2Hi = 0x1.6a09e667f3bcdp-1;

@@ -74,10 +74,12 @@ def test_batched_workload_64_images(torch_dev, oracle_mod):
                   path="f32tiled", a_max=8.0) for j in jobs]
     outs = binding.filter_batched(items, check=True)
     rng = np.random.default_rng(604)
-    for k in rng.choice(len(jobs), size=6, replace=False):
-        j = jobs[k]
-        err = sampled_rel_max(outs[k].cpu().numpy(), j.image, j.scales, j.order, 12, rng, oracle_mod)
+    worst = 0.0
+    for k, j in enumerate(jobs):  # 64 sampled pixels of every image
+        err = sampled_rel_max(outs[k].cpu().numpy(), j.image, j.scales, j.order, 64, rng, oracle_mod)
+        worst = max(worst, err)
         assert err < TOL_F32, (k, j.order, j.image.shape)
+    print(f"batched 64 images: worst rel_max over 64 pixels each {worst:.3g}")
 
 
 def test_padded_pitches(torch_dev, oracle_mod):

@@ -46,7 +46,16 @@ def test_workspace_size_is_host_only():
     j.out, j.out_pitch = 32, 100
     n = ctypes.c_size_t()
     assert lib.bsf_workspace_size(ctypes.byref(j), ctypes.byref(n)) == 0
-    assert n.value >= 7 * 4 * 8  # room for every tile in the overflow list
+    assert n.value == 0  # every window fits half the LDS: tier 1 alone, no work area
+    j.a_max = 14.0  # windows of ~100 KB: the tiles go through the overflow lists of tier 2
+    assert lib.bsf_workspace_size(ctypes.byref(j), ctypes.byref(n)) == 0
+    assert 2 * 7 * 4 * 8 <= n.value < 1 << 16
+    j.a_max = 40.0  # beyond the LDS: tier-3 scratch slices, one per tile here (28 tiles)
+    assert lib.bsf_workspace_size(ctypes.byref(j), ctypes.byref(n)) == 0
+    assert n.value > 28 * 160 * 1024
+    j.a_max = 0.25  # neither 0 nor an admissible bound
+    assert lib.bsf_workspace_size(ctypes.byref(j), ctypes.byref(n)) == 1
+    j.a_max = 4.0
     j.order = 7
     assert lib.bsf_workspace_size(ctypes.byref(j), ctypes.byref(n)) == 4  # unsupported order
     j.order, j.scales = 2, 66  # misaligned scale field
@@ -121,3 +130,102 @@ def test_binding_structs_match_the_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(py), cname
         for fname, _ in py._fields_:
             assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
+
+
+PLAN_DRIVER = r'''
+#include <cstdio>
+#include <cstdlib>
+#include "plan.h"
+using namespace bsf_plan;
+static int fails = 0;
+#define CHECK(c) do { if (!(c)) { std::printf("FAIL line %d: %s\n", __LINE__, #c); ++fails; } } while (0)
+int main() {
+    // every plan's LDS launches fit, for any static reserve the kernels may declare
+    for (long long st : {0ll, 1024ll, 5376ll, 12288ll, 40000ll})
+        for (int order = 1; order <= 3; ++order) {
+            Limits L{163840, {st, st, st, st}, 256};
+            const long long full = full_cap(L, order), half = half_cap(L, order);
+            CHECK(launch_fits(L, order, full * 8) && !launch_fits(L, order, full * 8 + 8));
+            for (long long need : {1ll, half - 1, half, half + 1, full - 1, full, full + 1, 10 * full}) {
+                const Plan p = plan_tiers(L, need, order);
+                CHECK(plan_fits(L, p, order));
+                CHECK(p.t1 <= half);                                  // two workgroups per CU
+                CHECK((need <= half) == !p.use2);
+                CHECK((need > full) == p.use3);
+                CHECK(!p.use3 || p.t3 == need);                      // tier 3 holds any window
+                CHECK(p.use3 || (p.use2 ? p.t2 : p.t1) >= need);      // the last LDS tier holds it
+                // the bound used without a device never plans a smaller work area
+                const Limits B = gfx950_bound();
+                if (st <= B.lds_static[order])
+                    for (long long tiles : {1ll, 7ll, 4096ll})
+                        CHECK(single_call_bytes(B, plan_tiers(B, need, order), tiles) >=
+                              single_call_bytes(L, p, tiles));
+            }
+        }
+    // a static reserve the planner does not know about is caught before the launch
+    {
+        Limits L{163840, {0, 1024, 1024, 1024}, 256};
+        const Plan p = plan_tiers(L, full_cap(L, 2), 2);
+        Limits M = L;
+        M.lds_static[2] = 4096;
+        CHECK(plan_fits(L, p, 2) && !plan_fits(M, p, 2));
+    }
+    // work area of a fixed buffer: lists, then at least one tier-3 slice
+    {
+        const Limits L{163840, {0, 2048, 2048, 6144}, 256};
+        const Plan p = plan_tiers(L, 50000, 2);
+        CHECK(p.use3);
+        const FixedArea a = fixed_area(L, p, 1000, (size_t)32 << 20);
+        CHECK(a.ok && a.grid3 >= 1 && a.grid3 <= grid3_of(L, 1000) && a.bytes <= ((size_t)32 << 20));
+        CHECK(!fixed_area(L, plan_tiers(L, 5000000, 2), 1000, (size_t)32 << 20).ok);  // one slice too large
+        CHECK(!fixed_area(L, p, 5000000, (size_t)32 << 20).ok);                      // lists too large
+        CHECK(fixed_area(L, plan_tiers(L, 100, 2), 5000000, 0).ok);                   // tier 1: no area
+    }
+    // the slot ring never holds more than the workspace limit
+    {
+        srand(7);
+        for (int trial = 0; trial < 20000; ++trial) {
+            size_t cur[kRing], tgt[kRing];
+            const size_t limit = (size_t)(rand() % 4096 + 1) << (rand() % 12);
+            size_t tot = 0;
+            for (int r = 0; r < kRing; ++r) {
+                cur[r] = (rand() & 1) ? (size_t)(rand() % 2048) << (rand() % 10) : 0;
+                if (tot + cur[r] > limit) cur[r] = 0;
+                tot += cur[r];
+            }
+            const int idx = rand() % kRing;
+            const size_t bytes = (size_t)(rand() % 4096) << (rand() % 12);
+            const bool ok = ring_growth(cur, idx, bytes, limit, tgt);
+            size_t after = 0;
+            for (int r = 0; r < kRing; ++r) after += tgt[r];
+            CHECK(ok == (bytes <= limit));
+            if (ok) {
+                CHECK(tgt[idx] >= bytes);
+                CHECK(after <= limit || after == tot);  // within the limit (or untouched)
+                for (int r = 0; r < kRing; ++r) CHECK(r == idx || tgt[r] <= cur[r] || tgt[r] == tgt[idx]);
+            }
+        }
+        size_t cur[kRing] = {0}, tgt[kRing];
+        CHECK(ring_growth(cur, 3, 1000, (size_t)1 << 30, tgt));
+        for (int r = 0; r < kRing; ++r) CHECK(tgt[r] == ((size_t)1 << 16));  // every slot grows at once
+    }
+    std::printf("fails %d\n", fails);
+    return fails != 0;
+}
+'''
+
+
+def test_launch_plan_arithmetic(tmp_path):
+    """The host planner (csrc/plan.h): every launch's dynamic + static LDS fits the device,
+    tiers hold their windows, the device-free workspace bound never undercuts a device's
+    plan, a fixed buffer is carved into lists and tier-3 slices, and the slot ring stays
+    within the workspace limit.  Compiled on its own with g++ (plain C++, no device code)."""
+    src = tmp_path / "plan_driver.cpp"
+    src.write_text(PLAN_DRIVER)
+    exe = tmp_path / "plan_driver"
+    csrc = os.path.join(ROOT, "paper_0908_3861_amd", "csrc")
+    subprocess.run(["g++", "-std=c++17", "-O1", "-Wall", "-I", csrc, "-o", str(exe), str(src)], check=True,
+                   capture_output=True)
+    res = subprocess.run([str(exe)], capture_output=True, text=True)
+    assert res.returncode == 0, res.stdout
+    assert "fails 0" in res.stdout
