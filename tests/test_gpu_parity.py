@@ -525,7 +525,8 @@ def test_workspace_limit(bsf, torch_dev):
         bsf.filter(img, sc, 2, a_max=40.0, ctx=small)  # tier-3 slices of ~180 KB each
     assert ei.value.status == 2
     lib = bsf.load()
-    for a_max in (12.0, 13.0, 14.5, 16.0, 17.5, 19.0, 24.0):
+    # a_max bounds every scale of the image (the tile at [0,16)^2 reaches 13)
+    for a_max in (13.0, 14.5, 16.0, 17.5, 19.0, 24.0):
         j, _ = bsf.make_job(img, sc, 2, a_max=a_max)
         need = ctypes.c_size_t()
         assert lib.bsf_workspace_size(ctypes.byref(j), ctypes.byref(need)) == 0
