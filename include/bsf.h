@@ -116,6 +116,19 @@ bsf_status bsf_filter(bsf_ctx* ctx, const bsf_job* job, void* stream);
  * what bsf_filter writes for that job alone.  `jobs` is a host array. */
 bsf_status bsf_filter_batched(bsf_ctx* ctx, const bsf_job* jobs, int njobs, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the same result as bsf_filter, bitwise,
+ * with the call's work area (tile lists, counters, tier-3 window slices) in a fixed 32 MiB
+ * array in device memory that the library holds on each GPU until the process ends.  The
+ * call allocates nothing and never waits on the host.  The caller still passes the job's
+ * inputs and output; the context supplies the device and the error word.  A job whose work
+ * area cannot fit the array (16 bytes per 16x16 tile, about 2 million tiles, plus at least
+ * one restart window slice when a window exceeds the chip's LDS) returns
+ * BSF_ERR_OUT_OF_MEMORY synchronously.  Every call on one GPU shares that GPU's array, from
+ * any context: calls that overlap on the device (other streams, other threads) race and
+ * must be serialised by the caller.  Asynchronous on `stream`. */
+bsf_status bsf_filter_noalloc(bsf_ctx* ctx, const bsf_job* job, void* stream);
+
 /* Stage 1 alone, as a global pre-integrator (eq. RS applied n times per direction):
  * the unit-weight n-fold running sums of the window  f_ext[y0 + r][x0 + c],
  * 0 <= r < hq, 0 <= c < wq  (f_ext = the job's image under its boundary rule; the job's

@@ -68,6 +68,7 @@ def load():
             lib.bsf_workspace_size.argtypes = [jp, ctypes.POINTER(sz)]
             lib.bsf_filter.argtypes = [vp, jp, vp]
             lib.bsf_filter_batched.argtypes = [vp, jp, i, vp]
+            lib.bsf_filter_noalloc.argtypes = [vp, jp, vp]
             lib.bsf_preintegrate.argtypes = [vp, jp, i, i, i, i, vp, ctypes.c_ssize_t, vp]
             lib.bsf_get_device_error.argtypes = [vp, vp]
             lib.bsf_get_counters.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_ulonglong), i]
@@ -80,6 +81,7 @@ def load():
             lib.bsf_last_error.restype = ctypes.c_char_p
             lib.bsf_debug_tile_window.argtypes = [vp, jp, i, vp, ctypes.c_longlong, vp, vp]
             for fn in ("bsf_create", "bsf_destroy", "bsf_workspace_size", "bsf_filter", "bsf_filter_batched",
+                       "bsf_filter_noalloc",
                        "bsf_preintegrate", "bsf_get_device_error", "bsf_get_counters", "bsf_scales_from_ellipses",
                        "bsf_debug_tile_window", "bsf_filter1d", "bsf_filter1d_max_scale"):
                 getattr(lib, fn).restype = i
@@ -213,6 +215,20 @@ def filter(img, scales, order: int, path: str = "f64", border: str = "clamp", a_
     with _on(stream):
         j, out = make_job(img, scales, order, path, border, a_max, out)
     ctx._check(ctx.lib.bsf_filter(ctx.handle, ctypes.byref(j), _stream_ptr(stream)))
+    if check:
+        ctx.check_device(stream)
+    return out
+
+
+def filter_noalloc(img, scales, order: int, path: str = "f64", border: str = "clamp", a_max: float | None = None,
+                   out=None, ctx: Context | None = None, stream=None, check: bool = False):
+    """``filter`` through bsf_filter_noalloc: the library allocates nothing (its work area is a
+    fixed array per GPU; ``out`` and ``a_max`` should be given to keep the call free of torch
+    allocations and host syncs too)."""
+    ctx = ctx or default_context(img.device.index)
+    with _on(stream):
+        j, out = make_job(img, scales, order, path, border, a_max, out)
+    ctx._check(ctx.lib.bsf_filter_noalloc(ctx.handle, ctypes.byref(j), _stream_ptr(stream)))
     if check:
         ctx.check_device(stream)
     return out

@@ -16,6 +16,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1758,6 +1759,13 @@ __global__ __launch_bounds__(256) void ellipse_scales_kernel(const float* __rest
 // ===========================================================================
 // Host side: the C ABI.
 // ===========================================================================
+// Work area of bsf_filter_noalloc: a fixed array in device memory, one copy per GPU the
+// library runs on, held until the process ends.  Host code never passes this symbol to a
+// kernel (on the host it names a stand-in, not device memory): it uses the device address
+// hipGetSymbolAddress returns for each device, cached in noalloc_address().
+constexpr size_t kNoAllocBytes = size_t(32) << 20;
+static __device__ __align__(256) unsigned char noalloc_scratch[kNoAllocBytes];
+
 struct bsf_ctx {
     int device = 0;
     int cus = 256;
@@ -1777,6 +1785,8 @@ struct bsf_ctx {
     } slot[kRing];
     int slot_next = 0;
     long long lds_max_bytes = 0;   // LDS a workgroup may hold
+    void* noalloc = nullptr;       // this device's copy of noalloc_scratch (null: lookup failed)
+    std::string noalloc_error;     // why the lookup failed
     long long lds_static[4] = {1024, 1024, 1024, 1024};  // per order: the largest static LDS of its kernels, plus a margin
     std::string last;
     bsf_plan::Limits limits() const {
@@ -1799,6 +1809,27 @@ bsf_status fail(bsf_ctx* c, bsf_status s, const std::string& msg) {
 
 bsf_status hip_fail(bsf_ctx* c, hipError_t e, const char* what) {
     return fail(c, BSF_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Device address of noalloc_scratch on `device`, looked up once per device with that
+// device current (each GPU holds its own copy of the array at its own address).
+hipError_t noalloc_address(int device, void** out) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void* addr[kMaxDevices] = {};
+    static hipError_t err[kMaxDevices] = {};
+    static bool done[kMaxDevices] = {};
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!done[device]) {
+        void* p = nullptr;
+        err[device] = hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch));
+        addr[device] = err[device] == hipSuccess ? p : nullptr;
+        done[device] = true;
+    }
+    *out = addr[device];
+    return err[device];
 }
 
 bsf_status validate(bsf_ctx* c, const bsf_job* j, bool need_out) {
@@ -2200,6 +2231,13 @@ bsf_status bsf_create(bsf_ctx** out, int hip_device, size_t workspace_limit_byte
             return BSF_ERR_HIP;
         }
     }
+    // the fixed work area of bsf_filter_noalloc (device current)
+    e = noalloc_address(hip_device, &c->noalloc);
+    if (e != hipSuccess) {
+        c->noalloc = nullptr;
+        c->noalloc_error = std::string("hipGetSymbolAddress: ") + hipGetErrorString(e);
+        (void)hipGetLastError();
+    }
     e = hipMalloc(&c->d_err, 64);  // the error word, then the two counters at byte 8
     if (e != hipSuccess) {
         delete c;
@@ -2268,6 +2306,39 @@ bsf_status bsf_filter(bsf_ctx* c, const bsf_job* j, void* stream) {
     }
     e = dispatch_single(j->order, j->path, A, p, t, tiles, st);
     if (e == hipSuccess && slot >= 0) e = hipEventRecord(c->slot[slot].done, st);
+    if (e != hipSuccess) return hip_fail(c, e, "tile kernel launch");
+    return BSF_OK;
+}
+
+bsf_status bsf_filter_noalloc(bsf_ctx* c, const bsf_job* j, void* stream) {
+    if (!c) return BSF_ERR_INVALID_ARG;
+    bsf_status s = validate(c, j, true);
+    if (s != BSF_OK) return s;
+    if (!c->noalloc) return fail(c, BSF_ERR_HIP, "no fixed work area on this device (" + c->noalloc_error + ")");
+    const Plan p = plan_tiers(c, job_window_need(c, j), j->order);
+    if (!bsf_plan::plan_fits(c->limits(), p, j->order))
+        return fail(c, BSF_ERR_UNSUPPORTED, "the launch's LDS exceeds the device's limit");
+    const JobDesc A = make_desc(j);
+    const int tiles = A.tiles_x * A.tiles_y;
+    const bsf_plan::FixedArea f = bsf_plan::fixed_area(c->limits(), p, tiles, kNoAllocBytes);
+    if (!f.ok)
+        return fail(c, BSF_ERR_OUT_OF_MEMORY,
+                    "the call's work area (" + std::to_string(work_layout(tiles, 0, 0).total) + " bytes of tile lists" +
+                        (p.use3 ? " and at least one window slice of " + std::to_string(p.t3 * 8) + " bytes" : "") +
+                        ") exceeds the fixed " + std::to_string(kNoAllocBytes) + "-byte area of bsf_filter_noalloc");
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+    Tiers t;
+    if (p.use2) {
+        const WorkLayout w = work_layout(tiles, 0, f.bytes - work_layout(tiles, 0, 0).total);
+        t = make_tiers(c, p, (char*)c->noalloc, w, tiles, j->order, f.grid3);
+        // the counters must start at zero: a kernel clears them (the area keeps the last call's contents)
+        hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, st, (unsigned*)c->noalloc);
+    } else {
+        t = make_tiers(c, p, nullptr, WorkLayout{}, tiles, j->order);
+    }
+    e = dispatch_single(j->order, j->path, A, p, t, tiles, st);
     if (e != hipSuccess) return hip_fail(c, e, "tile kernel launch");
     return BSF_OK;
 }
