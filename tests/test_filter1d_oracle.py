@@ -6,7 +6,11 @@
   B-spline-interpolated running sums), in exact rational arithmetic with the B-splines from the
   Cox-de Boor recursion -- a different algorithm from the oracle's truncated-power closed form;
 * partition of unity and reproduction of linear signals at integer scales, a moving-average
-  brute force for the box (n = 1), and symmetry under reversal.
+  brute force for the box (n = 1), and symmetry under reversal;
+* for the prefiltered models (n1 = 2, 3): the closed-form impulse response of the inverse
+  interpolation filter, rho z^|k| (high-precision mpmath), scipy's B-spline prefilter in the
+  interior of a long signal, and the projection of a reproduced polynomial, whose value
+  follows from the moments of the B-spline alone (p(m) + p''(m) n a^2 / 24).
 """
 import math
 from fractions import Fraction
@@ -50,7 +54,7 @@ def test_box_is_half_open():
     assert [F.kernel_value(x, 2.5, 1) for x in (-2, -1, 0, 1, 2)] == [0] + [Fraction(2, 5)] * 3 + [0]
 
 
-@pytest.mark.parametrize("n1,n", [(0, 1), (0, 2), (1, 1), (1, 3), (0, 3)])
+@pytest.mark.parametrize("n1,n", [(0, 1), (0, 2), (1, 1), (1, 3), (0, 3), (2, 1), (2, 3), (3, 2)])
 def test_model_kernel_is_the_convolution(n1, n):
     rng = np.random.default_rng(20 + 3 * n1 + n)
     for a in rng.uniform(0.5, 6.0, 4).astype(np.float32):
@@ -80,12 +84,16 @@ def cox_de_boor(x: Fraction, D: int) -> Fraction:
 
 
 def prop31(f, scales, n, n1, m_list):
-    """s[m] by Proposition 3.1 with zero extension: g = n-fold running sum (u_1^n) of c = f,
-    F(x) = sum_k g[k] beta^{n1+n}(x + tau - k), s[m] = Delta_a^n F(m), tau = (a-1) n / 2."""
+    """s[m] by Proposition 3.1 with zero extension: g = n-fold running sum (u_1^n) of c,
+    F(x) = sum_k g[k] beta^{n1+n}(x + tau - k), s[m] = Delta_a^n F(m), tau = (a-1) n / 2.
+    c = f for n1 <= 1; for n1 >= 2 the oracle's coefficients (their own pins are below)."""
     L = len(f)
     D = n1 + n
     pad = 64
-    c = [Fraction(0)] * pad + [Fraction(float(v)) for v in f] + [Fraction(0)] * pad
+    if n1 >= 2:
+        c = F.coefficients(f, n1, "zero", -pad, L + pad)
+    else:
+        c = [Fraction(0)] * pad + [Fraction(float(v)) for v in f] + [Fraction(0)] * pad
     g = c
     for _ in range(n):
         acc, out = Fraction(0), []
@@ -110,7 +118,8 @@ def prop31(f, scales, n, n1, m_list):
     return res
 
 
-@pytest.mark.parametrize("n1,n", [(-1, 1), (-1, 2), (-1, 3), (0, 1), (0, 2), (1, 2), (1, 3)])
+@pytest.mark.parametrize("n1,n", [(-1, 1), (-1, 2), (-1, 3), (0, 1), (0, 2), (1, 2), (1, 3), (2, 1), (2, 2),
+                                  (3, 1), (3, 3)])
 def test_oracle_equals_proposition_31_exactly(n1, n):
     rng = np.random.default_rng(30 + 4 * n1 + n)
     L = 24
@@ -120,7 +129,10 @@ def test_oracle_equals_proposition_31_exactly(n1, n):
     ms = list(range(8, 16))
     ref = prop31(f, scales, n, n1, ms)
     ours = F.filter1d_exact(f, scales, n, n1, "zero", ms)
-    assert ours == ref
+    if n1 <= 1:
+        assert ours == ref
+    else:  # the two prefilter blocks are truncated differently (far below 1e-30)
+        assert all(abs(o - r) < Fraction(1, 10 ** 30) for o, r in zip(ours, ref))
 
 
 # --- invariants -------------------------------------------------------------------------------
@@ -172,3 +184,65 @@ def test_rounding_and_batch():
                                   [full[b, m] for b, m in pts])
     ex = F.filter1d_exact(sig[1], sc[1], 2, 0, "clamp", [7])[0]
     assert full[1, 7] == float(ex)
+
+
+# --- the prefiltered models (n1 = 2, 3) --------------------------------------------------------
+
+@pytest.mark.parametrize("n1", [2, 3])
+def test_prefilter_impulse_response_is_the_two_sided_exponential(n1):
+    """The inverse of b^{n1} = (b1, b0, b1) is rho z^|k|: z the root inside the unit circle of
+    b1 z^2 + b0 z + b1 (z = 2 sqrt2 - 3, sqrt3 - 2) and rho = 1 / (b1 (z - 1/z))."""
+    import mpmath
+    mpmath.mp.dps = 60
+    b0, b1 = (mpmath.mpf(3) / 4, mpmath.mpf(1) / 8) if n1 == 2 else (mpmath.mpf(2) / 3, mpmath.mpf(1) / 6)
+    z = (-b0 + mpmath.sqrt(b0 * b0 - 4 * b1 * b1)) / (2 * b1)
+    rho = 1 / (b1 * (z - 1 / z))
+    assert abs(rho - (mpmath.sqrt(2) if n1 == 2 else mpmath.sqrt(3))) < mpmath.mpf(10) ** -50
+    L = 121
+    f = np.zeros(L)
+    f[60] = 1.0
+    c = F.coefficients(f, n1, "zero", 20, 101)
+    for k in range(20, 101):
+        exact = rho * z ** abs(k - 60)
+        assert abs(mpmath.mpf(c[k - 20].numerator) / c[k - 20].denominator - exact) < mpmath.mpf(10) ** -30, k
+
+
+@pytest.mark.parametrize("n1", [2, 3])
+def test_prefilter_interior_matches_scipy(n1):
+    from scipy import ndimage
+    rng = np.random.default_rng(80 + n1)
+    L = 400
+    f = rng.standard_normal(L)
+    ours = np.array([float(v) for v in F.coefficients(f, n1, "clamp", 100, 300)])
+    ref = ndimage.spline_filter1d(f, order=n1, mode="mirror")[100:300]
+    np.testing.assert_allclose(ours, ref, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("n1,n", [(2, 1), (2, 2), (2, 3), (3, 1), (3, 2), (3, 3)])
+def test_prefiltered_model_projects_polynomials_by_their_moments(n1, n):
+    """A polynomial of degree <= n1 is its own model; its projection onto beta_a^{n-1} is
+    p(m) + p''(m) Var/2 with Var = n a^2 / 12 (odd moments vanish), away from the ends."""
+    rng = np.random.default_rng(90 + 4 * n1 + n)
+    L = 300
+    coef = [Fraction(3), Fraction(-2), Fraction(1, 2), Fraction(1, 64) if n1 == 3 else Fraction(0)]
+    p = lambda x: sum(c * Fraction(x) ** i for i, c in enumerate(coef))  # noqa: E731
+    p2 = lambda x: 2 * coef[2] + 6 * coef[3] * x  # noqa: E731
+    f = np.array([float(p(k)) for k in range(L)])
+    assert all(Fraction(float(f[k])) == p(k) for k in range(L))  # exact in float64
+    sc = rng.uniform(0.5, 9.0, L).astype(np.float32)
+    ms = list(range(120, 180, 3))
+    ours = F.filter1d_exact(f, sc, n, n1, "clamp", ms)
+    for m, v in zip(ms, ours):
+        a = Fraction(float(sc[m]))
+        want = p(m) + p2(m) * n * a * a / 24
+        assert abs(v - want) < Fraction(1, 10 ** 25), (m, float(v - want))
+
+
+@pytest.mark.parametrize("n1", [2, 3])
+def test_prefiltered_constant_is_reproduced_at_any_scale(n1):
+    rng = np.random.default_rng(100 + n1)
+    L = 40
+    sc = rng.uniform(0.5, 7.0, L).astype(np.float32)
+    for n in (1, 2, 3):
+        out = F.filter1d_exact(np.full(L, 2.5), sc, n, n1, "clamp")
+        assert all(abs(v - Fraction(5, 2)) < Fraction(1, 10 ** 30) for v in out)
