@@ -116,6 +116,28 @@ bsf_status bsf_filter(bsf_ctx* ctx, const bsf_job* job, void* stream);
  * what bsf_filter writes for that job alone.  `jobs` is a host array. */
 bsf_status bsf_filter_batched(bsf_ctx* ctx, const bsf_job* jobs, int njobs, void* stream);
 
+/* Captured batched launches for serving loops (the batched form of bsf_filter_batched as a
+ * replayable plan).  bsf_batch_plan_create allocates a plan's own work area for batches of up
+ * to `max_jobs` jobs and `max_tiles` 16x16 tiles in total, all of whose scales are bounded by
+ * `a_max`, and captures the whole launch sequence once as a HIP graph: the upload of the
+ * batch's descriptors from the plan's pinned staging, the persistent tile kernels of every
+ * (order, path) variant and tier (they read the batch's counts from device memory, so the
+ * same graph serves any batch within the capacity), and the download of one error word per
+ * job.  bsf_batch_plan_run fills the staging for `jobs` (host array; each job's a_max must be
+ * set and at most the plan's) and replays the graph on `stream`; every output is bitwise
+ * equal to what bsf_filter writes for that job alone.  A run first waits (on the host) until
+ * the plan's previous run has finished, so a caller that wants runs to overlap uses one plan
+ * per stream.  bsf_batch_plan_job_status waits for the last run and writes, for its first
+ * `njobs` jobs (the order of the `jobs` array), the status the kernels found for that job
+ * alone: BSF_OK, BSF_ERR_SCALE_RANGE, BSF_ERR_UNSUPPORTED or BSF_ERR_RANGE (whose outputs
+ * hold NaN where the error struck).  The plan belongs to the context it was created on and is
+ * used by one host thread at a time. */
+typedef struct bsf_batch_plan bsf_batch_plan;
+bsf_status bsf_batch_plan_create(bsf_ctx* ctx, int max_jobs, long long max_tiles, float a_max, bsf_batch_plan** plan);
+bsf_status bsf_batch_plan_run(bsf_batch_plan* plan, const bsf_job* jobs, int njobs, void* stream);
+bsf_status bsf_batch_plan_job_status(bsf_batch_plan* plan, int* status, int njobs);
+bsf_status bsf_batch_plan_destroy(bsf_batch_plan* plan);
+
 /* For callers that cannot allocate device memory (code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc): the same result as bsf_filter, bitwise,
  * with the call's work area (tile lists, counters, tier-3 window slices) in a fixed 32 MiB
@@ -172,11 +194,13 @@ bsf_status bsf_scales_from_ellipses(bsf_ctx* ctx, const float* ellipses, ptrdiff
  *     s[m] = sum_k c_ext[k] (beta^model * beta_a^(order-1))(m - k),
  * where the model f(x) = sum_k c[k] beta^model(x - k) has degree model = -1 (impulses at the
  * samples, the model of the two-dimensional filter), 0 or 1 (for these the interpolation
- * filter is the unit impulse, so c = the samples), and c_ext extends each signal by its end
- * values (clamp) or zeros.  Computed by Proposition 3.1: order running sums (eq. RS, unit
- * scale), then per sample the finite-difference mask Delta_a^order (eq. FD) applied to the
- * running sums interpolated with the B-spline of degree model + order, on restart windows of
- * 256 outputs.  BSF_PATH_F64: the running sums, the interpolation and the mask carry a
+ * filter is the unit impulse, so c = the samples), or 2 or 3 (c = the extended samples filtered
+ * by the inverse of b^model[k] = beta^model(k), so that the model interpolates them: the
+ * two-sided exponential rho z^|k| of the inverse, truncated where its tail falls below 2^-60),
+ * and each signal is extended by its end values (clamp) or zeros.  Computed by Proposition
+ * 3.1: order running sums (eq. RS, unit scale), then per sample the finite-difference mask
+ * Delta_a^order (eq. FD) applied to the running sums interpolated with the B-spline of degree
+ * model + order, on restart windows of 256 outputs.  BSF_PATH_F64: the running sums, the interpolation and the mask carry a
  * compensation term, so the float64 result matches the exact projection to a few ulps of its
  * largest terms.  BSF_PATH_F32_TILED: the running sums are compensated, the interpolation and
  * the mask plain float64, the result float32; its error is below 1e-5 of the output's
@@ -189,7 +213,7 @@ typedef struct {
     const float* scales;            /* [count][scale_pitch] scales a                        */
     ptrdiff_t scale_pitch;          /* >= length                                           */
     int order;                      /* number of running sums, 1..3 (B-spline degree + 1)  */
-    int model;                      /* degree of the signal model: -1, 0 or 1              */
+    int model;                      /* degree of the signal model: -1, 0, 1, 2 or 3        */
     bsf_path path;                  /* F64: float64 output; F32_TILED: float32 output       */
     bsf_border border;
     float a_max;                    /* upper bound on every scale (sizes the on-chip windows;
@@ -206,7 +230,7 @@ typedef struct {
 bsf_status bsf_filter1d(bsf_ctx* ctx, const bsf_job1d* job, void* stream);
 
 /* The largest a_max bsf_filter1d accepts for this order and model, on either path (the
- * restart window of 256 + about order * a_max samples, at (3 + model + order) * 16 bytes per
+ * restart window of 256 + about order * a_max samples, at (2 + model + order) * 16 bytes per
  * sample, must fit the on-chip memory of one workgroup).  Host only. */
 bsf_status bsf_filter1d_max_scale(bsf_ctx* ctx, int order, int model, float* a_max);
 

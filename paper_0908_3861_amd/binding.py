@@ -69,6 +69,10 @@ def load():
             lib.bsf_filter.argtypes = [vp, jp, vp]
             lib.bsf_filter_batched.argtypes = [vp, jp, i, vp]
             lib.bsf_filter_noalloc.argtypes = [vp, jp, vp]
+            lib.bsf_batch_plan_create.argtypes = [vp, i, ctypes.c_longlong, ctypes.c_float, ctypes.POINTER(vp)]
+            lib.bsf_batch_plan_run.argtypes = [vp, jp, i, vp]
+            lib.bsf_batch_plan_job_status.argtypes = [vp, ctypes.POINTER(i), i]
+            lib.bsf_batch_plan_destroy.argtypes = [vp]
             lib.bsf_preintegrate.argtypes = [vp, jp, i, i, i, i, vp, ctypes.c_ssize_t, vp]
             lib.bsf_get_device_error.argtypes = [vp, vp]
             lib.bsf_get_counters.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_ulonglong), i]
@@ -81,7 +85,8 @@ def load():
             lib.bsf_last_error.restype = ctypes.c_char_p
             lib.bsf_debug_tile_window.argtypes = [vp, jp, i, vp, ctypes.c_longlong, vp, vp]
             for fn in ("bsf_create", "bsf_destroy", "bsf_workspace_size", "bsf_filter", "bsf_filter_batched",
-                       "bsf_filter_noalloc",
+                       "bsf_filter_noalloc", "bsf_batch_plan_create", "bsf_batch_plan_run", "bsf_batch_plan_job_status",
+                       "bsf_batch_plan_destroy",
                        "bsf_preintegrate", "bsf_get_device_error", "bsf_get_counters", "bsf_scales_from_ellipses",
                        "bsf_debug_tile_window", "bsf_filter1d", "bsf_filter1d_max_scale"):
                 getattr(lib, fn).restype = i
@@ -251,6 +256,53 @@ def filter_batched(items, ctx: Context | None = None, stream=None, check: bool =
     if check:
         ctx.check_device(stream)
     return outs
+
+
+class BatchPlan:
+    """A captured batched launch (bsf_batch_plan_*): create once, then ``run`` any batch of up
+    to ``max_jobs`` jobs and ``max_tiles`` tiles whose scales are bounded by ``a_max``."""
+
+    def __init__(self, ctx: Context, max_jobs: int, max_tiles: int, a_max: float):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        self.max_jobs = int(max_jobs)
+        self.a_max = float(a_max)
+        self._h = ctypes.c_void_p()
+        ctx._check(self.lib.bsf_batch_plan_create(ctx.handle, self.max_jobs, int(max_tiles), self.a_max,
+                                                  ctypes.byref(self._h)))
+        self._last = 0
+
+    def run(self, items, stream=None):
+        """items: dicts as for ``filter_batched`` (each job's a_max defaults to the plan's).
+        Returns the output tensors; the call is asynchronous on ``stream``."""
+        jobs = (Job * max(len(items), 1))()
+        outs = []
+        with _on(stream):
+            for i, it in enumerate(items):
+                j, o = make_job(it["img"], it["scales"], it["order"], it.get("path", "f64"),
+                                it.get("border", "clamp"), it.get("a_max") or self.a_max, it.get("out"))
+                jobs[i] = j
+                outs.append(o)
+        self.ctx._check(self.lib.bsf_batch_plan_run(self._h, jobs, len(items), _stream_ptr(stream)))
+        self._last = len(items)
+        return outs
+
+    def job_status(self) -> list[int]:
+        """Per-job status of the last run (waits for it)."""
+        st = (ctypes.c_int * max(self._last, 1))()
+        self.ctx._check(self.lib.bsf_batch_plan_job_status(self._h, st, self._last))
+        return [int(st[i]) for i in range(self._last)]
+
+    def close(self):
+        if self._h:
+            self.lib.bsf_batch_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def scales_from_ellipses(ell, order: int, out=None, ctx: Context | None = None, stream=None):

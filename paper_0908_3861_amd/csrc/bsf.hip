@@ -42,12 +42,12 @@ struct JobDesc {
     int order, path;
     int tiles_x, tiles_y;
     long long item_base;  // first work item of this job in a batched launch
+    unsigned* err;        // sticky error bits of this job (a context's word, or a plan's per-job word)
 };
 
 // Launch-wide parameters.
 struct Launch {
     long long lds_cap;    // int64 elements a window may use (dynamic LDS, or a scratch slice)
-    unsigned* err;        // sticky error bits
     unsigned long long* stats;  // [0] pixels of the float64 path evaluated split, [1] of
                                 //   those evaluated again compensated (null: not counted)
     unsigned* push_count; // tiles whose window does not fit go to this list for a later,
@@ -1033,7 +1033,7 @@ __device__ __forceinline__ void process_tile(const JobDesc A, int job, int tile,
         const float av[4] = {a.x, a.y, a.z, a.w};
 #pragma unroll
         for (int d = 0; d < 4; ++d) valid = valid && (av[d] >= (float)kScaleMin) && (av[d] <= (float)kScaleMax);
-        if (!valid) atomicOr(L.err, kErrScale);
+        if (!valid) atomicOr(A.err, kErrScale);
     }
     double R1 = valid ? reach1(N, a.x, a.y, a.w) : 0.0;
     double R2 = valid ? reach1(N, a.z, a.y, a.w) : 0.0;
@@ -1075,11 +1075,11 @@ __device__ __forceinline__ void process_tile(const JobDesc A, int job, int tile,
             if (tid == 0) {
                 const unsigned k = atomicAdd(L.push_count, 1u);
                 if (k < (unsigned)L.push_cap) L.push_list[k] = make_int2(job, tile);
-                else atomicOr(L.err, kErrWindow);
+                else atomicOr(A.err, kErrWindow);
             }
             return;
         }
-        if (tid == 0) atomicOr(L.err, kErrWindow);
+        if (tid == 0) atomicOr(A.err, kErrWindow);
         store(nan);
         return;
     }
@@ -1126,7 +1126,7 @@ __device__ __forceinline__ void process_tile(const JobDesc A, int job, int tile,
         }
         double s = finalize_f64<N>(m.hi, a);
         if (bad) {
-            atomicOr(L.err, kErrWindow);
+            atomicOr(A.err, kErrWindow);
             s = nan;
         }
         store(s);
@@ -1274,7 +1274,7 @@ __device__ __forceinline__ void process_tile(const JobDesc A, int job, int tile,
         done = !overflowed;
     }
     if (!done) {
-        if (tid == 0) atomicOr(L.err, kErrRange);
+        if (tid == 0) atomicOr(A.err, kErrRange);
         store(nan);
         return;
     }
@@ -1293,7 +1293,7 @@ __device__ __forceinline__ void process_tile(const JobDesc A, int job, int tile,
     double s = (PATH == BSF_PATH_F64) ? finalize_dd<N>(acc_dd, a) : finalize_f64<N>(acc_f, a);
     s = ldexp(s, -sh);
     if (bad) {
-        atomicOr(L.err, kErrWindow);
+        atomicOr(A.err, kErrWindow);
         s = nan;
     }
     store(s);
@@ -1376,24 +1376,48 @@ __device__ __forceinline__ int find_job(const JobDesc* jobs, int njobs, long lon
 }
 
 // One (order, path) variant of a batch: its jobs are jobs[j0 .. j0+nj), its items
-// first .. first+count-1 in the batch's numbering.  Each variant runs in kernels of its
-// own, so every variant gets the registers and LDS its own tiles need.
+// first .. first+count-1 in the batch's numbering.  The kernels read these counts from
+// device memory, so one launch sequence (a captured graph, say) serves any batch whose
+// counts were uploaded before it.
+struct GroupHdr {
+    int j0, nj;
+    long long first, count;
+};
+
+// The group's slices of the batch-wide overflow lists: items first .. first+count-1.
+__device__ __forceinline__ void group_lists(const GroupHdr& h, Launch& L, ItemList* in) {
+    if (L.push_cap > 0) {
+        L.push_list += h.first;
+        L.push_cap = (int)h.count;
+    }
+    if (in) {
+        in->items += h.first;
+        in->cap = (int)h.count;
+    }
+}
+
+// Each variant runs in kernels of its own, so every variant gets the registers and LDS its
+// own tiles need.
 template <int N, int PATH>
 __global__ __launch_bounds__((threads_of<N, PATH>())) __attribute__((amdgpu_waves_per_eu(N < 3 ? 2 : 1))) void batch_kernel(
-    const JobDesc* jobs, int j0, int nj, long long first, long long count, Launch L, unsigned* cursor) {
+    const JobDesc* jobs, const GroupHdr* hdr, Launch L, unsigned* cursor) {
     __shared__ Shared sh;
+    const GroupHdr h = *hdr;
+    group_lists(h, L, nullptr);
     for (;;) {
         const long long i = next_item(cursor, sh);
-        if (i >= count) break;
-        const int j = j0 + find_job(jobs + j0, nj, first + i);
+        if (i >= h.count) break;
+        const int j = h.j0 + find_job(jobs + h.j0, h.nj, h.first + i);
         const JobDesc A = jobs[j];
-        process_tile<N, PATH>(A, j, (int)(first + i - A.item_base), L, g_lds, sh);
+        process_tile<N, PATH>(A, j, (int)(h.first + i - A.item_base), L, g_lds, sh);
     }
 }
 
 template <int N, int PATH>
-__global__ __launch_bounds__((threads_of<N, PATH>())) void batch_overflow_kernel(const JobDesc* jobs, Launch L, ItemList in) {
+__global__ __launch_bounds__((threads_of<N, PATH>())) void batch_overflow_kernel(const JobDesc* jobs, const GroupHdr* hdr,
+                                                                                 Launch L, ItemList in) {
     __shared__ Shared sh;
+    group_lists(*hdr, L, &in);
     const int total = (int)min(*in.count, (unsigned)in.cap);
     for (;;) {
         const int i = next_item(in.cursor, sh);
@@ -1404,10 +1428,11 @@ __global__ __launch_bounds__((threads_of<N, PATH>())) void batch_overflow_kernel
 }
 
 template <int N, int PATH>
-__global__ __launch_bounds__((threads_of<N, PATH>())) void batch_scratch_kernel(const JobDesc* jobs, Launch L, ItemList in,
-                                                                 long long* scratch) {
+__global__ __launch_bounds__((threads_of<N, PATH>())) void batch_scratch_kernel(const JobDesc* jobs, const GroupHdr* hdr,
+                                                                                Launch L, ItemList in, long long* scratch) {
     __shared__ Shared sh;
     long long* S = scratch + (long long)blockIdx.x * L.lds_cap;
+    group_lists(*hdr, L, &in);
     const int total = (int)min(*in.count, (unsigned)in.cap);
     for (;;) {
         const int i = next_item(in.cursor, sh);
@@ -1415,6 +1440,11 @@ __global__ __launch_bounds__((threads_of<N, PATH>())) void batch_scratch_kernel(
         const int2 it = in.items[i];
         process_tile<N, PATH>(jobs[it.x], it.x, it.y, L, S, sh);
     }
+}
+
+// Clears `n` words (a plan's per-job error words) at the start of its launch sequence.
+__global__ void clear_words(unsigned* w, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) w[i] = 0u;
 }
 
 // The 64 counters at the head of a call's work area (8 per batch variant).
@@ -1798,6 +1828,22 @@ struct bsf_ctx {
     }
 };
 
+// A captured batched launch (bsf_batch_plan_*): a fixed work area sized for its capacity,
+// pinned descriptor staging, one error word per job, and the graph of the launch sequence.
+struct bsf_batch_plan {
+    bsf_ctx* ctx = nullptr;
+    int max_jobs = 0;
+    long long max_tiles = 0;
+    float a_max = 0.f;
+    void* dev = nullptr;            // counters | list A | list B | headers + descriptors | scratch | error words
+    size_t jobs_off = 0, err_off = 0;
+    bsf::JobDesc* host = nullptr;   // pinned staging: kHdrSlots header slots, then max_jobs descriptors
+    unsigned* herr = nullptr;       // pinned: the per-job error words of the last run, by the caller's job index
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;      // recorded after each replay
+    int last_njobs = 0;
+};
+
 namespace {
 
 using namespace bsf;
@@ -1905,7 +1951,6 @@ Tiers make_tiers_at(const bsf_ctx* c, const Plan& p, unsigned* ctr, int2* la, in
     Tiers t;
     t.L1 = Launch{};
     t.L1.lds_cap = p.t1;
-    t.L1.err = c->d_err;
     t.L1.stats = c->d_stats;
     t.L2 = t.L1;
     t.L2.lds_cap = p.t2;
@@ -1986,8 +2031,9 @@ hipError_t dispatch_debug(int n, int path, const JobDesc& A, const Launch& L, in
 #undef BSF_DBG
 }
 
-JobDesc make_desc(const bsf_job* j) {
+JobDesc make_desc(const bsf_job* j, unsigned* err) {
     JobDesc a{};
+    a.err = err;
     a.in = j->in;
     a.in_pitch = j->in_pitch;
     a.scales = j->scales;
@@ -2088,37 +2134,58 @@ long long measure_static_lds_n() {
 }
 
 template <int N, int PATH>
-hipError_t launch_batch_group(const bsf_ctx* c, const JobDesc* djobs, int j0, int nj, long long first,
-                              long long count, const Plan& p, const Tiers& t, unsigned* ctr, hipStream_t st) {
+void opt_in_batch_kernels() {
     static bool once = false;
     if (!once) {
         allow_big_lds(&batch_kernel<N, PATH>);
         allow_big_lds(&batch_overflow_kernel<N, PATH>);
         once = true;
     }
-    const int grid1 = (int)std::min<long long>(count, (long long)c->cus * std::min(per_cu(c, p.t1, N), 8));
-    hipLaunchKernelGGL((batch_kernel<N, PATH>), dim3(grid1), dim3(threads_of<N, PATH>()), (size_t)p.t1 * 8, st, djobs, j0, nj,
-                       first, count, t.L1, ctr + 2);
+}
+
+void opt_in_all_batch_kernels() {
+    opt_in_batch_kernels<1, 0>();
+    opt_in_batch_kernels<1, 1>();
+    opt_in_batch_kernels<2, 0>();
+    opt_in_batch_kernels<2, 1>();
+    opt_in_batch_kernels<3, 0>();
+    opt_in_batch_kernels<3, 1>();
+}
+
+// The launches of one variant; `items` (the group's items, or a plan's capacity) sizes the
+// persistent grids, `hdr` holds the counts the kernels go by.
+template <int N, int PATH>
+hipError_t launch_batch_group(const bsf_ctx* c, const JobDesc* djobs, const GroupHdr* hdr, long long items, const Plan& p,
+                              const Tiers& t, unsigned* ctr, hipStream_t st) {
+    opt_in_batch_kernels<N, PATH>();
+    const int grid1 = (int)std::min<long long>(items, (long long)c->cus * std::min(per_cu(c, p.t1, N), 8));
+    hipLaunchKernelGGL((batch_kernel<N, PATH>), dim3(grid1), dim3(threads_of<N, PATH>()), (size_t)p.t1 * 8, st, djobs, hdr,
+                       t.L1, ctr + 2);
     if (p.use2)
         hipLaunchKernelGGL((batch_overflow_kernel<N, PATH>), dim3(t.grid2), dim3(threads_of<N, PATH>()), (size_t)p.t2 * 8, st,
-                           djobs, t.L2, t.inA);
+                           djobs, hdr, t.L2, t.inA);
     if (p.use3)
-        hipLaunchKernelGGL((batch_scratch_kernel<N, PATH>), dim3(t.grid3), dim3(threads_of<N, PATH>()), 0, st, djobs, t.L3, t.inB,
-                           t.scratch);
+        hipLaunchKernelGGL((batch_scratch_kernel<N, PATH>), dim3(t.grid3), dim3(threads_of<N, PATH>()), 0, st, djobs, hdr, t.L3,
+                           t.inB, t.scratch);
     return hipGetLastError();
 }
 
-hipError_t dispatch_batch_group(const bsf_ctx* c, int v, const JobDesc* djobs, int j0, int nj, long long first,
-                                long long count, const Plan& p, const Tiers& t, unsigned* ctr, hipStream_t st) {
+hipError_t dispatch_batch_group(const bsf_ctx* c, int v, const JobDesc* djobs, const GroupHdr* hdr, long long items,
+                                const Plan& p, const Tiers& t, unsigned* ctr, hipStream_t st) {
     switch (v) {
-        case 0: return launch_batch_group<1, 0>(c, djobs, j0, nj, first, count, p, t, ctr, st);
-        case 1: return launch_batch_group<1, 1>(c, djobs, j0, nj, first, count, p, t, ctr, st);
-        case 2: return launch_batch_group<2, 0>(c, djobs, j0, nj, first, count, p, t, ctr, st);
-        case 3: return launch_batch_group<2, 1>(c, djobs, j0, nj, first, count, p, t, ctr, st);
-        case 4: return launch_batch_group<3, 0>(c, djobs, j0, nj, first, count, p, t, ctr, st);
-        default: return launch_batch_group<3, 1>(c, djobs, j0, nj, first, count, p, t, ctr, st);
+        case 0: return launch_batch_group<1, 0>(c, djobs, hdr, items, p, t, ctr, st);
+        case 1: return launch_batch_group<1, 1>(c, djobs, hdr, items, p, t, ctr, st);
+        case 2: return launch_batch_group<2, 0>(c, djobs, hdr, items, p, t, ctr, st);
+        case 3: return launch_batch_group<2, 1>(c, djobs, hdr, items, p, t, ctr, st);
+        case 4: return launch_batch_group<3, 0>(c, djobs, hdr, items, p, t, ctr, st);
+        default: return launch_batch_group<3, 1>(c, djobs, hdr, items, p, t, ctr, st);
     }
 }
+
+// Batch descriptors in device memory (and in their pinned staging): the six group headers
+// in the first two descriptor slots, then the jobs.
+constexpr int kHdrSlots = 2;
+static_assert(6 * sizeof(GroupHdr) <= kHdrSlots * sizeof(JobDesc), "group headers fit their slots");
 
 }  // namespace
 
@@ -2138,16 +2205,23 @@ hipError_t launch_filter1d(const bsf::f1d::Args& A, int blocks, long long lds, h
 
 template <int PATH>
 hipError_t dispatch_filter1d_path(int n, int D, const bsf::f1d::Args& A, int blocks, long long lds, hipStream_t st) {
+    // D = model degree + n, model in {-1, 0, 1, 2, 3}
     switch (n * 8 + D) {
         case 1 * 8 + 0: return launch_filter1d<1, 0, PATH>(A, blocks, lds, st);
         case 1 * 8 + 1: return launch_filter1d<1, 1, PATH>(A, blocks, lds, st);
         case 1 * 8 + 2: return launch_filter1d<1, 2, PATH>(A, blocks, lds, st);
+        case 1 * 8 + 3: return launch_filter1d<1, 3, PATH>(A, blocks, lds, st);
+        case 1 * 8 + 4: return launch_filter1d<1, 4, PATH>(A, blocks, lds, st);
         case 2 * 8 + 1: return launch_filter1d<2, 1, PATH>(A, blocks, lds, st);
         case 2 * 8 + 2: return launch_filter1d<2, 2, PATH>(A, blocks, lds, st);
         case 2 * 8 + 3: return launch_filter1d<2, 3, PATH>(A, blocks, lds, st);
+        case 2 * 8 + 4: return launch_filter1d<2, 4, PATH>(A, blocks, lds, st);
+        case 2 * 8 + 5: return launch_filter1d<2, 5, PATH>(A, blocks, lds, st);
         case 3 * 8 + 2: return launch_filter1d<3, 2, PATH>(A, blocks, lds, st);
         case 3 * 8 + 3: return launch_filter1d<3, 3, PATH>(A, blocks, lds, st);
-        default: return launch_filter1d<3, 4, PATH>(A, blocks, lds, st);
+        case 3 * 8 + 4: return launch_filter1d<3, 4, PATH>(A, blocks, lds, st);
+        case 3 * 8 + 5: return launch_filter1d<3, 5, PATH>(A, blocks, lds, st);
+        default: return launch_filter1d<3, 6, PATH>(A, blocks, lds, st);
     }
 }
 
@@ -2290,7 +2364,7 @@ bsf_status bsf_filter(bsf_ctx* c, const bsf_job* j, void* stream) {
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
-    const JobDesc A = make_desc(j);
+    const JobDesc A = make_desc(j, c->d_err);
     const int tiles = A.tiles_x * A.tiles_y;
     Tiers t;
     int slot = -1;
@@ -2318,7 +2392,7 @@ bsf_status bsf_filter_noalloc(bsf_ctx* c, const bsf_job* j, void* stream) {
     const Plan p = plan_tiers(c, job_window_need(c, j), j->order);
     if (!bsf_plan::plan_fits(c->limits(), p, j->order))
         return fail(c, BSF_ERR_UNSUPPORTED, "the launch's LDS exceeds the device's limit");
-    const JobDesc A = make_desc(j);
+    const JobDesc A = make_desc(j, c->d_err);
     const int tiles = A.tiles_x * A.tiles_y;
     const bsf_plan::FixedArea f = bsf_plan::fixed_area(c->limits(), p, tiles, kNoAllocBytes);
     if (!f.ok)
@@ -2406,34 +2480,207 @@ bsf_status bsf_filter_batched(bsf_ctx* c, const bsf_job* jobs, int njobs, void* 
             groups.push_back(g);
         }
     }
-    const WorkLayout w = work_layout(total, njobs, scratch_bytes);
+    const WorkLayout w = work_layout(total, njobs + kHdrSlots, scratch_bytes);
     int slot = -1;
-    bsf_status s = acquire_slot(c, w.total, njobs, slot);
+    bsf_status s = acquire_slot(c, w.total, njobs + kHdrSlots, slot);
     if (s != BSF_OK) return s;
     bsf_ctx::Slot& sl = c->slot[slot];
+    GroupHdr* hhdr = reinterpret_cast<GroupHdr*>(sl.host);
+    for (int v = 0; v < kVariants; ++v) hhdr[v] = GroupHdr{0, 0, 0, 0};
+    for (const Group& g : groups) hhdr[g.v] = GroupHdr{g.j0, g.nj, g.first, g.count};
     total = 0;
     for (int k = 0; k < njobs; ++k) {
-        JobDesc d = make_desc(jobs + order[k]);
+        JobDesc d = make_desc(jobs + order[k], c->d_err);
         d.item_base = total;
         total += (long long)d.tiles_x * d.tiles_y;
-        sl.host[k] = d;
+        sl.host[kHdrSlots + k] = d;
     }
     char* work = (char*)sl.dev;
-    const JobDesc* djobs = (const JobDesc*)(work + w.jobs_off);
-    e = hipMemcpyAsync((void*)djobs, sl.host, sizeof(JobDesc) * (size_t)njobs, hipMemcpyHostToDevice, st);
+    const GroupHdr* dhdr = (const GroupHdr*)(work + w.jobs_off);
+    const JobDesc* djobs = (const JobDesc*)(work + w.jobs_off) + kHdrSlots;
+    e = hipMemcpyAsync(work + w.jobs_off, sl.host, sizeof(JobDesc) * (size_t)(njobs + kHdrSlots), hipMemcpyHostToDevice,
+                       st);
     if (e != hipSuccess) return hip_fail(c, e, "uploading the batch descriptors");
     hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, st, (unsigned*)work);
     for (size_t gi = 0; gi < groups.size(); ++gi) {
         const Group& g = groups[gi];
         unsigned* ctr = (unsigned*)work + 8 * g.v;  // each variant appears in one group
-        const Tiers t = make_tiers_at(c, g.p, ctr, (int2*)(work + w.lists_off) + g.first,
-                                      (int2*)(work + w.listb_off) + g.first, (long long*)(work + w.scratch_off),
-                                      g.count, g.v / 2 + 1);
-        e = dispatch_batch_group(c, g.v, djobs, g.j0, g.nj, g.first, g.count, g.p, t, ctr, st);
+        const Tiers t = make_tiers_at(c, g.p, ctr, (int2*)(work + w.lists_off), (int2*)(work + w.listb_off),
+                                      (long long*)(work + w.scratch_off), g.count, g.v / 2 + 1);
+        e = dispatch_batch_group(c, g.v, djobs, dhdr + g.v, g.count, g.p, t, ctr, st);
         if (e != hipSuccess) return hip_fail(c, e, "batch kernel launch");
     }
     e = hipEventRecord(sl.done, st);
     if (e != hipSuccess) return hip_fail(c, e, "batch kernel launch");
+    return BSF_OK;
+}
+
+bsf_status bsf_batch_plan_destroy(bsf_batch_plan* p) {
+    if (!p) return BSF_ERR_INVALID_ARG;
+    if (p->ctx) (void)hipSetDevice(p->ctx->device);
+    if (p->done) (void)hipEventSynchronize(p->done);
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->done) (void)hipEventDestroy(p->done);
+    if (p->dev) (void)hipFree(p->dev);
+    if (p->host) (void)hipHostFree(p->host);
+    if (p->herr) (void)hipHostFree(p->herr);
+    delete p;
+    return BSF_OK;
+}
+
+bsf_status bsf_batch_plan_create(bsf_ctx* c, int max_jobs, long long max_tiles, float a_max, bsf_batch_plan** out) {
+    if (!c || !out) return BSF_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (max_jobs < 1 || max_jobs > (1 << 20)) return fail(c, BSF_ERR_INVALID_ARG, "max_jobs must lie in [1, 2^20]");
+    if (max_tiles < 1 || max_tiles >= (1ll << 31)) return fail(c, BSF_ERR_INVALID_ARG, "max_tiles must lie in [1, 2^31)");
+    if (!(a_max >= (float)kScaleMin && a_max <= (float)kScaleMax))
+        return fail(c, BSF_ERR_INVALID_ARG, "a plan's a_max must lie in [0.5, 1e4]");
+    constexpr int kVariants = 6;
+    Plan pv[kVariants];
+    size_t scratch_bytes = 0;
+    for (int v = 0; v < kVariants; ++v) {
+        const int n = v / 2 + 1;
+        pv[v] = plan_tiers(c, window_bound(n, a_max) + 64, n);
+        if (!bsf_plan::plan_fits(c->limits(), pv[v], n))
+            return fail(c, BSF_ERR_UNSUPPORTED, "the launch's LDS exceeds the device's limit");
+        if (pv[v].use3)
+            scratch_bytes = std::max(scratch_bytes, (size_t)bsf_plan::grid3_of(c->limits(), max_tiles) * (size_t)pv[v].t3 * 8);
+    }
+    const WorkLayout w = work_layout(max_tiles, max_jobs + kHdrSlots, scratch_bytes);
+    const size_t err_off = (w.total + 255) & ~(size_t)255;
+    const size_t bytes = err_off + 4 * (size_t)max_jobs;
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+    bsf_batch_plan* p = new bsf_batch_plan();
+    p->ctx = c;
+    p->max_jobs = max_jobs;
+    p->max_tiles = max_tiles;
+    p->a_max = a_max;
+    p->jobs_off = w.jobs_off;
+    p->err_off = err_off;
+    auto bail = [&](bsf_status st) {
+        bsf_batch_plan_destroy(p);
+        return st;
+    };
+    e = hipMalloc(&p->dev, bytes);
+    if (e != hipSuccess) return bail(hip_fail(c, e, "plan work area"));
+    e = hipHostMalloc((void**)&p->host, sizeof(JobDesc) * (size_t)(max_jobs + kHdrSlots));
+    if (e != hipSuccess) return bail(hip_fail(c, e, "plan descriptor staging"));
+    std::memset((void*)p->host, 0, sizeof(JobDesc) * (size_t)(max_jobs + kHdrSlots));
+    e = hipHostMalloc((void**)&p->herr, 4 * (size_t)max_jobs);
+    if (e != hipSuccess) return bail(hip_fail(c, e, "plan error staging"));
+    std::memset(p->herr, 0, 4 * (size_t)max_jobs);
+    e = hipEventCreateWithFlags(&p->done, hipEventDisableTiming);
+    if (e != hipSuccess) return bail(hip_fail(c, e, "plan event"));
+    opt_in_all_batch_kernels();  // before capture: no attribute calls inside it
+
+    // Capture the launch sequence once on a private stream: upload the staged headers and
+    // descriptors, clear the counters and error words (kernels, no memset nodes), run every
+    // variant's tiers over persistent grids sized for the capacity, fetch the error words.
+    hipStream_t cs = nullptr;
+    e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return bail(hip_fail(c, e, "capture stream"));
+    char* work = (char*)p->dev;
+    unsigned* derr = (unsigned*)(work + err_off);
+    hipGraph_t graph = nullptr;
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t le = hipMemcpyAsync(work + w.jobs_off, p->host, sizeof(JobDesc) * (size_t)(max_jobs + kHdrSlots),
+                                       hipMemcpyHostToDevice, cs);
+        hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, cs, (unsigned*)work);
+        hipLaunchKernelGGL(clear_words, dim3((max_jobs + 255) / 256), dim3(256), 0, cs, derr, max_jobs);
+        const GroupHdr* dhdr = (const GroupHdr*)(work + w.jobs_off);
+        const JobDesc* djobs = (const JobDesc*)(work + w.jobs_off) + kHdrSlots;
+        for (int v = 0; v < kVariants && le == hipSuccess; ++v) {
+            unsigned* ctr = (unsigned*)work + 8 * v;
+            const Tiers t = make_tiers_at(c, pv[v], ctr, (int2*)(work + w.lists_off), (int2*)(work + w.listb_off),
+                                          (long long*)(work + w.scratch_off), max_tiles, v / 2 + 1);
+            le = dispatch_batch_group(c, v, djobs, dhdr + v, max_tiles, pv[v], t, ctr, cs);
+        }
+        if (le == hipSuccess)
+            le = hipMemcpyAsync(p->herr, derr, 4 * (size_t)max_jobs, hipMemcpyDeviceToHost, cs);
+        e = hipStreamEndCapture(cs, &graph);
+        if (le != hipSuccess) e = le;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) return bail(hip_fail(c, e, "capturing the plan's launch sequence"));
+    *out = p;
+    return BSF_OK;
+}
+
+bsf_status bsf_batch_plan_run(bsf_batch_plan* p, const bsf_job* jobs, int njobs, void* stream) {
+    if (!p) return BSF_ERR_INVALID_ARG;
+    bsf_ctx* c = p->ctx;
+    if (njobs < 0 || (njobs > 0 && !jobs)) return fail(c, BSF_ERR_INVALID_ARG, "bad batch");
+    if (njobs > p->max_jobs) return fail(c, BSF_ERR_INVALID_ARG, "more jobs than the plan holds");
+    constexpr int kVariants = 6;
+    std::vector<int> order(njobs);
+    std::vector<double> cost(njobs);
+    double vcost[kVariants] = {};
+    long long total = 0;
+    for (int i = 0; i < njobs; ++i) {
+        bsf_status s = validate(c, jobs + i, true);
+        if (s != BSF_OK) return fail(c, s, "job " + std::to_string(i) + ": " + c->last);
+        if (!(jobs[i].a_max > 0.0f && jobs[i].a_max <= p->a_max))
+            return fail(c, BSF_ERR_INVALID_ARG, "job " + std::to_string(i) + ": a_max must lie in (0, the plan's a_max]");
+        const int n = jobs[i].order;
+        cost[i] = (double)jobs[i].width * jobs[i].height * std::pow(n + 1.0, 4) * 7.0 * n * n;
+        vcost[(n - 1) * 2 + (int)jobs[i].path] += cost[i];
+        total += (long long)((jobs[i].width + kTile - 1) / kTile) * ((jobs[i].height + kTile - 1) / kTile);
+        order[i] = i;
+    }
+    if (total > p->max_tiles) return fail(c, BSF_ERR_INVALID_ARG, "the batch has more tiles than the plan holds");
+    auto var = [&](int i) { return (jobs[i].order - 1) * 2 + (int)jobs[i].path; };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        const int va = var(a), vb = var(b);
+        if (va != vb) return vcost[va] > vcost[vb] || (vcost[va] == vcost[vb] && va < vb);
+        return cost[a] > cost[b];
+    });
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+    // the staging is read by the previous replay's first node: wait until that replay is done
+    e = hipEventSynchronize(p->done);
+    if (e != hipSuccess) return hip_fail(c, e, "waiting for the plan's previous run");
+    unsigned* derr = (unsigned*)((char*)p->dev + p->err_off);
+    GroupHdr* hhdr = reinterpret_cast<GroupHdr*>(p->host);
+    for (int v = 0; v < kVariants; ++v) hhdr[v] = GroupHdr{0, 0, 0, 0};
+    long long item = 0;
+    for (int k = 0; k < njobs;) {
+        const int v = var(order[k]);
+        GroupHdr h{k, 0, item, 0};
+        while (k < njobs && var(order[k]) == v) {
+            JobDesc d = make_desc(jobs + order[k], derr + order[k]);
+            d.item_base = item;
+            item += (long long)d.tiles_x * d.tiles_y;
+            p->host[kHdrSlots + k] = d;
+            ++k;
+            ++h.nj;
+        }
+        h.count = item - h.first;
+        hhdr[v] = h;
+    }
+    e = hipGraphLaunch(p->exec, (hipStream_t)stream);
+    if (e == hipSuccess) e = hipEventRecord(p->done, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "plan replay");
+    p->last_njobs = njobs;
+    return BSF_OK;
+}
+
+bsf_status bsf_batch_plan_job_status(bsf_batch_plan* p, int* status, int njobs) {
+    if (!p || (njobs > 0 && !status)) return BSF_ERR_INVALID_ARG;
+    if (njobs < 0 || njobs > p->last_njobs) return fail(p->ctx, BSF_ERR_INVALID_ARG, "more jobs than the last run had");
+    hipError_t e = hipSetDevice(p->ctx->device);
+    if (e == hipSuccess) e = hipEventSynchronize(p->done);
+    if (e != hipSuccess) return hip_fail(p->ctx, e, "waiting for the plan's run");
+    for (int i = 0; i < njobs; ++i) {
+        const unsigned h = p->herr[i];
+        status[i] = (h & kErrScale) ? BSF_ERR_SCALE_RANGE
+                    : (h & kErrWindow) ? BSF_ERR_UNSUPPORTED
+                    : (h & kErrRange) ? BSF_ERR_RANGE
+                                      : BSF_OK;
+    }
     return BSF_OK;
 }
 
@@ -2527,8 +2774,8 @@ bsf_status bsf_scales_from_ellipses(bsf_ctx* c, const float* ellipses, ptrdiff_t
 
 bsf_status bsf_filter1d_max_scale(bsf_ctx* c, int order, int model, float* a_max) {
     if (!c) return BSF_ERR_INVALID_ARG;
-    if (order < 1 || order > 3 || model < -1 || model > 1 || !a_max)
-        return fail(c, BSF_ERR_INVALID_ARG, "order must be 1..3 and model -1..1");
+    if (order < 1 || order > 3 || model < -1 || model > 3 || !a_max)
+        return fail(c, BSF_ERR_INVALID_ARG, "order must be 1..3 and model -1..3");
     *a_max = (float)filter1d_max_scale(c, order, order + model);
     return BSF_OK;
 }
@@ -2545,7 +2792,7 @@ bsf_status bsf_filter1d(bsf_ctx* c, const bsf_job1d* j, void* stream) {
         return fail(c, BSF_ERR_INVALID_ARG, "bad input dtype");
     if (j->border != BSF_BORDER_CLAMP && j->border != BSF_BORDER_ZERO) return fail(c, BSF_ERR_INVALID_ARG, "bad border");
     if (j->order < 1 || j->order > 3) return fail(c, BSF_ERR_INVALID_ARG, "order must be 1, 2 or 3");
-    if (j->model < -1 || j->model > 1) return fail(c, BSF_ERR_INVALID_ARG, "model degree must be -1, 0 or 1");
+    if (j->model < -1 || j->model > 3) return fail(c, BSF_ERR_INVALID_ARG, "model degree must lie in -1 .. 3");
     if (j->path != BSF_PATH_F64 && j->path != BSF_PATH_F32_TILED) return fail(c, BSF_ERR_INVALID_ARG, "bad path");
     const int n = j->order, D = j->order + j->model, path = (int)j->path;
     const double limit = filter1d_max_scale(c, n, D);
@@ -2589,7 +2836,7 @@ bsf_status bsf_debug_tile_window(bsf_ctx* c, const bsf_job* j, int tile, int64_t
     if (!c) return BSF_ERR_INVALID_ARG;
     bsf_status s = validate(c, j, true);
     if (s != BSF_OK) return s;
-    const JobDesc A = make_desc(j);
+    const JobDesc A = make_desc(j, c->d_err);
     if (tile < 0 || tile >= A.tiles_x * A.tiles_y || !window || !geom)
         return fail(c, BSF_ERR_INVALID_ARG, "bad debug tile arguments");
     const long long full = (c->lds_max_bytes - c->lds_static[j->order]) / 8;
@@ -2597,7 +2844,6 @@ bsf_status bsf_debug_tile_window(bsf_ctx* c, const bsf_job* j, int tile, int64_t
     L.lds_cap = std::min(job_window_need(c, j), full);
     if (!bsf_plan::launch_fits(c->limits(), j->order, L.lds_cap * 8))
         return fail(c, BSF_ERR_UNSUPPORTED, "the launch's LDS exceeds the device's limit");
-    L.err = c->d_err;
     L.dbg_window = (long long*)window;
     L.dbg_geom = geom;
     L.dbg_cap = cap;

@@ -96,6 +96,12 @@ def test_admission_is_fifo_by_footprint_and_slots():
     adm2 = Admission(budget_bytes=10 ** 9, slots=2)
     pend = collections.deque([1, 1, 1])
     assert len(adm2.admit(pend, 8, footprint=lambda r: r)) == 2  # slot limit
+    # the tiles one launch holds: a group stops before the request that would overflow it
+    adm3 = Admission(budget_bytes=10 ** 9, slots=8)
+    pend = collections.deque([300, 500, 300, 100])
+    g = adm3.admit(pend, 8, footprint=lambda r: 1, max_tiles=1000, tiles=lambda r: r)
+    assert g == [300, 500] and list(pend) == [300, 100]
+    assert adm3.admit(pend, 8, footprint=lambda r: 1, max_tiles=1000, tiles=lambda r: r) == [300, 100]
 
 
 def test_rep3_groups_header_is_current(tmp_path):
