@@ -14,8 +14,10 @@ with the HIP path (``paper_0908_3861_amd``) and never imports it.
 * ``preintegrate(window, n)`` -- stage 1 alone: the recursion of Section 7
   (eq. RS, steps (1)-(4)), n times per direction, unit weights, exact integers.
 
-Sibling modules: ``oracle.ellipse`` (the scale field of elliptical windows) and
-``oracle.filter1d`` (the one-dimensional scale-adaptive filter of Section 3, exact rationals).
+Sibling modules: ``oracle.ellipse`` (the scale field of elliptical windows),
+``oracle.filter1d`` (the one-dimensional scale-adaptive filter of Section 3, exact rationals,
+with the prefiltered B-spline models) and ``oracle.rect`` (the two-direction box spline,
+eq. def with N = 2, with any of those models).
 """
 from __future__ import annotations
 

@@ -123,12 +123,20 @@ def coefficients(f, n1: int, border: str, lo: int, hi: int) -> list[Fraction]:
     tridiagonal elimination, in exact rationals)."""
     if n1 <= 1:
         return [Fraction(float(_ext(f, k, border))) for k in range(lo, hi)]
-    b0, b1 = bspline_at_integer(0, n1), bspline_at_integer(1, n1)
     M = PREFILTER_MARGIN
-    ks = list(range(lo - M, hi + M))
-    rhs = [Fraction(float(_ext(f, k, border))) for k in ks]
-    N = len(ks)
-    # unknowns c[1..N-2]; c[0], c[N-1] fixed to the extended samples
+    rhs = [Fraction(float(_ext(f, k, border))) for k in range(lo - M, hi + M)]
+    return solve_block(rhs, n1)[M:M + (hi - lo)]
+
+
+def solve_block(rhs: list, n1: int) -> list[Fraction]:
+    """The coefficients c of one block: b1 c[k-1] + b0 c[k] + b1 c[k+1] = rhs[k] for the inner
+    k, with c at the block's two ends set to rhs there (tridiagonal elimination, exact)."""
+    b0, b1 = bspline_at_integer(0, n1), bspline_at_integer(1, n1)
+    rhs = [Fraction(v) for v in rhs]
+    N = len(rhs)
+    if N < 3:
+        return rhs
+    # unknowns c[1..N-2]; c[0], c[N-1] fixed to the block's end values
     first, last = rhs[0], rhs[-1]
     d = rhs[1:N - 1]
     d[0] -= b1 * first
@@ -146,8 +154,7 @@ def coefficients(f, n1: int, border: str, lo: int, hi: int) -> list[Fraction]:
     x[-1] = dp[-1]
     for i in range(m - 2, -1, -1):
         x[i] = dp[i] - cp[i] * x[i + 1]
-    c = [first] + x + [last]
-    return c[M:M + (hi - lo)]
+    return [first] + x + [last]
 
 
 def _ext(f, k: int, border: str):
