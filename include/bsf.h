@@ -234,6 +234,49 @@ bsf_status bsf_filter1d(bsf_ctx* ctx, const bsf_job1d* job, void* stream);
  * sample, must fit the on-chip memory of one workgroup).  Host only. */
 bsf_status bsf_filter1d_max_scale(bsf_ctx* ctx, int order, int model, float* a_max);
 
+/* Two-direction (rect) space-variant filter: Section 4, eq. def with directional order N = 2
+ * (angles 0 and pi/2), whose box spline is the tensor product of a segment of length a1 along x
+ * (columns) and one of length a2 along y (rows); rect is the one at (1, 1).  Order n is its
+ * n-fold self-convolution beta_a1^(n-1)(x1) beta_a2^(n-1)(x2).  Every pixel m gets the
+ * projection of the image's continuous model onto it at m's own scales (Section 6):
+ *     out[m] = sum_k c_ext[k] K_a1(m1 - k1) K_a2(m2 - k2),   K_a = beta^model * beta_a^(order-1),
+ * with the model f(x) = sum_k c[k] (beta^model x beta^model)(x - k) of degree model = -1
+ * (impulses at the samples, the model of Section 7), 0 or 1 (c = the samples), or 2 or 3
+ * (c = the extended samples filtered by the inverse of b^model x b^model, so that the model
+ * interpolates them; the inverse is truncated where its tail falls below 2^-60), and the
+ * image extended by clamp or zero.  Computed by the two steps of Section 6 with b = (1, 1):
+ * order running sums along rows and columns (eq. RS_filter; the summed-area table for
+ * order 1), then per pixel the (order+1)^2 finite-difference taps of eq. mask interpolated
+ * with the tensor B-spline of degree model + order, on restart windows per tile.  Running
+ * sums and mask carry a compensation term on both paths, which differ only in the output
+ * (BSF_PATH_F64: float64; BSF_PATH_F32_TILED: float32).  scales is [height][scale_pitch][2]
+ * float32 (a1, a2), 8-byte aligned; scales outside [0.5, a_max] (NaN included) give NaN and the
+ * sticky BSF_ERR_SCALE_RANGE flag.  a_max (0 = the largest bsf_filter_rect_max_scale allows)
+ * sizes the windows; beyond that limit the call returns BSF_ERR_UNSUPPORTED.  Models 2 and 3
+ * use a work area of about 16 bytes per pixel of the image plus its halos (context
+ * workspace).  Asynchronous on `stream`. */
+typedef struct {
+    int width, height;              /* >= 1                                                */
+    bsf_dtype in_dtype;             /* u8, f32 or f64                                       */
+    const void* in;                 /* [height][in_pitch] samples                           */
+    ptrdiff_t in_pitch;             /* >= width                                             */
+    const float* scales;            /* [height][scale_pitch][2] = (a1, a2) per pixel        */
+    ptrdiff_t scale_pitch;          /* >= width, in pixels                                  */
+    int order;                      /* n in {1, 2, 3}                                       */
+    int model;                      /* degree of the image model: -1, 0, 1, 2 or 3          */
+    bsf_path path;
+    bsf_border border;
+    float a_max;                    /* bound on every scale (0 = the largest allowed)       */
+    void* out;                      /* [height][out_pitch] float64 (F64) / float32 (F32)   */
+    ptrdiff_t out_pitch;            /* >= width                                             */
+} bsf_job_rect;
+
+bsf_status bsf_filter_rect(bsf_ctx* ctx, const bsf_job_rect* job, void* stream);
+
+/* The largest a_max bsf_filter_rect accepts for this order and model (the restart window of
+ * an 8x8 tile, 16 bytes per element, must fit one workgroup's LDS).  Host only. */
+bsf_status bsf_filter_rect_max_scale(bsf_ctx* ctx, int order, int model, float* a_max);
+
 /* Evaluation counters of the float64 path (Section 7 mesh, eq. final_eqn), kept per
  * context since its creation or the last reset.  A tile whose samples need a single
  * digit evaluates each tap's interpolant with the terms of total degree above 2 (order

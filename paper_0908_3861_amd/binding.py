@@ -50,6 +50,17 @@ class Job1d(ctypes.Structure):
     ]
 
 
+class JobRect(ctypes.Structure):
+    _fields_ = [
+        ("width", ctypes.c_int), ("height", ctypes.c_int),
+        ("in_dtype", ctypes.c_int), ("in_", ctypes.c_void_p), ("in_pitch", ctypes.c_ssize_t),
+        ("scales", ctypes.c_void_p), ("scale_pitch", ctypes.c_ssize_t),
+        ("order", ctypes.c_int), ("model", ctypes.c_int), ("path", ctypes.c_int), ("border", ctypes.c_int),
+        ("a_max", ctypes.c_float),
+        ("out", ctypes.c_void_p), ("out_pitch", ctypes.c_ssize_t),
+    ]
+
+
 _lib = None
 _lock = threading.Lock()
 
@@ -79,6 +90,8 @@ def load():
             lib.bsf_scales_from_ellipses.argtypes = [vp, vp, ctypes.c_ssize_t, i, i, i, vp, ctypes.c_ssize_t, vp]
             lib.bsf_filter1d.argtypes = [vp, ctypes.POINTER(Job1d), vp]
             lib.bsf_filter1d_max_scale.argtypes = [vp, i, i, ctypes.POINTER(ctypes.c_float)]
+            lib.bsf_filter_rect.argtypes = [vp, ctypes.POINTER(JobRect), vp]
+            lib.bsf_filter_rect_max_scale.argtypes = [vp, i, i, ctypes.POINTER(ctypes.c_float)]
             lib.bsf_status_string.argtypes = [i]
             lib.bsf_status_string.restype = ctypes.c_char_p
             lib.bsf_last_error.argtypes = [vp]
@@ -86,7 +99,7 @@ def load():
             lib.bsf_debug_tile_window.argtypes = [vp, jp, i, vp, ctypes.c_longlong, vp, vp]
             for fn in ("bsf_create", "bsf_destroy", "bsf_workspace_size", "bsf_filter", "bsf_filter_batched",
                        "bsf_filter_noalloc", "bsf_batch_plan_create", "bsf_batch_plan_run", "bsf_batch_plan_job_status",
-                       "bsf_batch_plan_destroy",
+                       "bsf_batch_plan_destroy", "bsf_filter_rect", "bsf_filter_rect_max_scale",
                        "bsf_preintegrate", "bsf_get_device_error", "bsf_get_counters", "bsf_scales_from_ellipses",
                        "bsf_debug_tile_window", "bsf_filter1d", "bsf_filter1d_max_scale"):
                 getattr(lib, fn).restype = i
@@ -412,3 +425,54 @@ def debug_tile_window(img, scales, order: int, tile: int, centred: bool, path: s
     torch.cuda.synchronize()
     x0, y0, wq, hq, _, ovf, sh, _ = [int(v) for v in geom.cpu()]
     return win[: wq * hq].view(hq, wq).cpu().numpy(), (x0, y0, wq, hq), bool(ovf)
+
+
+def filter_rect_max_scale(order: int, model: int = -1, ctx: Context | None = None) -> float:
+    """The largest scale bound bsf_filter_rect accepts for this order and model."""
+    ctx = ctx or default_context()
+    v = ctypes.c_float()
+    ctx._check(ctx.lib.bsf_filter_rect_max_scale(ctx.handle, int(order), int(model), ctypes.byref(v)))
+    return float(v.value)
+
+
+def filter_rect(img, scales, order: int, model: int = -1, path: str = "f64", border: str = "clamp",
+                a_max: float | None = None, out=None, ctx: Context | None = None, stream=None, check: bool = False):
+    """Two-direction (rect) adaptive filter (bsf_filter_rect) of a device image [H, W]
+    (uint8/float32/float64) with float32 scales [H, W, 2] = (a1 along x, a2 along y).
+    ``a_max`` defaults to the largest scale (one device reduction and a host sync)."""
+    import torch
+    ctx = ctx or default_context(img.device.index)
+    if img.dim() != 2 or scales.dim() != 3 or scales.shape[2] != 2 or tuple(scales.shape[:2]) != tuple(img.shape):
+        raise ValueError("expected img [H, W] and scales [H, W, 2]")
+    if not (img.is_cuda and scales.is_cuda):
+        raise ValueError("img and scales must be device tensors")
+    if scales.dtype != torch.float32 or scales.stride(2) != 1 or scales.stride(1) != 2 or img.stride(1) != 1:
+        raise ValueError("scales must be float32 with contiguous (a1, a2) per pixel; image rows contiguous")
+    H, W = img.shape
+    odt = torch.float64 if path == "f64" else torch.float32
+    if out is None:
+        with _on(stream):
+            out = torch.empty((H, W), dtype=odt, device=img.device)
+    elif out.dtype != odt or tuple(out.shape) != (H, W) or out.stride(1) != 1:
+        raise ValueError("bad output tensor")
+    if a_max is None:
+        with _on(stream):
+            a_max = float(scales.max().item())
+    j = JobRect()
+    j.width, j.height = W, H
+    j.in_dtype = _dtype_code(img)
+    j.in_ = img.data_ptr()
+    j.in_pitch = img.stride(0)
+    j.scales = scales.data_ptr()
+    j.scale_pitch = scales.stride(0) // 2
+    j.order = int(order)
+    j.model = int(model)
+    j.path = PATHS[path]
+    j.border = BORDERS[border]
+    j.a_max = float(a_max)
+    j.out = out.data_ptr()
+    j.out_pitch = out.stride(0)
+    ctx._check(ctx.lib.bsf_filter_rect(ctx.handle, ctypes.byref(j), _stream_ptr(stream)))
+    if check:
+        ctx.check_device(stream)
+    return out

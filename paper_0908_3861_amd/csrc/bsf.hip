@@ -1789,6 +1789,8 @@ __global__ __launch_bounds__(256) void ellipse_scales_kernel(const float* __rest
 // ===========================================================================
 // Host side: the C ABI.
 // ===========================================================================
+#include "rect.h"
+
 // Work area of bsf_filter_noalloc: a fixed array in device memory, one copy per GPU the
 // library runs on, held until the process ends.  Host code never passes this symbol to a
 // kernel (on the host it names a stand-in, not device memory): it uses the device address
@@ -2249,6 +2251,65 @@ double filter1d_max_scale(const bsf_ctx* c, int n, int D) {
         (fits(mid) ? lo : hi) = mid;
     }
     return std::floor(lo * 8.0) / 8.0;
+}
+
+}  // namespace
+
+namespace {
+
+template <int N, int D, int SRC>
+hipError_t launch_rect(const bsf::rect::Args& A, int blocks, long long lds, hipStream_t st) {
+    static bool opted = false;
+    if (!opted) {
+        allow_big_lds(bsf::rect::rect_kernel<N, D, SRC>);
+        opted = true;
+    }
+    hipLaunchKernelGGL((bsf::rect::rect_kernel<N, D, SRC>), dim3(blocks), dim3(bsf::rect::kThreads), (size_t)lds, st, A);
+    return hipGetLastError();
+}
+
+template <int SRC>
+hipError_t dispatch_rect_src(int n, int D, const bsf::rect::Args& A, int blocks, long long lds, hipStream_t st) {
+    // D = model degree + n, model in -1..3
+    switch (n * 8 + D) {
+        case 1 * 8 + 0: return launch_rect<1, 0, SRC>(A, blocks, lds, st);
+        case 1 * 8 + 1: return launch_rect<1, 1, SRC>(A, blocks, lds, st);
+        case 1 * 8 + 2: return launch_rect<1, 2, SRC>(A, blocks, lds, st);
+        case 1 * 8 + 3: return launch_rect<1, 3, SRC>(A, blocks, lds, st);
+        case 1 * 8 + 4: return launch_rect<1, 4, SRC>(A, blocks, lds, st);
+        case 2 * 8 + 1: return launch_rect<2, 1, SRC>(A, blocks, lds, st);
+        case 2 * 8 + 2: return launch_rect<2, 2, SRC>(A, blocks, lds, st);
+        case 2 * 8 + 3: return launch_rect<2, 3, SRC>(A, blocks, lds, st);
+        case 2 * 8 + 4: return launch_rect<2, 4, SRC>(A, blocks, lds, st);
+        case 2 * 8 + 5: return launch_rect<2, 5, SRC>(A, blocks, lds, st);
+        case 3 * 8 + 2: return launch_rect<3, 2, SRC>(A, blocks, lds, st);
+        case 3 * 8 + 3: return launch_rect<3, 3, SRC>(A, blocks, lds, st);
+        case 3 * 8 + 4: return launch_rect<3, 4, SRC>(A, blocks, lds, st);
+        case 3 * 8 + 5: return launch_rect<3, 5, SRC>(A, blocks, lds, st);
+        default: return launch_rect<3, 6, SRC>(A, blocks, lds, st);
+    }
+}
+
+// LDS a rect workgroup may hold: the device's limit less the kernels' (small) static LDS
+long long rect_lds_cap(const bsf_ctx* c) { return std::min<long long>(c->lds_max_bytes, 163840) - 1024; }
+
+// The tile side for (n, D, a_max): the largest of 32, 16, 8 whose window fits (0: none)
+int rect_tile(const bsf_ctx* c, int n, int D, double a_max) {
+    for (int T : {32, 16, 8})
+        if (bsf::rect::lds_bytes(T, n, D, a_max) <= rect_lds_cap(c)) return T;
+    return 0;
+}
+
+double rect_max_scale(const bsf_ctx* c, int n, int D) {
+    auto fits = [&](double a) { return rect_tile(c, n, D, a) > 0; };
+    if (!fits(0.5)) return 0.0;
+    double lo = 0.5, hi = 1e4;
+    if (fits(hi)) return hi;
+    for (int i = 0; i < 60; ++i) {
+        const double mid = 0.5 * (lo + hi);
+        (fits(mid) ? lo : hi) = mid;
+    }
+    return std::floor(lo * 4.0) / 4.0;  // a quarter-pixel grid: exact in float32
 }
 
 }  // namespace
@@ -2825,6 +2886,109 @@ bsf_status bsf_filter1d(bsf_ctx* c, const bsf_job1d* j, void* stream) {
         e = dispatch_filter1d(n, D, path, A, (int)(tiles * j->count), bsf::f1d::lds_bytes(D, A.W, path),
                               (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(c, e, "filter1d launch");
+    return BSF_OK;
+}
+
+bsf_status bsf_filter_rect_max_scale(bsf_ctx* c, int order, int model, float* a_max) {
+    if (!c) return BSF_ERR_INVALID_ARG;
+    if (order < 1 || order > 3 || model < -1 || model > 3 || !a_max)
+        return fail(c, BSF_ERR_INVALID_ARG, "order must be 1..3 and model -1..3");
+    *a_max = (float)rect_max_scale(c, order, order + model);
+    return BSF_OK;
+}
+
+bsf_status bsf_filter_rect(bsf_ctx* c, const bsf_job_rect* j, void* stream) {
+    if (!c) return BSF_ERR_INVALID_ARG;
+    if (!j) return fail(c, BSF_ERR_INVALID_ARG, "job is null");
+    if (j->width < 1 || j->height < 1) return fail(c, BSF_ERR_INVALID_ARG, "width and height must be >= 1");
+    if (j->width > (1 << 24) || j->height > (1 << 24)) return fail(c, BSF_ERR_INVALID_ARG, "image too large");
+    if (!j->in || !j->scales || !j->out) return fail(c, BSF_ERR_INVALID_ARG, "null buffer");
+    if (((uintptr_t)j->scales) % 8) return fail(c, BSF_ERR_INVALID_ARG, "scales must be 8-byte aligned");
+    if (j->in_pitch < j->width || j->scale_pitch < j->width || j->out_pitch < j->width)
+        return fail(c, BSF_ERR_INVALID_ARG, "pitches must be >= width");
+    if (j->in_dtype != BSF_U8 && j->in_dtype != BSF_F32 && j->in_dtype != BSF_F64)
+        return fail(c, BSF_ERR_INVALID_ARG, "bad input dtype");
+    if (j->border != BSF_BORDER_CLAMP && j->border != BSF_BORDER_ZERO) return fail(c, BSF_ERR_INVALID_ARG, "bad border");
+    if (j->order < 1 || j->order > 3) return fail(c, BSF_ERR_INVALID_ARG, "order must be 1, 2 or 3");
+    if (j->model < -1 || j->model > 3) return fail(c, BSF_ERR_INVALID_ARG, "model degree must lie in -1 .. 3");
+    if (j->path != BSF_PATH_F64 && j->path != BSF_PATH_F32_TILED) return fail(c, BSF_ERR_INVALID_ARG, "bad path");
+    const int n = j->order, D = j->order + j->model;
+    double a_max = j->a_max;
+    if (!(a_max == 0.0 || (a_max >= 0.5 && a_max <= 1e4)))
+        return fail(c, BSF_ERR_INVALID_ARG, "a_max must be 0 or lie in [0.5, 1e4]");
+    const double limit = rect_max_scale(c, n, D);
+    if (a_max == 0.0) a_max = limit;
+    if (a_max > limit)
+        return fail(c, BSF_ERR_UNSUPPORTED, "a_max " + std::to_string(a_max) +
+                                                " exceeds the largest scale whose window fits on chip (" +
+                                                std::to_string(limit) + ")");
+    bsf::rect::Args A{};
+    A.in = j->in;
+    A.in_pitch = j->in_pitch;
+    A.dtype = (int)j->in_dtype;
+    A.border = (int)j->border;
+    A.scales = j->scales;
+    A.sc_pitch = j->scale_pitch;
+    A.out = j->out;
+    A.out_pitch = j->out_pitch;
+    A.width = j->width;
+    A.height = j->height;
+    A.path = (int)j->path;
+    A.T = rect_tile(c, n, D, a_max);
+    A.tiles_x = (j->width + A.T - 1) / A.T;
+    A.tiles_y = (j->height + A.T - 1) / A.T;
+    A.left = bsf::rect::halo_left(n, D, a_max);
+    A.right = bsf::rect::halo_right(n, D, a_max);
+    A.wx = A.T + A.left + A.right;
+    A.pitch = bsf::rect::lds_pitch(A.wx);
+    A.a_max = (float)a_max;
+    A.err = c->d_err;
+    const long long lds = bsf::rect::lds_bytes(A.T, n, D, a_max);
+    const long long tiles = (long long)A.tiles_x * A.tiles_y;
+    if (tiles > 0x7fffffffll) return fail(c, BSF_ERR_INVALID_ARG, "image too large");
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+    if (j->model <= 1) {
+        e = dispatch_rect_src<0>(n, D, A, (int)tiles, lds, st);
+        if (e != hipSuccess) return hip_fail(c, e, "rect kernel launch");
+        return BSF_OK;
+    }
+    // degree-2/3 models: c = f_ext filtered by the inverse interpolation filter, over the
+    // domain every window reads, in a work slot (rows pass into h, columns pass into c)
+    const int K = j->model == 2 ? bsf::f1d::Prefilter<2>::K : bsf::f1d::Prefilter<3>::K;
+    bsf::rect::PrefArgs Pa{};
+    Pa.in = j->in;
+    Pa.in_pitch = j->in_pitch;
+    Pa.dtype = (int)j->in_dtype;
+    Pa.border = (int)j->border;
+    Pa.width = j->width;
+    Pa.height = j->height;
+    Pa.org = -A.left;
+    Pa.cw = A.tiles_x * A.T + A.left + A.right;
+    Pa.ch = A.tiles_y * A.T + A.left + A.right;
+    Pa.pitch = ((long long)Pa.cw + 31) & ~31ll;
+    const size_t hbytes = (size_t)(Pa.ch + 2 * K) * Pa.pitch * 8, cbytes = (size_t)Pa.ch * Pa.pitch * 8;
+    int slot = -1;
+    bsf_status s = acquire_slot(c, hbytes + cbytes, 0, slot);
+    if (s != BSF_OK) return s;
+    Pa.h = (double*)c->slot[slot].dev;
+    Pa.c = Pa.h + (size_t)(Pa.ch + 2 * K) * Pa.pitch;
+    A.cbuf = Pa.c;
+    A.cpitch = Pa.pitch;
+    const long long hn = (long long)(Pa.ch + 2 * K) * Pa.cw, cn = (long long)Pa.ch * Pa.cw;
+    const int gh = (int)std::min<long long>((hn + 255) / 256, 65536), gc = (int)std::min<long long>((cn + 255) / 256, 65536);
+    if (j->model == 2) {
+        hipLaunchKernelGGL(bsf::rect::rect_prefilter_rows<2>, dim3(gh), dim3(256), 0, st, Pa);
+        hipLaunchKernelGGL(bsf::rect::rect_prefilter_cols<2>, dim3(gc), dim3(256), 0, st, Pa);
+    } else {
+        hipLaunchKernelGGL(bsf::rect::rect_prefilter_rows<3>, dim3(gh), dim3(256), 0, st, Pa);
+        hipLaunchKernelGGL(bsf::rect::rect_prefilter_cols<3>, dim3(gc), dim3(256), 0, st, Pa);
+    }
+    e = hipGetLastError();
+    if (e == hipSuccess) e = dispatch_rect_src<1>(n, D, A, (int)tiles, lds, st);
+    if (e == hipSuccess) e = hipEventRecord(c->slot[slot].done, st);
+    if (e != hipSuccess) return hip_fail(c, e, "rect kernel launch");
     return BSF_OK;
 }
 

@@ -2,9 +2,10 @@
 //
 // Every output sample m is the projection of the signal's continuous model onto the
 // B-spline of degree n-1 and scale a[m] centred at m.  The model is
-// f(x) = sum_k c[k] beta^{n1}(x - k) with n1 in {-1, 0, 1} (n1 = -1: impulses at the samples;
-// n1 = 0, 1: the interpolation filter is the unit impulse, c = f).  Proposition 3.1 computes
-// it in two steps:
+// f(x) = sum_k c[k] beta^{n1}(x - k) with n1 in {-1, 0, 1, 2, 3} (n1 = -1: impulses at the
+// samples; n1 = 0, 1: the interpolation filter is the unit impulse, c = f; n1 = 2, 3: c is the
+// extended signal filtered by the inverse of b^{n1}[k] = beta^{n1}(k), the model interpolating
+// the samples).  Proposition 3.1 computes it in two steps:
 //   1. non-adaptive: g = n-fold running sum of c (the filter u_1^n, eq. RS with b = 1);
 //   2. adaptive: F(x) = sum_k g[k] beta^D(x + tau - k) with D = n1 + n, tau = (a-1) n / 2,
 //      and s[m] = Delta_a^n F(m) = a^-n sum_j (-1)^j C(n,j) F(m - a j) (eq. FD).
@@ -68,6 +69,27 @@ __host__ inline long long lds_bytes(int D, int W, int path) {
     return 16ll * W + (path == 0 ? 16ll : 8ll) * W * (D + 1);
 }
 
+// The prefilter of the degree-2 and degree-3 models (Section 3, c = f * (b^{n1})^{-1}): the
+// inverse of the symmetric filter (b1, b0, b1) is the two-sided exponential rho z^|k|, with
+// z the root of b1 z^2 + b0 z + b1 inside the unit circle and rho = 1 / (b1 (z - 1/z)):
+// z = 2 sqrt2 - 3, rho = sqrt2 for degree 2; z = sqrt3 - 2, rho = sqrt3 for degree 3.  It is
+// truncated at |k| <= K: the dropped tail is at most 2 rho |z|^(K+1) / (1 - |z|) of max |f|,
+// below 2^-60 for K = 24 (degree 2) and K = 32 (degree 3).
+template <int M>
+struct Prefilter {
+    static constexpr int K = 0;
+};
+template <>
+struct Prefilter<2> {
+    static constexpr int K = 24;
+    static constexpr double z = -0.1715728752538099, rho = 1.4142135623730951;
+};
+template <>
+struct Prefilter<3> {
+    static constexpr int K = 32;
+    static constexpr double z = -0.2679491924311227, rho = 1.7320508075688772;
+};
+
 struct cpair {
     double s, c;
 };
@@ -121,12 +143,13 @@ __device__ __forceinline__ cpair cp_weighted(long long w, cpair v) {
     return {h.hi, h.lo + v.c * (double)w};
 }
 
-template <typename T>
-__device__ __forceinline__ void load_window(const Args& A, const T* row, int P, double2* gbuf) {
+// The extended samples f_ext[P + idx], idx = 0 .. count-1, handed to put(idx, value).
+template <typename T, typename Put>
+__device__ __forceinline__ void load_window(const Args& A, const T* row, int P, int count, Put put) {
     const int L = A.length;
     const bool zero_border = A.border != 0;
     // four samples per thread in flight at a time
-    for (int base = threadIdx.x; base < A.W; base += 4 * kThreads) {
+    for (int base = threadIdx.x; base < count; base += 4 * kThreads) {
         double x[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -134,14 +157,22 @@ __device__ __forceinline__ void load_window(const Args& A, const T* row, int P, 
             const int k = P + idx;
             const bool inside = k >= 0 && k < L;
             const int kc = k < 0 ? 0 : (k >= L ? L - 1 : k);
-            x[r] = (idx < A.W && !(zero_border && !inside)) ? (double)row[kc] : 0.0;
+            x[r] = (idx < count && !(zero_border && !inside)) ? (double)row[kc] : 0.0;
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int idx = base + r * kThreads;
-            if (idx < A.W) gbuf[idx] = make_double2(x[r], 0.0);
+            if (idx < count) put(idx, x[r]);
         }
     }
+}
+
+template <typename Put>
+__device__ __forceinline__ void load_any(const Args& A, int b, int P, int count, Put put) {
+    const long long off = (long long)b * A.in_pitch;
+    if (A.dtype == 0) load_window(A, static_cast<const unsigned char*>(A.in) + off, P, count, put);
+    else if (A.dtype == 1) load_window(A, static_cast<const float*>(A.in) + off, P, count, put);
+    else load_window(A, static_cast<const double*>(A.in) + off, P, count, put);
 }
 
 // PATH 0: float64 output, every step compensated.  PATH 1: float32 output; the running sums
@@ -170,12 +201,27 @@ __global__ __launch_bounds__(kThreads) void filter1d_kernel(Args A) {
         af[q] = m < L ? A.scales[(long long)b * A.sc_pitch + m] : 1.0f;
     }
 
-    // ---- the window's samples, coalesced, into LDS ----------------------------------------
-    {
-        const long long off = (long long)b * A.in_pitch;
-        if (A.dtype == 0) load_window(A, static_cast<const unsigned char*>(A.in) + off, P, gbuf);
-        else if (A.dtype == 1) load_window(A, static_cast<const float*>(A.in) + off, P, gbuf);
-        else load_window(A, static_cast<const double*>(A.in) + off, P, gbuf);
+    // ---- the window's coefficients c, coalesced, into LDS -----------------------------------
+    constexpr int MODEL = D - N;
+    if constexpr (MODEL >= 2) {
+        // c = f_ext * (b^{MODEL})^{-1} on the window: the extended samples of the window and K
+        // more on each side go to the table area (free until the tables are built), then every
+        // position sums its truncated two-sided exponential, Horner in z over the pairs
+        // f[k-j] + f[k+j] (the terms shrink geometrically, so the sum is accurate to a few ulps).
+        using PF = Prefilter<MODEL>;
+        double* fx = reinterpret_cast<double*>(gbuf + W);
+        load_any(A, b, P - PF::K, W + 2 * PF::K, [&](int idx, double v) { fx[idx] = v; });
+        __syncthreads();
+        for (int idx = tid; idx < W; idx += kThreads) {
+            const double* f0 = fx + idx + PF::K;  // f_ext at this position
+            double acc = f0[-PF::K] + f0[PF::K];
+#pragma unroll
+            for (int j = PF::K - 1; j >= 1; --j) acc = __fma_rn(acc, PF::z, f0[-j] + f0[j]);
+            acc = __fma_rn(acc, PF::z, f0[0]);
+            gbuf[idx] = make_double2(PF::rho * acc, 0.0);
+        }
+    } else {
+        load_any(A, b, P, W, [&](int idx, double v) { gbuf[idx] = make_double2(v, 0.0); });
     }
     __syncthreads();
 

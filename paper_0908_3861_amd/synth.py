@@ -30,6 +30,7 @@ import numpy as np
 __all__ = [
     "unit_grid_image", "blurred_u8_image", "integer_scales", "uniform_scales",
     "smooth_scales", "smooth_scales_1d", "Job", "config_job", "batch_jobs", "serving_requests", "CONFIGS",
+    "rect_workload",
 ]
 
 
@@ -112,6 +113,8 @@ CONFIGS = {
                          "orientation in [0,pi) (sigma=32 fields), order 2", seed=6),
     "signal1d": dict(desc="1024 signals x 65536 samples, f32 unit-grid samples, smooth real scales "
                           "[1,16] (knots every 256 samples), order 3, impulse model, clamp", seed=7),
+    "rect": dict(desc="2048x2048 uint8 blurred(sigma=3) noise, two smooth real scale fields [1,16] "
+                      "(sigma=32), two-direction (rect) box spline, order 2, impulse model", seed=8),
 }
 
 
@@ -130,6 +133,16 @@ def ellipse_field(rng: np.random.Generator, h: int, w: int, s_lo: float = 1.0, s
     out[..., 1] = out[..., 0] / (1.0 + (elong_hi - 1.0) * t[1])
     out[..., 2] = np.pi * t[2]
     return out
+
+
+def rect_workload(size: tuple[int, int] = (2048, 2048), seed: int | None = None):
+    """(image [H, W] uint8, scales [H, W, 2] float32) of the two-direction workload: the plain
+    workload's image recipe, and two of its smooth scale fields (a1 along x, a2 along y)."""
+    rng = np.random.default_rng(CONFIGS["rect"]["seed"] if seed is None else seed)
+    h, w = size
+    img = blurred_u8_image(rng, h, w, 3.0)
+    sc = np.ascontiguousarray(smooth_scales(rng, h, w, 1.0, 16.0, 32.0)[..., :2])
+    return img, sc
 
 
 def config_job(name: str, size: tuple[int, int] | None = None, seed: int | None = None) -> Job:

@@ -280,3 +280,82 @@ def test_distinct_pitches_and_many_short_signals(torch_dev):
     assert rel_max(s[rows], o) < TOL
     s32 = run(torch, sig, sc, 3, -1, a_max=4.0, path="f32tiled")
     assert rel_max(s32[rows], o) < F32_TOL
+
+
+# --- prefiltered models (degree 2 and 3): the IIR inverse of the interpolation filter --------
+
+PF_MODELS = [(n, n1) for n in (1, 2, 3) for n1 in (2, 3)]
+
+
+@pytest.mark.parametrize("n,n1", PF_MODELS)
+@pytest.mark.parametrize("border", ["clamp", "zero"])
+def test_prefiltered_models_parity(torch_dev, n, n1, border):
+    """Both paths against the exact oracle (prefilter solved in rationals), ragged signals over
+    several tiles, smallest scales included (the mask's largest gain)."""
+    rng = np.random.default_rng(2100 + 10 * n + n1 + (0 if border == "clamp" else 5))
+    count, L = 2, 1100
+    sig = synth.unit_grid_image(rng, count, L, np.float64)
+    sc = rng.uniform(0.5, 12.0, size=(count, L)).astype(np.float32)
+    sc[1, 600:700] = 0.5
+    o = F.filter1d_batch(sig, sc, n, n1, border)
+    s = run(torch_dev, sig, sc, n, n1, border)
+    err = rel_max(s, o)
+    s32 = run(torch_dev, sig.astype(np.float32), sc, n, n1, border, path="f32tiled")
+    err32 = rel_max(s32, o)
+    print(f"prefiltered model {n1}, order {n}, {border}: rel_max f64 {err:.2e}, f32 {err32:.2e}")
+    assert err < TOL and err32 < F32_TOL
+
+
+def test_prefiltered_models_edge_cases(torch_dev):
+    torch = torch_dev
+    rng = np.random.default_rng(2190)
+    for n, n1 in PF_MODELS:
+        # one sample (clamp: a constant signal, reproduced exactly by the model)
+        sig = np.array([[3.25]])
+        sc = np.array([[2.5]], np.float32)
+        assert rel_max(run(torch, sig, sc, n, n1), F.filter1d_batch(sig, sc, n, n1)) < TOL
+        # shorter than the prefilter's reach, zero border, smallest scale
+        sig = synth.unit_grid_image(rng, 3, 20, np.float64)
+        sc = np.full((3, 20), 0.5, np.float32)
+        assert rel_max(run(torch, sig, sc, n, n1, "zero"), F.filter1d_batch(sig, sc, n, n1, "zero")) < TOL
+    # u8 input, exactly two tiles, a bound equal to the largest scale
+    sig = rng.integers(0, 256, size=(2, 512)).astype(np.uint8)
+    sc = rng.uniform(1, 6, size=(2, 512)).astype(np.float32)
+    sc[:, ::9] = 6.0
+    assert rel_max(run(torch, sig, sc, 2, 3, a_max=6.0), F.filter1d_batch(sig, sc, 2, 3)) < TOL
+
+
+@pytest.mark.parametrize("n,n1", [(1, 2), (3, 3)])
+def test_prefiltered_largest_windows(torch_dev, n, n1):
+    torch = torch_dev
+    from paper_0908_3861_amd import binding
+    lim = binding.filter1d_max_scale(n, n1)
+    assert lim > 50.0
+    rng = np.random.default_rng(2195 + n)
+    count, L = 2, 1300
+    sig = synth.unit_grid_image(rng, count, L, np.float64)
+    sc = rng.uniform(0.75 * lim, lim, size=(count, L)).astype(np.float32)
+    sc[0, :3] = np.float32(lim)
+    s = run(torch, sig, sc, n, n1, "clamp", a_max=lim)
+    pr = np.random.default_rng(8)
+    pts = [(0, 0), (0, 1), (1, L - 1), (1, 255), (1, 256)]
+    pts += [(int(b), int(m)) for b, m in zip(pr.integers(0, count, 30), pr.integers(0, L, 30))]
+    o = F.filter1d_batch(sig, sc, n, n1, "clamp", pts)
+    assert rel_max(np.array([s[b, m] for b, m in pts]), o) < TOL
+
+
+def test_prefiltered_full_size_sampled(torch_dev):
+    """The 1024 x 65536 workload shape with the cubic model, on sampled outputs."""
+    torch = torch_dev
+    rng = np.random.default_rng(synth.CONFIGS["signal1d"]["seed"])
+    count, L = 1024, 65536
+    sig = synth.unit_grid_image(rng, count, L, np.float32)
+    sc = synth.smooth_scales_1d(rng, count, L, 1.0, 16.0)
+    s = run(torch, sig, sc, 3, 3, a_max=16.0)
+    pr = np.random.default_rng(9)
+    pts = [(int(b), int(m)) for b, m in zip(pr.integers(0, count, 300), pr.integers(0, L, 300))]
+    pts += [(0, 0), (count - 1, L - 1), (5, 255), (5, 256), (7, L - 257)]
+    o = F.filter1d_batch(sig, sc, 3, 3, "clamp", pts)
+    err = rel_max(np.array([s[b, m] for b, m in pts]), o)
+    print(f"cubic model, full size: rel_max {err:.2e} on {len(pts)} samples")
+    assert err < TOL

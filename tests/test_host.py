@@ -117,7 +117,7 @@ def test_binding_structs_match_the_header(tmp_path):
     """The ctypes job structures have the C layout of include/bsf.h (field offsets and size),
     checked by compiling the header with gcc."""
     from paper_0908_3861_amd import binding
-    structs = {"bsf_job": binding.Job, "bsf_job1d": binding.Job1d}
+    structs = {"bsf_job": binding.Job, "bsf_job1d": binding.Job1d, "bsf_job_rect": binding.JobRect}
     rename = {"in_": "in"}
     lines = ["#include <stdio.h>", "#include <stddef.h>", f'#include "{HDR}"', "int main(void) {"]
     for cname, py in structs.items():
