@@ -8,9 +8,13 @@ path.  Inputs are resident in HBM before timing starts.  Prints one JSON line wi
 Mpixel/s, the roofline of the filter call (HIP events on its launch stream) and the CPU
 oracle timed on a bounded pixel sample.
 
+The default run also times the float32-output path on the same inputs (its speedup and its
+error against the oracle at the same pixels, in extra.f32tiled).
+
 Other forms (not run by default): --workload small | precision | batched | serving | stage1 |
 ellipse (the scale field of elliptical windows, the step before the filter) | signal1d (the
-one-dimensional scale-adaptive filter of Section 3 on a batch of signals).
+one-dimensional scale-adaptive filter of Section 3 on a batch of signals) | rect (the
+two-direction box spline, Section 4 with N = 2).
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu-baseline]
 """
@@ -100,6 +104,24 @@ def oracle_sample(img64, scales, order, pixels_total, cpu_seconds, rng, border="
     t0 = time.perf_counter()
     o = oracle.filter(img64, scales, order, border, pixels=sample)
     return sample, o, time.perf_counter() - t0
+
+
+def kappa_summary(img, scales, order, sample, o, seconds) -> dict:
+    """Percentiles of the cancellation factor kappa(m) = sum|terms| / |s| of the two-stage
+    method on per-pixel restart windows, over the first pixels of the oracle's sample that fit
+    in about `seconds` (the errors above are of order kappa eps; tile windows see more)."""
+    from oracle import kappa as OK
+    ks, worst, t0 = [], 0.0, time.perf_counter()
+    for p, v in zip(sample, o):
+        k, w = OK.kappa(img, scales, order, [p], [v])
+        ks.append(float(k[0]))
+        worst = max(worst, w)
+        if time.perf_counter() - t0 > seconds:
+            break
+    ks = np.array(ks)
+    return {"p50": float(np.percentile(ks, 50)), "p99": float(np.percentile(ks, 99)), "max": float(ks.max()),
+            "pixels": int(len(ks)), "window": "per-pixel restart window",
+            "two_stage_check": worst}
 
 
 def threads_used() -> int:
@@ -216,6 +238,15 @@ def workload_plain(args):
                "sample": f"{len(sample)} random pixels of the same {W}x{H} order-{job.order} workload "
                          f"(direct box-spline sum, float64, OpenMP), {tc:.1f} s"}
         extra["err_vs_oracle"] = errors(out.cpu().numpy().reshape(-1)[sample], o)
+        extra["kappa"] = kappa_summary(job.image, job.scales, job.order, sample, o, args.kappa_seconds)
+    if args.path == "f64" and not args.no_f32_leg:
+        # the float32-output path on the same inputs: its speedup and its error at the same pixels
+        out32, ms32, wall32, _, _ = run_single(args, "plain", job, a_max, "f32tiled")
+        leg = {"filter_ms": ms32, "Mpixel_per_s": P * args.steps / wall32 / 1e6,
+               "speedup_over_f64": ms / ms32}
+        if cpu is not None:
+            leg["err_vs_oracle"] = errors(out32.cpu().numpy().reshape(-1)[sample].astype(np.float64), o)
+        extra["f32tiled"] = leg
     # the global (paper's literal) stage 1 alone over the same image, padded by the
     # halo of the largest scale: R = (n/2)(a + 2a/sqrt2) + 3n, about 42 at n = 2, a = 16
     extra["stage1_global_alone"] = stage1_alone(job, 42, max(3, args.steps // 2), 2)
@@ -333,37 +364,51 @@ def workload_serving(args):
         sc = synth.integer_scales(rng, s, s, 1, 8)
         pool.append((torch.from_numpy(img).pin_memory(), torch.from_numpy(sc).pin_memory(), n,
                      "f64" if f64 else "f32tiled"))
-    srv = serve.Server(budget_bytes=args.budget_gib << 30, slots=args.slots, streams=4)
+    def server(graphs):
+        return serve.Server(budget_bytes=args.budget_gib << 30, slots=args.slots, streams=4, a_max=8.0,
+                            graphs=graphs, max_group=args.slots)
+
     # closed-loop capacity probe: every pool request at once
+    srv = server(True)
     t0 = time.perf_counter()
-    futs = [srv.submit(im, sc, n, path, a_max=8.0) for (im, sc, n, path) in pool]
+    futs = [srv.submit(im, sc, n, path) for (im, sc, n, path) in pool]
     for f in futs:
         f.result()
     probe_s = time.perf_counter() - t0
     capacity = len(pool) / probe_s
     srv.close()
     rate = args.rate if args.rate > 0 else 0.7 * capacity
-    srv = serve.Server(budget_bytes=args.budget_gib << 30, slots=args.slots, streams=4)
     arrivals = np.cumsum(rng.exponential(1.0 / rate, size=int(rate * args.duration * 2) + 10))
     arrivals = arrivals[arrivals < args.duration]
     picks = rng.integers(0, len(pool), size=len(arrivals))
-    t_start = time.perf_counter()
-    futs = []
-    for t_a, k in zip(arrivals, picks):
-        now = time.perf_counter() - t_start
-        if t_a > now:
-            time.sleep(t_a - now)
-        im, sc, n, path = pool[k]
-        futs.append(srv.submit(im, sc, n, path, a_max=8.0))
-    for f in futs:
-        f.result()
-    wall = time.perf_counter() - t_start
-    srv.close()
-    srv.check_device()
-    st = srv.stats()
+
+    def stream_run(graphs):
+        srv = server(graphs)
+        t_start = time.perf_counter()
+        futs = []
+        for t_a, k in zip(arrivals, picks):
+            now = time.perf_counter() - t_start
+            if t_a > now:
+                time.sleep(t_a - now)
+            im, sc, n, path = pool[k]
+            futs.append(srv.submit(im, sc, n, path))
+        for f in futs:
+            f.result()
+        wall = time.perf_counter() - t_start
+        srv.close()
+        st = srv.stats()
+        print(f"serving ({'graph replays' if graphs else 'eager launches'}): {st}", file=sys.stderr, flush=True)
+        return st, wall
+
+    st, wall = stream_run(True)
     extra = {"p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"], "requests": st["completed"],
+             "failed": st["failed"], "launches": st["launches"], "launch_form": "captured batch plans (graph replay)",
              "arrival_rate_hz": rate, "capacity_probe_hz": capacity, "duration_s": args.duration,
              "budget_gib": args.budget_gib, "slots": args.slots, "streams": 4, "pool": len(pool)}
+    if args.serving_compare:
+        st_e, wall_e = stream_run(False)
+        extra["eager"] = {"p50_ms": st_e["p50_ms"], "p99_ms": st_e["p99_ms"], "mean_ms": st_e["mean_ms"],
+                          "Mpixel_per_s": st_e["pixels"] / wall_e / 1e6, "launches": st_e["launches"]}
     config = {"workload": "serving: Poisson stream, square sides log-uniform [128, %d], f32/f64 50/50, "
                           "integer scales U{1..8}, orders U{1,2,3}" % args.max_side}
     return record(st["pixels"] / wall / 1e6, wall, 1, 0, "f64 / f64-mesh+f32-out (mixed)", config,
@@ -531,6 +576,68 @@ def workload_signal1d(args):
                   "f64" if path == "f64" else "f64-compute/f32-out", config, roof, cpu, extra, unit="Msample/s")
 
 
+def rect_flops_per_pixel(order: int, model: int) -> float:
+    """Interpolation-weighted tap MACs of the two-direction mask: (n+1)^2 taps x (D+1)^2
+    tensor B-spline weights x 2, D = model + n."""
+    D = model + order
+    return 2.0 * (order + 1) ** 2 * (D + 1) ** 2
+
+
+def workload_rect(args):
+    """The two-direction (rect, N = 2) filter (bsf_filter_rect): 2048 x 2048 uint8 blurred
+    noise, two smooth scale fields in [1, 16], order 2, impulse model.  One step = one call
+    (restart windows, running sums along rows and columns, the separable mask)."""
+    import torch
+    from paper_0908_3861_amd import binding
+    import oracle.rect as OR
+    order, model, path = 2, -1, args.path
+    img_np, sc_np = synth.rect_workload((args.size, args.size))
+    H, W = img_np.shape
+    dev = torch.device("cuda:0")
+    img = torch.from_numpy(img_np).to(dev)
+    sc = torch.from_numpy(sc_np).to(dev)
+    out = torch.empty((H, W), dtype=torch.float64 if path == "f64" else torch.float32, device=dev)
+    ctx = binding.default_context(0)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        binding.filter_rect(img, sc, order, model, path, "clamp", a_max=16.0, out=out, ctx=ctx, stream=stream)
+
+    wall, ms = time_steps(step, args.steps, args.warmup, stream)
+    ctx.check_device()
+    P = H * W
+    T, halo = 32, 2 * math.ceil(17 * order / 2 + (model + order + 1) / 2) + 2
+    box = math.ceil(W / T) * math.ceil(H / T) * (T + halo) ** 2
+    flops = P * rect_flops_per_pixel(order, model) + box * 2.0 * order
+    roof = {"bound": "alu", "achieved": flops / (ms * 1e-3) / 1e12, "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s",
+            "frac": flops / (ms * 1e-3) / PEAK_FP64_VALU, "traffic": None}
+    alg_bytes = P * (1 + 8 + (8 if path == "f64" else 4))
+    extra = {"filter_ms": ms, "hbm_algorithmic_GBps": alg_bytes / (ms * 1e-3) / 1e9,
+             "flops_per_pixel": rect_flops_per_pixel(order, model)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        s = out.cpu().numpy().reshape(-1).astype(np.float64)
+        pr = np.random.default_rng(12348)
+        probe = pr.choice(P, size=64, replace=False)
+        t0 = time.perf_counter()
+        OR.filter_rect(img_np, sc_np, order, model, "clamp", probe)
+        tp = max(time.perf_counter() - t0, 1e-3)
+        k = int(min(P, max(64, 64 * args.cpu_seconds / tp)))
+        pix = np.sort(pr.choice(P, size=k, replace=False))
+        t0 = time.perf_counter()
+        ref = OR.filter_rect(img_np, sc_np, order, model, "clamp", pix)
+        tc = time.perf_counter() - t0
+        extra["err_vs_oracle"] = errors(s[pix], ref)
+        cpu = {"value": k / tc / 1e6, "unit": "Mpixel/s", "cores": 1, "kind": "oracle",
+               "sample": f"{k} random pixels of the same {W}x{H} image (separable direct sum, numpy, one thread), "
+                         f"{tc:.1f} s"}
+    config = {"workload": f"rect: {W}x{H} uint8 blurred-noise image, two smooth real scale fields in [1,16], "
+                          f"two-direction box spline, order {order}, impulse model, {path} path",
+              "pixels": P, "order": order, "model": model, "path": path}
+    return record(P * args.steps / wall / 1e6, wall, args.steps, args.warmup,
+                  "f64" if path == "f64" else "f64-compute/f32-out", config, roof, cpu, extra)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -541,7 +648,11 @@ def main():
     ap.add_argument("--path", default="f64", choices=["f64", "f32tiled"])
     ap.add_argument("--size", type=int, default=2048)
     ap.add_argument("--workload", default="plain",
-                    choices=["plain", "small", "precision", "batched", "serving", "stage1", "ellipse", "signal1d"])
+                    choices=["plain", "small", "precision", "batched", "serving", "stage1", "ellipse", "signal1d",
+                             "rect"])
+    ap.add_argument("--no-f32-leg", action="store_true", help="plain workload: skip the float32-output leg")
+    ap.add_argument("--kappa-seconds", type=float, default=6.0, help="CPU time for the kappa percentiles")
+    ap.add_argument("--serving-compare", action="store_true", help="serving: also run the stream with eager launches")
     ap.add_argument("--signals", type=int, default=1024)
     ap.add_argument("--length", type=int, default=65536)
     ap.add_argument("--batch-count", type=int, default=64)
@@ -559,7 +670,7 @@ def main():
         sys.exit(2)
     fn = {"plain": workload_plain, "small": workload_small, "precision": workload_precision,
           "batched": workload_batched, "serving": workload_serving, "stage1": workload_stage1,
-          "ellipse": workload_ellipse, "signal1d": workload_signal1d}[args.workload]
+          "ellipse": workload_ellipse, "signal1d": workload_signal1d, "rect": workload_rect}[args.workload]
     print(json.dumps(fn(args)), flush=True)
 
 
