@@ -20,7 +20,8 @@
 // weighted sum is formed and weighted along y.
 //
 // Restart windows.  A workgroup owns a T x T tile and runs step 1 on a window that holds
-// every sample the tile's masks reach, the running sums anchored at the window centre: that
+// every sample the tile's masks reach, the running sums anchored at the window centre (each
+// line's two halves, after and before the anchor, on two threads): that
 // changes g by a polynomial of degree < n along each direction, which the degree-D
 // interpolation reproduces and the n-th difference annihilates (same result in exact
 // arithmetic, magnitudes bounded by the window instead of the image).  Both stages carry a
@@ -73,25 +74,28 @@ __host__ inline long long lds_bytes(int T, int n, int D, double a_max) {
 using f1d::cpair;
 using f1d::cp_sum;
 
-__device__ __forceinline__ cpair cp_neg(cpair a) { return {-a.s, -a.c}; }
-
-// One line of the window, `len` entries `stride` apart, n anchored running sums: forward
-// from the anchor (y[t] = y[t-1] + x[t], y[anchor] = 0) and backward from it.
+// One half of a line of the window (entries `stride` apart), n anchored running sums
+// y[t] = y[t-1] + x[t] with y[anchor] = 0: the half after the anchor runs forward from it
+// (back = false, positions anchor+1 .. len-1), the rest backward, y[t-1] = y[t] - x[t]
+// (back = true, positions anchor .. 0).  Each fold of a half reads only that half of the
+// previous fold, so the two halves are independent and run on different threads.
 template <int N>
-__device__ __forceinline__ void anchored_sums(double2* line, int len, int stride, int anchor) {
+__device__ __forceinline__ void anchored_half(double2* line, int len, int stride, int anchor, bool back) {
 #pragma unroll 1
     for (int fold = 0; fold < N; ++fold) {
         cpair acc = {0.0, 0.0};
-        for (int t = anchor + 1; t < len; ++t) {
-            const double2 x = line[t * stride];
-            acc = cp_sum(acc, {x.x, x.y});
-            line[t * stride] = make_double2(acc.s, acc.c);
-        }
-        acc = {0.0, 0.0};
-        for (int t = anchor; t >= 0; --t) {
-            const double2 x = line[t * stride];
-            line[t * stride] = make_double2(acc.s, acc.c);
-            acc = cp_sum(acc, {-x.x, -x.y});
+        if (!back) {
+            for (int t = anchor + 1; t < len; ++t) {
+                const double2 x = line[t * stride];
+                acc = cp_sum(acc, {x.x, x.y});
+                line[t * stride] = make_double2(acc.s, acc.c);
+            }
+        } else {
+            for (int t = anchor; t >= 0; --t) {
+                const double2 x = line[t * stride];
+                line[t * stride] = make_double2(acc.s, acc.c);
+                acc = cp_sum(acc, {-x.x, -x.y});
+            }
         }
     }
 }
@@ -168,9 +172,9 @@ __global__ __launch_bounds__(kThreads) void rect_kernel(Args A) {
 
     // ---- step 1: n anchored running sums along rows, then along columns ----------------------
     const int ctr = wx / 2 - 1;
-    for (int r = tid; r < wx; r += kThreads) anchored_sums<N>(S + r * P, wx, 1, ctr);
+    for (int h = tid; h < 2 * wx; h += kThreads) anchored_half<N>(S + (h >> 1) * P, wx, 1, ctr, h & 1);
     __syncthreads();
-    for (int c = tid; c < wx; c += kThreads) anchored_sums<N>(S + c, wx, P, ctr);
+    for (int h = tid; h < 2 * wx; h += kThreads) anchored_half<N>(S + (h >> 1), wx, P, ctr, h & 1);
     __syncthreads();
 
     // ---- step 2: the separable mask at each output's own scales ------------------------------
