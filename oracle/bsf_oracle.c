@@ -288,3 +288,180 @@ int bsf_oracle_preintegrate(const int64_t* win, int Hq, int Wq, int n, int64_t* 
     free(F);
     return rc;
 }
+
+/*
+ * Continuous models (Section 6): the image is f(x) = sum_k c[k] phi(x - k) with
+ * phi = beta^{n1} (x) beta^{n1} (centred unit-scale B-splines of degree n1 along x and y;
+ * n1 = -1 is phi = delta, Section 7's choice), and the projection onto the box spline is
+ *
+ *     s[m] = sum_k c[k] (phi * B_a)(m - k).                                       (2)
+ *
+ * phi is separable and B_a depends on x1 and x2 only through its two axis factors, so
+ *
+ *   (phi * B_a)(x) = int int b2(s) b4(t) K1(x1 - (s - t)/sqrt2) K3(x2 - (s + t)/sqrt2) ds dt,
+ *
+ * with K_d = beta^{n1} * b_d the one-dimensional model kernel of Section 3 at the scale
+ * a_d.  K_d is evaluated as the integral of beta^{n1}(u) b_d(y - u) over u, piece by piece
+ * between the knots of both factors (Gauss-Legendre exact for the product's degree; the
+ * integrand is non-negative), and the outer integral as before, on the cells cut out by
+ * the knots of b2, b4 and of K1, K3.
+ */
+#define MAX_KN 64
+
+/* K(y) = (beta^{n1} * beta^{n-1}_a)(y); n1 = -1: beta^{n-1}_a(y) */
+static double model_kernel(int n, int n1, double a, double y) {
+    if (n1 < 0) return scaled_bspline(n - 1, a, y);
+    double kn[MAX_KN];
+    int nk = 0;
+    for (int i = 0; i <= n1 + 1; ++i) kn[nk++] = -0.5 * (n1 + 1) + i;   /* beta^{n1}(u)   */
+    for (int j = 0; j <= n; ++j) kn[nk++] = y - a * (j - 0.5 * n);        /* b(y - u)       */
+    for (int i = 1; i < nk; ++i)                                           /* sort           */
+        for (int k = i; k > 0 && kn[k - 1] > kn[k]; --k) {
+            const double t = kn[k];
+            kn[k] = kn[k - 1];
+            kn[k - 1] = t;
+        }
+    const double lo = fmax(-0.5 * (n1 + 1), y - 0.5 * a * n), hi = fmin(0.5 * (n1 + 1), y + 0.5 * a * n);
+    if (!(lo < hi)) return 0.0;
+    const int deg = n1 + n - 1, mg = deg / 2 + 1;
+    double total = 0.0;
+    for (int i = 0; i + 1 < nk; ++i) {
+        const double u0 = fmax(kn[i], lo), u1 = fmin(kn[i + 1], hi);
+        if (!(u0 < u1)) continue;
+        double acc = 0.0;
+        for (int g = 0; g < mg; ++g) {
+            const double u = u0 + (u1 - u0) * gl_x[mg][g];
+            acc += gl_w[mg][g] * cardinal_bspline(n1, u) * scaled_bspline(n - 1, a, y - u);
+        }
+        total += acc * (u1 - u0);
+    }
+    return total;
+}
+
+/* knots of K (in y), sorted and de-duplicated */
+static int model_knots(int n, int n1, double a, double* kn) {
+    int nk = 0;
+    const int ni = n1 < 0 ? 0 : n1 + 1;
+    for (int i = 0; i <= ni; ++i)
+        for (int j = 0; j <= n; ++j) kn[nk++] = (n1 < 0 ? 0.0 : -0.5 * (n1 + 1) + i) + a * (j - 0.5 * n);
+    for (int i = 1; i < nk; ++i)
+        for (int k = i; k > 0 && kn[k - 1] > kn[k]; --k) {
+            const double t = kn[k];
+            kn[k] = kn[k - 1];
+            kn[k - 1] = t;
+        }
+    int m = 0;
+    for (int i = 0; i < nk; ++i)
+        if (m == 0 || kn[i] > kn[m - 1]) kn[m++] = kn[i];
+    return m;
+}
+
+double bsf_oracle_box_spline_model(double x1, double x2, const double* a, int n, int n1) {
+    gl_init();
+    if (n < 1 || n1 < -1 || n1 > 3 || (n1 + 1) * (n + 1) + n + 1 > MAX_KN) return NAN;
+    const double a1 = a[0], a2 = a[1], a3 = a[2], a4 = a[3];
+    const int m = n - 1;
+    const double h = 0.5 * n, e = n1 < 0 ? 0.0 : 0.5 * (n1 + 1);
+    if (fabs(x1) >= h * (a1 + (a2 + a4) * M_SQRT1_2) + e || fabs(x2) >= h * (a3 + (a2 + a4) * M_SQRT1_2) + e)
+        return 0.0;
+    double ks[8], kt[8], k1[MAX_KN], k3[MAX_KN];
+    for (int i = 0; i <= n; ++i) {
+        ks[i] = a2 * (i - h);
+        kt[i] = a4 * (i - h);
+    }
+    const int n1k = model_knots(n, n1, a1, k1), n3k = model_knots(n, n1, a3, k3);
+    /* K1 knot kappa: the line s - t = sqrt2 (x1 - kappa); descending in kappa = ascending in s - t */
+    const int dK = n1 < 0 ? m : n1 + n;
+    const int p = 2 * m + 2 * dK;
+    const int mu = (p + 3) / 2, mw = (p + 2) / 2;
+    if (mu > MAX_GL || mw > MAX_GL) return NAN;
+    double total = 0.0;
+    pt2 A[24], B[24];
+    for (int i = 0; i < n; ++i)
+        for (int k = 0; k < n; ++k)
+            for (int ii = 0; ii + 1 < n1k; ++ii) {
+                /* x1 - (s-t)/sqrt2 in [k1[ii], k1[ii+1]]  <=>  s - t in [sqrt2 (x1 - k1[ii+1]), sqrt2 (x1 - k1[ii])] */
+                const double lo1 = M_SQRT2 * (x1 - k1[ii + 1]), hi1 = M_SQRT2 * (x1 - k1[ii]);
+                for (int kk = 0; kk + 1 < n3k; ++kk) {
+                    const double lo3 = M_SQRT2 * (x2 - k3[kk + 1]), hi3 = M_SQRT2 * (x2 - k3[kk]);
+                    int np = 4;
+                    A[0].s = ks[i];     A[0].t = kt[k];
+                    A[1].s = ks[i + 1]; A[1].t = kt[k];
+                    A[2].s = ks[i + 1]; A[2].t = kt[k + 1];
+                    A[3].s = ks[i];     A[3].t = kt[k + 1];
+                    np = clip_poly(A, np, 1.0, -1.0, hi1, B);
+                    if (np < 3) continue;
+                    np = clip_poly(B, np, -1.0, 1.0, -lo1, A);
+                    if (np < 3) continue;
+                    np = clip_poly(A, np, 1.0, 1.0, hi3, B);
+                    if (np < 3) continue;
+                    np = clip_poly(B, np, -1.0, -1.0, -lo3, A);
+                    if (np < 3) continue;
+                    for (int q = 1; q + 1 < np; ++q) {
+                        const pt2 v0 = A[0], v1 = A[q], v2 = A[q + 1];
+                        const double e1s = v1.s - v0.s, e1t = v1.t - v0.t;
+                        const double e2s = v2.s - v0.s, e2t = v2.t - v0.t;
+                        const double area2 = fabs(e1s * e2t - e1t * e2s);
+                        if (area2 == 0.0) continue;
+                        double acc = 0.0;
+                        for (int iu = 0; iu < mu; ++iu) {
+                            const double u = gl_x[mu][iu], wu = gl_w[mu][iu];
+                            for (int iw = 0; iw < mw; ++iw) {
+                                const double w = gl_x[mw][iw], ww = gl_w[mw][iw];
+                                const double xi = u, eta = w * (1.0 - u);
+                                const double s = v0.s + xi * e1s + eta * e2s;
+                                const double t = v0.t + xi * e1t + eta * e2t;
+                                const double val = scaled_bspline(m, a2, s) * scaled_bspline(m, a4, t) *
+                                                   model_kernel(n, n1, a1, x1 - (s - t) * M_SQRT1_2) *
+                                                   model_kernel(n, n1, a3, x2 - (s + t) * M_SQRT1_2);
+                                acc += val * wu * ww * (1.0 - u);
+                            }
+                        }
+                        total += acc * area2;
+                    }
+                }
+            }
+    return total;
+}
+
+/*
+ * (2) for a coefficient array that already holds c[k] for every k the sums reach:
+ * c[(k2 + org) * pitch + (k1 + org)] for k in [-org, H + org) x [-org, W + org).
+ * Output as bsf_oracle_filter.  Returns 0, or -1 on bad arguments (including an org too
+ * small for a pixel's support).
+ */
+int bsf_oracle_filter_model(const double* c, int H, int W, ptrdiff_t pitch, int org, const float* scales, int n,
+                            int n1, const int64_t* pix, int64_t npix, double* out) {
+    if (!c || !scales || !out || H < 1 || W < 1 || n < 1 || n > 6 || n1 < -1 || n1 > 3 || org < 0 ||
+        pitch < W + 2 * org)
+        return -1;
+    gl_init();
+    const int64_t total = pix ? npix : (int64_t)H * W;
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(| : bad)
+    for (int64_t i = 0; i < total; ++i) {
+        const int64_t id = pix ? pix[i] : i;
+        const int m2 = (int)(id / W), m1 = (int)(id % W);
+        const float* sc = scales + 4 * id;
+        double a[4] = {sc[0], sc[1], sc[2], sc[3]};
+        const double h = 0.5 * n, e = n1 < 0 ? 0.0 : 0.5 * (n1 + 1);
+        const double R1 = h * (a[0] + (a[1] + a[3]) * M_SQRT1_2) + e;
+        const double R2 = h * (a[2] + (a[1] + a[3]) * M_SQRT1_2) + e;
+        const int k1lo = (int)floor(m1 - R1), k1hi = (int)ceil(m1 + R1);
+        const int k2lo = (int)floor(m2 - R2), k2hi = (int)ceil(m2 + R2);
+        if (k1lo < -org || k2lo < -org || k1hi >= W + org || k2hi >= H + org) {
+            bad = 1;
+            out[i] = NAN;
+            continue;
+        }
+        double acc = 0.0;
+        for (int k2 = k2lo; k2 <= k2hi; ++k2)
+            for (int k1 = k1lo; k1 <= k1hi; ++k1) {
+                const double v = c[(ptrdiff_t)(k2 + org) * pitch + (k1 + org)];
+                if (v == 0.0) continue;
+                acc += v * bsf_oracle_box_spline_model((double)(m1 - k1), (double)(m2 - k2), a, n, n1);
+            }
+        out[i] = acc;
+    }
+    return bad ? -1 : 0;
+}
