@@ -138,6 +138,19 @@ bsf_status bsf_batch_plan_run(bsf_batch_plan* plan, const bsf_job* jobs, int njo
 bsf_status bsf_batch_plan_job_status(bsf_batch_plan* plan, int* status, int njobs);
 bsf_status bsf_batch_plan_destroy(bsf_batch_plan* plan);
 
+/* Continuous image models (Section 6): the image is f(x) = sum_k c[k] phi(x - k) with
+ * phi = beta^model x beta^model, the centred unit-scale B-spline of degree `model` along x and
+ * y, and every pixel gets the projection of f onto the four-direction box spline at its own
+ * scales:  out[m] = sum_k c_ext[k] (phi * B_a(m))(m - k).  model = -1 is phi = delta, Section
+ * 7's choice and exactly bsf_filter; model = 0 (piecewise-constant) and 1 (bilinear) need no
+ * prefilter (b^model is the unit impulse, c = the samples).  The two steps of Section 6 are
+ * unchanged except the interpolant of eq. mask, phi * beta_b: the box spline of
+ * {l1^(model+2), l2, l3^(model+2), l4}, tabulated exactly like beta_b; the restart windows
+ * also hold phi's extra (model+1)/2 of support.  Models 0 and 1 are provided at order 1 (the
+ * paper's 16-tap mesh, Table 1); other (order, model) pairs return BSF_ERR_UNSUPPORTED.  Same
+ * paths, borders, workspace and errors as bsf_filter. */
+bsf_status bsf_filter_model(bsf_ctx* ctx, const bsf_job* job, int model, void* stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc): the same result as bsf_filter, bitwise,
  * with the call's work area (tile lists, counters, tier-3 window slices) in a fixed 32 MiB

@@ -80,6 +80,7 @@ def load():
             lib.bsf_filter.argtypes = [vp, jp, vp]
             lib.bsf_filter_batched.argtypes = [vp, jp, i, vp]
             lib.bsf_filter_noalloc.argtypes = [vp, jp, vp]
+            lib.bsf_filter_model.argtypes = [vp, jp, i, vp]
             lib.bsf_batch_plan_create.argtypes = [vp, i, ctypes.c_longlong, ctypes.c_float, ctypes.POINTER(vp)]
             lib.bsf_batch_plan_run.argtypes = [vp, jp, i, vp]
             lib.bsf_batch_plan_job_status.argtypes = [vp, ctypes.POINTER(i), i]
@@ -98,7 +99,7 @@ def load():
             lib.bsf_last_error.restype = ctypes.c_char_p
             lib.bsf_debug_tile_window.argtypes = [vp, jp, i, vp, ctypes.c_longlong, vp, vp]
             for fn in ("bsf_create", "bsf_destroy", "bsf_workspace_size", "bsf_filter", "bsf_filter_batched",
-                       "bsf_filter_noalloc", "bsf_batch_plan_create", "bsf_batch_plan_run", "bsf_batch_plan_job_status",
+                       "bsf_filter_noalloc", "bsf_filter_model", "bsf_batch_plan_create", "bsf_batch_plan_run", "bsf_batch_plan_job_status",
                        "bsf_batch_plan_destroy", "bsf_filter_rect", "bsf_filter_rect_max_scale",
                        "bsf_preintegrate", "bsf_get_device_error", "bsf_get_counters", "bsf_scales_from_ellipses",
                        "bsf_debug_tile_window", "bsf_filter1d", "bsf_filter1d_max_scale"):
@@ -227,12 +228,16 @@ def _on(stream):
 
 
 def filter(img, scales, order: int, path: str = "f64", border: str = "clamp", a_max: float | None = None,
-           out=None, ctx: Context | None = None, stream=None, check: bool = False):
-    """Adaptive box-spline filter of ``img`` with per-pixel scale vectors ``scales``."""
+           out=None, ctx: Context | None = None, stream=None, check: bool = False, model: int = -1):
+    """Adaptive box-spline filter of ``img`` with per-pixel scale vectors ``scales``.
+    ``model`` >= 0 selects the continuous image model of that degree (bsf_filter_model)."""
     ctx = ctx or default_context(img.device.index)
     with _on(stream):
         j, out = make_job(img, scales, order, path, border, a_max, out)
-    ctx._check(ctx.lib.bsf_filter(ctx.handle, ctypes.byref(j), _stream_ptr(stream)))
+    if model == -1:
+        ctx._check(ctx.lib.bsf_filter(ctx.handle, ctypes.byref(j), _stream_ptr(stream)))
+    else:
+        ctx._check(ctx.lib.bsf_filter_model(ctx.handle, ctypes.byref(j), int(model), _stream_ptr(stream)))
     if check:
         ctx.check_device(stream)
     return out

@@ -297,7 +297,7 @@ __device__ __forceinline__ TapFrame<N> tap_frame(int qx, int qy, Turn t, int wq,
     // odd n rotates about the anchor, even n about the anchor + (1/2, 1/2); stencil
     // point (jx, jy) of the reference triangle sits at (jx, jy), (e - jy, jx),
     // (e - jx, e - jy) or (jy, e - jx) for tri = 0..3
-    constexpr int e = (N & 1) ? 0 : 1;
+    constexpr int e = Tab<N>::ODD ? 0 : 1;
     const int S1 = t.swap ? wq : 1, S2 = t.swap ? 1 : wq;
     TapFrame<N> f;
     f.s1 = t.n1 ? -S1 : S1;
@@ -648,7 +648,7 @@ __device__ __forceinline__ void horner_chunk_split(
 // Split evaluation: terms of total degree up to split_low<N>() compensated, the rest
 // plain.  Order 1 (degree 2) is evaluated compensated throughout.
 template <int N>
-__host__ __device__ constexpr int split_low() { return N == 1 ? Tab<N>::DEG : (N == 2 ? 2 : 3); }
+__host__ __device__ constexpr int split_low() { return (N == 1 || N >= 10) ? Tab<N>::DEG : (N == 2 ? 2 : 3); }
 // a1 a2 a3 a4 from which a pixel's taps are evaluated split (see process_tile): a
 // geometric-mean scale of 5 (order 2) or 4.5 (order 3)
 template <int N>
@@ -713,7 +713,7 @@ __device__ __forceinline__ cp interp_dd(const long long* S, const TapFrame<N>& f
     using T = Tab<N>;
     cp P = {0.0, 0.0};
     double PH = 0.0;
-    if constexpr (N < 3 || SRC == SRC_DBL) {
+    if constexpr (N != 3 || SRC == SRC_DBL) {
         interp_chunk_dd<N, SRC, 0, T::DEG, true, LOW>(S, fr, v1, v2, P, PH, B, bad);
     } else {  // three parts: two u1-chunks (84 and 114 accumulators)
         interp_chunk_dd<N, SRC, 4, 10, true, LOW>(S, fr, v1, v2, P, PH, B, bad);
@@ -729,7 +729,7 @@ __device__ __forceinline__ double interp_f64(const long long* S, const TapFrame<
                                              unsigned& bad) {
     using T = Tab<N>;
     double P = 0.0;
-    if constexpr (N < 3 || SRC == SRC_DBL) {
+    if constexpr (N != 3 || SRC == SRC_DBL) {
         interp_chunk_f64<N, SRC, 0, T::DEG, true>(S, fr, v1, v2, P, bad);
     } else {
         interp_chunk_f64<N, SRC, 4, 10, true>(S, fr, v1, v2, P, bad);
@@ -762,7 +762,7 @@ __device__ __forceinline__ dd dd_turn(bool swap, bool neg, dd a, dd b) {  // +-(
 //
 // With LOW below the polynomial degree the taps use the split evaluation and E receives
 // sum_k |c_k| B_k, which times 2^-47 bounds the error of the plain parts.
-template <int N, int SRC, int LOW = Tab<N>::DEG>
+template <int N, int SRC, int LOW = Tab<N>::DEG, int K = N>
 __device__ dd mesh_dd(const long long* S, int wq, int hq, int mx, int my, float4 a, int k2lo, int k2hi,
                       unsigned& bad, double& E) {
     const dd isq = {kInvSqrt2Hi, kInvSqrt2Lo};
@@ -787,7 +787,7 @@ __device__ dd mesh_dd(const long long* S, int wq, int hq, int mx, int my, float4
                     const dd d2 = dd_add_d(B2, -(double)k3 * a3);
                     // anchor and local offset
                     double f1, f2;
-                    if (N & 1) {
+                    if (Tab<K>::ODD) {
                         f1 = rint(d1.hi);
                         f2 = rint(d2.hi);
                     } else {
@@ -796,23 +796,23 @@ __device__ dd mesh_dd(const long long* S, int wq, int hq, int mx, int my, float4
                     }
                     // u = d - (q + o) in double-double: d.hi - q alone is not exact when
                     // the anchor is floor(d) and d lies in (-1, 0)
-                    const double oc = (N & 1) ? 0.0 : 0.5;
+                    const double oc = Tab<K>::ODD ? 0.0 : 0.5;
                     const dd u1 = dd_add_d(d1, -(f1 + oc));
                     const dd u2 = dd_add_d(d2, -(f2 + oc));
                     const Turn t = cell_turn(u1.hi, u2.hi);
                     const dd v1 = dd_turn(t.swap, t.n1, u1, u2);
                     const dd v2 = dd_turn(t.swap, t.n2, u2, u1);
-                    const TapFrame<N> fr = tap_frame<N>(mx + (int)f1, my + (int)f2, t, wq, hq);
+                    const TapFrame<K> fr = tap_frame<K>(mx + (int)f1, my + (int)f2, t, wq, hq);
                     if (!fr.lo_ok) {
                         bad = 1;
                         continue;
                     }
                     double Bk = 0.0;
-                    const cp P = interp_dd<N, SRC, LOW>(S, fr, v1, v2, Bk, bad);
+                    const cp P = interp_dd<K, SRC, LOW>(S, fr, v1, v2, Bk, bad);
                     const int c = c124 * fd_binom<N>(k3);
                     const double cs = ((k1 + k2 + k3 + k4) & 1) ? -(double)c : (double)c;
                     acc = cp_axpy(acc, cs, P);
-                    if constexpr (LOW < Tab<N>::DEG) E = __fma_rn((double)c, Bk, E);
+                    if constexpr (LOW < Tab<K>::DEG) E = __fma_rn((double)c, Bk, E);
                 }
             }
         }
@@ -822,17 +822,17 @@ __device__ dd mesh_dd(const long long* S, int wq, int hq, int mx, int my, float4
 
 // s = acc * 2^n / DEN / (a1 a2 a3 a4)^n  (the sqrt2 weights of the two diagonal running
 // sums, the table denominator and the finite-difference weights d^n_a of eq. FD)
-template <int N>
+template <int N, int K = N>
 __device__ double finalize_dd(dd acc, float4 a) {
     const dd prod = two_prod((double)a.x * (double)a.y, (double)a.z * (double)a.w);  // exact
     dd pn = prod;
     for (int i = 1; i < N; ++i) pn = dd_mul(pn, prod);
-    const dd den = {Tab<N>::DEN / (double)(1 << N), 0.0};
+    const dd den = {Tab<K>::DEN / (double)(1 << N), 0.0};
     const dd r = dd_div(dd_div(acc, den), pn);
     return r.hi + r.lo;
 }
 
-template <int N, int SRC>
+template <int N, int SRC, int K = N>
 __device__ double mesh_f64(const long long* S, int wq, int hq, int mx, int my, float4 a, int k2lo, int k2hi,
                            unsigned& bad) {  // raw sum over k2 in [k2lo, k2hi]
     const double a1 = a.x, a3 = a.z;
@@ -851,19 +851,19 @@ __device__ double mesh_f64(const long long* S, int wq, int hq, int mx, int my, f
                 const double d1 = B1 - k1 * a1;
                 for (int k3 = 0; k3 <= N; ++k3) {
                     const double d2 = B2 - k3 * a3;
-                    const double f1 = (N & 1) ? rint(d1) : floor(d1);
-                    const double f2 = (N & 1) ? rint(d2) : floor(d2);
-                    const double oc = (N & 1) ? 0.0 : 0.5;
+                    const double f1 = Tab<K>::ODD ? rint(d1) : floor(d1);
+                    const double f2 = Tab<K>::ODD ? rint(d2) : floor(d2);
+                    const double oc = Tab<K>::ODD ? 0.0 : 0.5;
                     const double u1 = d1 - f1 - oc, u2 = d2 - f2 - oc;
                     const Turn t = cell_turn(u1, u2);
                     const double w1 = t.swap ? u2 : u1, w2 = t.swap ? u1 : u2;
                     const double v1 = t.n1 ? -w1 : w1, v2 = t.n2 ? -w2 : w2;
-                    const TapFrame<N> fr = tap_frame<N>(mx + (int)f1, my + (int)f2, t, wq, hq);
+                    const TapFrame<K> fr = tap_frame<K>(mx + (int)f1, my + (int)f2, t, wq, hq);
                     if (!fr.lo_ok) {
                         bad = 1;
                         continue;
                     }
-                    const double P = interp_f64<N, SRC>(S, fr, v1, v2, bad);
+                    const double P = interp_f64<K, SRC>(S, fr, v1, v2, bad);
                     const int c = c124 * fd_binom<N>(k3);
                     acc = __fma_rn(((k1 + k2 + k3 + k4) & 1) ? -(double)c : (double)c, P, acc);
                 }
@@ -873,12 +873,12 @@ __device__ double mesh_f64(const long long* S, int wq, int hq, int mx, int my, f
     return acc;
 }
 
-template <int N>
+template <int N, int K = N>
 __device__ double finalize_f64(double acc, float4 a) {
     const double prod = ((double)a.x * (double)a.y) * ((double)a.z * (double)a.w);
     double pn = prod;
     for (int i = 1; i < N; ++i) pn *= prod;
-    return acc * ((double)(1 << N) / Tab<N>::DEN) / pn;
+    return acc * ((double)(1 << N) / Tab<K>::DEN) / pn;
 }
 
 // ---------------------------------------------------------------------------
@@ -1007,7 +1007,7 @@ __device__ __forceinline__ void combine_halves(dd& acc, unsigned& bad) {
 }
 
 // Filter one 16x16 tile of job A (index `job`) with the window in S.
-template <int N, int PATH>
+template <int N, int PATH, int TK = N>
 __device__ __forceinline__ void process_tile(const JobDesc A, int job, int tile, const Launch L, long long* S,
                                              Shared& sh_) {
     auto& red = sh_.red;
@@ -1053,7 +1053,7 @@ __device__ __forceinline__ void process_tile(const JobDesc A, int job, int tile,
     }
 
     // 2. the restart window
-    const Window w = tile_window<N>(t1, t2, tw, th, R1, R2);
+    const Window w = tile_window<N, TK>(t1, t2, tw, th, R1, R2);
     const long long need = window_elems(w);
     const double nan = __builtin_nan("");
     auto store = [&](double v) {
@@ -1117,14 +1117,14 @@ __device__ __forceinline__ void process_tile(const JobDesc A, int job, int tile,
         }
         unsigned bad = 0;
         dd m = {0.0, 0.0};
-        if (inside && valid) m.hi = mesh_f64<N, SRC_DBL>(S, g.wq, g.hq, mx, my, a, k2lo, k2hi, bad);
+        if (inside && valid) m.hi = mesh_f64<N, SRC_DBL, TK>(S, g.wq, g.hq, mx, my, a, k2lo, k2hi, bad);
         combine_halves<SPLIT>(m, bad);
         if (!inside || half) return;
         if (!valid) {
             store(nan);
             return;
         }
-        double s = finalize_f64<N>(m.hi, a);
+        double s = finalize_f64<N, TK>(m.hi, a);
         if (bad) {
             atomicOr(A.err, kErrWindow);
             s = nan;
@@ -1222,7 +1222,7 @@ __device__ __forceinline__ void process_tile(const JobDesc A, int job, int tile,
                 const long long v = S[i];
                 mag |= (unsigned long long)(v < 0 ? -v : v);
             }
-            constexpr int kExact = exact_bits<N>();  // folded at compile time
+            constexpr int kExact = exact_bits<TK>();  // folded at compile time
             const bool fast = !__syncthreads_or((mag >> kExact) != 0ull);
             if (fast) {
                 for (int i = tid; i < g.qn; i += NT) reinterpret_cast<double*>(S)[i] = (double)S[i];
@@ -1234,32 +1234,32 @@ __device__ __forceinline__ void process_tile(const JobDesc A, int job, int tile,
             // roughly as that scale's 6th (order 2) or 7th (order 3) power and holds there
             // as a rule; below, a wave would mostly pay for both evaluations.
             const bool wave_split =
-                __all(!(inside && valid) || (double)a.x * a.y * a.z * a.w >= split_min_volume<N>()) != 0;
+                __all(!(inside && valid) || (double)a.x * a.y * a.z * a.w >= split_min_volume<TK>()) != 0;
             if (inside && valid) {
                 const double wk = ldexp(1.0, k * B);
                 if (PATH == BSF_PATH_F64) {
                     dd m;
                     double E = 0.0;
                     bool done_m = false;
-                    if constexpr (split_low<N>() < Tab<N>::DEG) {
+                    if constexpr (split_low<TK>() < Tab<TK>::DEG) {
                         if (K == 1 && wave_split) {
                             tried = true;
                             // split evaluation; a pixel whose bound on the plain parts' error,
                             // 2^-47 E, exceeds 2^-44 |s| is evaluated again, compensated
-                            constexpr int LOW = split_low<N>();
-                            m = fast ? mesh_dd<N, SRC_DBL, LOW>(S, g.wq, g.hq, mx, my, a, k2lo, k2hi, bad, E)
-                                     : mesh_dd<N, SRC_INT, LOW>(S, g.wq, g.hq, mx, my, a, k2lo, k2hi, bad, E);
+                            constexpr int LOW = split_low<TK>();
+                            m = fast ? mesh_dd<N, SRC_DBL, LOW, TK>(S, g.wq, g.hq, mx, my, a, k2lo, k2hi, bad, E)
+                                     : mesh_dd<N, SRC_INT, LOW, TK>(S, g.wq, g.hq, mx, my, a, k2lo, k2hi, bad, E);
                             done_m = E <= 8.0 * fabs(m.hi);
                             redo = !done_m;
                         }
                     }
                     if (!done_m)
-                        m = fast ? mesh_dd<N, SRC_DBL>(S, g.wq, g.hq, mx, my, a, k2lo, k2hi, bad, E)
-                                 : mesh_dd<N, SRC_INT>(S, g.wq, g.hq, mx, my, a, k2lo, k2hi, bad, E);
+                        m = fast ? mesh_dd<N, SRC_DBL, Tab<TK>::DEG, TK>(S, g.wq, g.hq, mx, my, a, k2lo, k2hi, bad, E)
+                                 : mesh_dd<N, SRC_INT, Tab<TK>::DEG, TK>(S, g.wq, g.hq, mx, my, a, k2lo, k2hi, bad, E);
                     acc_dd = dd_add(acc_dd, dd_mul_d(m, wk));
                 } else {
-                    const double m = fast ? mesh_f64<N, SRC_DBL>(S, g.wq, g.hq, mx, my, a, k2lo, k2hi, bad)
-                                          : mesh_f64<N, SRC_INT>(S, g.wq, g.hq, mx, my, a, k2lo, k2hi, bad);
+                    const double m = fast ? mesh_f64<N, SRC_DBL, TK>(S, g.wq, g.hq, mx, my, a, k2lo, k2hi, bad)
+                                          : mesh_f64<N, SRC_INT, TK>(S, g.wq, g.hq, mx, my, a, k2lo, k2hi, bad);
                     acc_f = __fma_rn(m, wk, acc_f);
                 }
             }
@@ -1290,7 +1290,7 @@ __device__ __forceinline__ void process_tile(const JobDesc A, int job, int tile,
         store(nan);
         return;
     }
-    double s = (PATH == BSF_PATH_F64) ? finalize_dd<N>(acc_dd, a) : finalize_f64<N>(acc_f, a);
+    double s = (PATH == BSF_PATH_F64) ? finalize_dd<N, TK>(acc_dd, a) : finalize_f64<N, TK>(acc_f, a);
     s = ldexp(s, -sh);
     if (bad) {
         atomicOr(A.err, kErrWindow);
@@ -1303,20 +1303,20 @@ __device__ __forceinline__ void process_tile(const JobDesc A, int job, int tile,
 extern __shared__ long long g_lds[];
 
 // Tier 1 of a single job: one workgroup per tile.
-template <int N, int PATH>
+template <int N, int PATH, int TK = N>
 __global__ __launch_bounds__((threads_of<N, PATH>())) __attribute__((amdgpu_waves_per_eu(N < 3 ? 2 : 1))) void tile_kernel(
     JobDesc A, Launch L) {
     extern __shared__ long long S[];
     __shared__ Shared sh;
-    process_tile<N, PATH>(A, 0, xcd_tile(blockIdx.x, gridDim.x), L, S, sh);
+    process_tile<N, PATH, TK>(A, 0, xcd_tile(blockIdx.x, gridDim.x), L, S, sh);
 }
 
 // Test aid: stage 1 of one tile.
-template <int N, int PATH>
+template <int N, int PATH, int TK = N>
 __global__ __launch_bounds__((threads_of<N, PATH>())) void debug_tile_kernel(JobDesc A, Launch L, int tile) {
     extern __shared__ long long S[];
     __shared__ Shared sh;
-    process_tile<N, PATH>(A, 0, tile, L, S, sh);
+    process_tile<N, PATH, TK>(A, 0, tile, L, S, sh);
 }
 
 // Persistent workgroups draining a work list through an atomic cursor; every
@@ -1337,7 +1337,7 @@ struct ItemList {
 };
 
 // Tier 2 of a single job: the tiles that did not fit tier 1's LDS (full LDS here).
-template <int N, int PATH>
+template <int N, int PATH, int TK = N>
 __global__ __launch_bounds__((threads_of<N, PATH>())) void overflow_kernel(JobDesc A, Launch L, ItemList in) {
     extern __shared__ long long S[];
     __shared__ Shared sh;
@@ -1345,13 +1345,13 @@ __global__ __launch_bounds__((threads_of<N, PATH>())) void overflow_kernel(JobDe
     for (;;) {
         const int i = next_item(in.cursor, sh);
         if (i >= total) break;
-        process_tile<N, PATH>(A, 0, in.items[i].y, L, S, sh);
+        process_tile<N, PATH, TK>(A, 0, in.items[i].y, L, S, sh);
     }
 }
 
 // Tier 3 of a single job: windows larger than any workgroup's LDS, each workgroup
 // working in its own slice of a global scratch buffer (L2/MALL-resident).
-template <int N, int PATH>
+template <int N, int PATH, int TK = N>
 __global__ __launch_bounds__((threads_of<N, PATH>())) void scratch_kernel(JobDesc A, Launch L, ItemList in, long long* scratch) {
     __shared__ Shared sh;
     long long* S = scratch + (long long)blockIdx.x * L.lds_cap;
@@ -1359,7 +1359,7 @@ __global__ __launch_bounds__((threads_of<N, PATH>())) void scratch_kernel(JobDes
     for (;;) {
         const int i = next_item(in.cursor, sh);
         if (i >= total) break;
-        process_tile<N, PATH>(A, 0, in.items[i].y, L, S, sh);
+        process_tile<N, PATH, TK>(A, 0, in.items[i].y, L, S, sh);
     }
 }
 
@@ -1904,13 +1904,16 @@ bsf_status validate(bsf_ctx* c, const bsf_job* j, bool need_out) {
     return BSF_OK;
 }
 
-template <int N>
+template <int N, int K = N>
 long long window_bound_elems(float a_max) {
     const double R = reach1(N, a_max, a_max, a_max);
-    return window_elems(tile_window<N>(0, 0, kTile, kTile, R, R));
+    return window_elems(tile_window<N, K>(0, 0, kTile, kTile, R, R));
 }
 
-long long window_bound(int n, float a_max) {
+// the largest window a 16x16 tile of order n (model m: -1 = phi = delta) needs for scales up to a_max
+long long window_bound(int n, float a_max, int model = -1) {
+    if (model == 0) return window_bound_elems<1, table_key(1, 0)>(a_max);
+    if (model == 1) return window_bound_elems<1, table_key(1, 1)>(a_max);
     switch (n) {
         case 1: return window_bound_elems<1>(a_max);
         case 2: return window_bound_elems<2>(a_max);
@@ -1983,27 +1986,36 @@ Tiers make_tiers(const bsf_ctx* c, const Plan& p, char* work, const WorkLayout& 
                          (long long*)(work + w.scratch_off), items, order, grid3);
 }
 
-template <int N, int PATH>
+template <int N, int PATH, int TK = N>
 hipError_t launch_single(const JobDesc& A, const Plan& p, const Tiers& t, int tiles, hipStream_t st) {
     static bool once = false;
     if (!once) {
-        allow_big_lds(&tile_kernel<N, PATH>);
-        allow_big_lds(&overflow_kernel<N, PATH>);
-        allow_big_lds(&debug_tile_kernel<N, PATH>);
+        allow_big_lds(&tile_kernel<N, PATH, TK>);
+        allow_big_lds(&overflow_kernel<N, PATH, TK>);
+        allow_big_lds(&debug_tile_kernel<N, PATH, TK>);
         once = true;
     }
-    hipLaunchKernelGGL((tile_kernel<N, PATH>), dim3(tiles), dim3(threads_of<N, PATH>()), (size_t)p.t1 * 8, st, A, t.L1);
+    hipLaunchKernelGGL((tile_kernel<N, PATH, TK>), dim3(tiles), dim3(threads_of<N, PATH>()), (size_t)p.t1 * 8, st, A, t.L1);
     if (p.use2)
-        hipLaunchKernelGGL((overflow_kernel<N, PATH>), dim3(t.grid2), dim3(threads_of<N, PATH>()), (size_t)p.t2 * 8, st, A, t.L2,
-                           t.inA);
+        hipLaunchKernelGGL((overflow_kernel<N, PATH, TK>), dim3(t.grid2), dim3(threads_of<N, PATH>()), (size_t)p.t2 * 8, st, A,
+                           t.L2, t.inA);
     if (p.use3)
-        hipLaunchKernelGGL((scratch_kernel<N, PATH>), dim3(t.grid3), dim3(threads_of<N, PATH>()), 0, st, A, t.L3, t.inB, t.scratch);
+        hipLaunchKernelGGL((scratch_kernel<N, PATH, TK>), dim3(t.grid3), dim3(threads_of<N, PATH>()), 0, st, A, t.L3, t.inB,
+                           t.scratch);
     return hipGetLastError();
 }
 
 hipError_t dispatch_single(int n, int path, const JobDesc& A, const Plan& p, const Tiers& t, int tiles,
-                           hipStream_t st) {
+                           hipStream_t st, int model = -1) {
 #define BSF_SINGLE(NN, PP) return launch_single<NN, PP>(A, p, t, tiles, st)
+    if (model >= 0) {  // the continuous models (order 1)
+        if (path == BSF_PATH_F64) {
+            if (model == 0) return launch_single<1, BSF_PATH_F64, table_key(1, 0)>(A, p, t, tiles, st);
+            return launch_single<1, BSF_PATH_F64, table_key(1, 1)>(A, p, t, tiles, st);
+        }
+        if (model == 0) return launch_single<1, BSF_PATH_F32_TILED, table_key(1, 0)>(A, p, t, tiles, st);
+        return launch_single<1, BSF_PATH_F32_TILED, table_key(1, 1)>(A, p, t, tiles, st);
+    }
     if (path == BSF_PATH_F64) {
         if (n == 1) BSF_SINGLE(1, BSF_PATH_F64);
         if (n == 2) BSF_SINGLE(2, BSF_PATH_F64);
@@ -2055,9 +2067,9 @@ JobDesc make_desc(const bsf_job* j, unsigned* err) {
 }
 
 // Window elements a job's tiles can need, from its a_max (0: at most the whole LDS)
-long long job_window_need(const bsf_ctx* c, const bsf_job* j) {
+long long job_window_need(const bsf_ctx* c, const bsf_job* j, int model = -1) {
     const long long full = ((long long)c->lds_max_bytes - c->lds_static[j->order]) / 8;
-    if (j->a_max > 0.0f) return window_bound(j->order, j->a_max) + 64;
+    if (j->a_max > 0.0f) return window_bound(j->order, j->a_max, model) + 64;
     return full;
 }
 
@@ -2132,6 +2144,14 @@ long long measure_static_lds_n() {
     static_lds(&batch_overflow_kernel<N, 1>, mx);
     static_lds(&batch_scratch_kernel<N, 0>, mx);
     static_lds(&batch_scratch_kernel<N, 1>, mx);
+    if constexpr (N == 1) {  // the continuous models run at order 1
+        static_lds(&tile_kernel<1, 0, table_key(1, 0)>, mx);
+        static_lds(&tile_kernel<1, 1, table_key(1, 0)>, mx);
+        static_lds(&tile_kernel<1, 0, table_key(1, 1)>, mx);
+        static_lds(&tile_kernel<1, 1, table_key(1, 1)>, mx);
+        static_lds(&overflow_kernel<1, 0, table_key(1, 1)>, mx);
+        static_lds(&overflow_kernel<1, 1, table_key(1, 1)>, mx);
+    }
     return mx;
 }
 
@@ -2415,11 +2435,14 @@ bsf_status bsf_workspace_size(const bsf_job* job, size_t* bytes) {
     return BSF_OK;
 }
 
-bsf_status bsf_filter(bsf_ctx* c, const bsf_job* j, void* stream) {
+bsf_status bsf_filter_model(bsf_ctx* c, const bsf_job* j, int model, void* stream) {
     if (!c) return BSF_ERR_INVALID_ARG;
     bsf_status s = validate(c, j, true);
     if (s != BSF_OK) return s;
-    const Plan p = plan_tiers(c, job_window_need(c, j), j->order);
+    if (model < -1 || model > 1) return fail(c, BSF_ERR_UNSUPPORTED, "model degree must be -1, 0 or 1");
+    if (model >= 0 && j->order != 1)
+        return fail(c, BSF_ERR_UNSUPPORTED, "the continuous models are provided at order 1");
+    const Plan p = plan_tiers(c, job_window_need(c, j, model), j->order);
     if (!bsf_plan::plan_fits(c->limits(), p, j->order))
         return fail(c, BSF_ERR_UNSUPPORTED, "the launch's LDS exceeds the device's limit");
     hipStream_t st = (hipStream_t)stream;
@@ -2439,11 +2462,13 @@ bsf_status bsf_filter(bsf_ctx* c, const bsf_job* j, void* stream) {
     } else {
         t = make_tiers(c, p, nullptr, WorkLayout{}, tiles, j->order);
     }
-    e = dispatch_single(j->order, j->path, A, p, t, tiles, st);
+    e = dispatch_single(j->order, j->path, A, p, t, tiles, st, model);
     if (e == hipSuccess && slot >= 0) e = hipEventRecord(c->slot[slot].done, st);
     if (e != hipSuccess) return hip_fail(c, e, "tile kernel launch");
     return BSF_OK;
 }
+
+bsf_status bsf_filter(bsf_ctx* c, const bsf_job* j, void* stream) { return bsf_filter_model(c, j, -1, stream); }
 
 bsf_status bsf_filter_noalloc(bsf_ctx* c, const bsf_job* j, void* stream) {
     if (!c) return BSF_ERR_INVALID_ARG;

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "boxspline_tables.h"
+#include "model_tables.h"
 
 namespace bsf {
 
@@ -126,6 +127,7 @@ struct Tab;
 template <>
 struct Tab<1> {
     static constexpr int S = bsf_tables::kStencil1, M = bsf_tables::kMono1, DEG = 2;
+    static constexpr bool ODD = true;  // cells centred on lattice points (anchor = round(p))
     static constexpr double DEN = bsf_tables::kDen1;
     static constexpr int SPLIT = 2, SHIFT = 32;  // int64 -> 2 exact doubles of 32 bits
     __host__ __device__ static constexpr double num(int j, int a) { return bsf_tables::kNum1[j][a]; }
@@ -137,6 +139,7 @@ struct Tab<1> {
 template <>
 struct Tab<2> {
     static constexpr int S = bsf_tables::kStencil2, M = bsf_tables::kMono2, DEG = 6;
+    static constexpr bool ODD = false;  // cells centred on lattice points (anchor = round(p))
     static constexpr double DEN = bsf_tables::kDen2;
     static constexpr int SPLIT = 2, SHIFT = 32;
     __host__ __device__ static constexpr double num(int j, int a) { return bsf_tables::kNum2[j][a]; }
@@ -148,6 +151,7 @@ struct Tab<2> {
 template <>
 struct Tab<3> {
     static constexpr int S = bsf_tables::kStencil3, M = bsf_tables::kMono3, DEG = 10;
+    static constexpr bool ODD = true;  // cells centred on lattice points (anchor = round(p))
     static constexpr double DEN = bsf_tables::kDen3;
     static constexpr int SPLIT = 3, SHIFT = 21;  // 21-bit parts keep every partial sum exact
     __host__ __device__ static constexpr double num(int j, int a) { return bsf_tables::kNum3[j][a]; }
@@ -156,6 +160,42 @@ struct Tab<3> {
     __host__ __device__ static constexpr int ma(int a) { return bsf_tables::kMonoExp3[a][0]; }
     __host__ __device__ static constexpr int mb(int a) { return bsf_tables::kMonoExp3[a][1]; }
 };
+
+// Interpolants of the continuous models of degree m = 0, 1 (Section 6, phi = beta^m x beta^m)
+// for the order-1 filter, table keys 10 + m: phi * beta_b is the box spline of
+// {l1^(m+2), l2, l3^(m+2), l4} (phi adds m+1 unit segments along l1 and l3), degree 2m + 4.
+// Its centre (m/2 + 1, m/2 + 2) is a lattice point for even m, so its cells are centred on
+// half-integer points there (anchor = floor(p)), and on lattice points for odd m.
+template <>
+struct Tab<10> {
+    static constexpr int S = bsf_tables::kStencilM10, M = bsf_tables::kMonoM10, DEG = 4;
+    static constexpr bool ODD = false;
+    static constexpr double DEN = bsf_tables::kDenM10;
+    static constexpr int SPLIT = 2, SHIFT = 32;
+    __host__ __device__ static constexpr double num(int j, int a) { return bsf_tables::kNumM10[j][a]; }
+    __host__ __device__ static constexpr int jx(int j) { return bsf_tables::kJM10[j][0]; }
+    __host__ __device__ static constexpr int jy(int j) { return bsf_tables::kJM10[j][1]; }
+    __host__ __device__ static constexpr int ma(int a) { return bsf_tables::kMonoExpM10[a][0]; }
+    __host__ __device__ static constexpr int mb(int a) { return bsf_tables::kMonoExpM10[a][1]; }
+};
+template <>
+struct Tab<11> {
+    static constexpr int S = bsf_tables::kStencilM11, M = bsf_tables::kMonoM11, DEG = 6;
+    static constexpr bool ODD = true;
+    static constexpr double DEN = bsf_tables::kDenM11;
+    static constexpr int SPLIT = 2, SHIFT = 32;
+    __host__ __device__ static constexpr double num(int j, int a) { return bsf_tables::kNumM11[j][a]; }
+    __host__ __device__ static constexpr int jx(int j) { return bsf_tables::kJM11[j][0]; }
+    __host__ __device__ static constexpr int jy(int j) { return bsf_tables::kJM11[j][1]; }
+    __host__ __device__ static constexpr int ma(int a) { return bsf_tables::kMonoExpM11[a][0]; }
+    __host__ __device__ static constexpr int mb(int a) { return bsf_tables::kMonoExpM11[a][1]; }
+};
+
+// The table key of order n with the model of degree m (-1: phi = delta).
+__host__ __device__ constexpr int table_key(int n, int m) { return m < 0 ? n : 10 + m; }
+// Half-width of phi's support along each axis, (m + 1)/2 (0 for phi = delta).
+template <int K>
+__host__ __device__ constexpr double model_reach() { return K >= 10 ? 0.5 * (K - 10 + 1) : 0.0; }
 
 // The reference triangle u1 >= |u2| is symmetric under u2 -> -u2 (about the cell
 // centre), so stencil point j and its mirror j' = (jx, e - jy) (e = 0 odd n, 1 even n)
@@ -184,14 +224,14 @@ __host__ __device__ constexpr int exact_bits() {
 
 template <int N>
 __host__ __device__ constexpr int mirror_of(int j) {
-    const int e = (N & 1) ? 0 : 1;
+    const int e = Tab<N>::ODD ? 0 : 1;
     for (int k = 0; k < Tab<N>::S; ++k)
         if (Tab<N>::jx(k) == Tab<N>::jx(j) && Tab<N>::jy(k) == e - Tab<N>::jy(j)) return k;
     return -1;
 }
 template <int N>
 __host__ __device__ constexpr bool is_rep(int j) {  // representative of its mirror pair
-    return 2 * Tab<N>::jy(j) >= ((N & 1) ? 0 : 1);
+    return 2 * Tab<N>::jy(j) >= (Tab<N>::ODD ? 0 : 1);
 }
 
 // Bounds of the stencil after the quarter turns about the cell centre (odd n: about
@@ -205,12 +245,12 @@ __host__ __device__ constexpr int stencil_lo() {
         hi = Tab<N>::jx(j) > hi ? Tab<N>::jx(j) : hi;
         hi = Tab<N>::jy(j) > hi ? Tab<N>::jy(j) : hi;
     }
-    const int other = (N & 1) ? -hi : 1 - hi;
+    const int other = Tab<N>::ODD ? -hi : 1 - hi;
     return lo < other ? lo : other;
 }
 template <int N>
 __host__ __device__ constexpr int stencil_hi() {
-    return (N & 1) ? -stencil_lo<N>() : 1 - stencil_lo<N>();
+    return Tab<N>::ODD ? -stencil_lo<N>() : 1 - stencil_lo<N>();
 }
 
 // ---------------------------------------------------------------------------
@@ -224,14 +264,17 @@ struct Window {
     int x0, y0, wq, hq;
 };
 
-template <int N>
+// K: the interpolant's table (order N, or a continuous model of it); a model's kernel
+// support reaches model_reach<K>() further along each axis.
+template <int N, int K = N>
 __host__ __device__ inline Window tile_window(int t1, int t2, int tw, int th, double R1, double R2) {
-    const double qlo = (N & 1) ? -0.5 : -1.0, qhi = (N & 1) ? 0.5 : 0.0;
-    const int jl = stencil_lo<N>(), jh = stencil_hi<N>();
-    int lx = (int)floor(-R1 - 0.5 * N + qlo) + jl, sx = (int)floor(-R1);
-    int hx = (int)ceil(R1 - 0.5 * N + qhi) + jh, ux = (int)ceil(R1);
-    int ly = (int)floor(-R2 - 1.5 * N + qlo) + jl, sy = (int)floor(-R2);
-    int hy = (int)ceil(R2 - 1.5 * N + qhi) + jh, uy = (int)ceil(R2);
+    const double qlo = Tab<K>::ODD ? -0.5 : -1.0, qhi = Tab<K>::ODD ? 0.5 : 0.0;
+    const int jl = stencil_lo<K>(), jh = stencil_hi<K>();
+    constexpr double e = model_reach<K>();
+    int lx = (int)floor(-R1 - 0.5 * N + qlo) + jl, sx = (int)floor(-R1 - e);
+    int hx = (int)ceil(R1 - 0.5 * N + qhi) + jh, ux = (int)ceil(R1 + e);
+    int ly = (int)floor(-R2 - 1.5 * N + qlo) + jl, sy = (int)floor(-R2 - e);
+    int hy = (int)ceil(R2 - 1.5 * N + qhi) + jh, uy = (int)ceil(R2 + e);
     Window w;
     w.x0 = t1 + (lx < sx ? lx : sx) - 1;
     w.y0 = t2 + (ly < sy ? ly : sy) - 1;

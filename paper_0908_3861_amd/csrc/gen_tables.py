@@ -42,7 +42,8 @@ Self-checks run before anything is written: partition of unity, the lattice
 values 1/2 and 1/8 of the n=1 element, quarter-turn symmetry (all four triangles
 computed independently), and continuity across the triangle edges.
 
-Usage:  python gen_tables.py  [--out boxspline_tables.h]
+Usage:  python gen_tables.py  [--out boxspline_tables.h] [--orders 1,2,3] [--models-out model_tables.h]
+        [--models 0,1]  (--orders '' writes the model tables alone)
 """
 import argparse
 import itertools
@@ -174,10 +175,11 @@ def add_direction(Tcone, xi):
     return new
 
 
-def cone_spline(n):
-    """T_Xi per sector as dict polynomials, Xi = {l1^n, l2^n, l3^n, l4^n}."""
+def cone_spline(n, q=None):
+    """T_Xi per sector as dict polynomials, Xi = {l1^n, l2^q, l3^n, l4^q} (q = n by default)."""
+    q = n if q is None else q
     Tcone = {0: sp.Integer(1), 1: sp.Integer(1)}  # cone of l1, l3: 1/|det| = 1
-    order = [DIRS[0]] * (n - 1) + [DIRS[2]] * (n - 1) + [DIRS[1]] * n + [DIRS[3]] * n
+    order = [DIRS[0]] * (n - 1) + [DIRS[2]] * (n - 1) + [DIRS[1]] * q + [DIRS[3]] * q
     for xi in order:
         Tcone = add_direction(Tcone, xi)
     return {s: sym_to_dict(e) for s, e in Tcone.items()}
@@ -186,14 +188,15 @@ def cone_spline(n):
 # ----------------------------------------------------------------------------
 # box spline pieces on cells
 # ----------------------------------------------------------------------------
-def box_piece(cone, n, base, centroid):
+def box_piece(cone, n, base, centroid, q=None):
     """Polynomial in u of M_Xi(base + u) on the mesh triangle that contains
-    base + centroid (base, centroid rational 2-vectors)."""
+    base + centroid (base, centroid rational 2-vectors); Xi = {l1^n, l2^q, l3^n, l4^q}."""
+    q = n if q is None else q
     P = {}
-    for k in itertools.product(range(n + 1), repeat=4):
+    for k in itertools.product(range(n + 1), range(q + 1), range(n + 1), range(q + 1)):
         coef = (-1) ** sum(k)
-        for kd in k:
-            coef *= comb(n, kd)
+        for kd, md in zip(k, (n, q, n, q)):
+            coef *= comb(md, kd)
         v = (k[0] * 1 + k[1] * 1 + k[3] * -1, k[1] + k[2] + k[3])
         z0 = (base[0] - v[0], base[1] - v[1])
         s = sector_of((z0[0] + centroid[0], z0[1] + centroid[1]))
@@ -217,25 +220,31 @@ def cell_offset(n):
     return (Fraction(0), Fraction(0)) if n % 2 else (Fraction(1, 2), Fraction(1, 2))
 
 
-def tables(n, check=True):
-    cone = cone_spline(n)
-    c = (Fraction(n, 2), Fraction(3 * n, 2))
+def tables(n, check=True, q=None):
+    """Pieces of the centred box spline of Xi = {l1^n, l2^q, l3^n, l4^q} (q = n: the order-n
+    lattice box spline).  With q = order and n = order + model + 1 it is the interpolant of
+    the continuous model of degree `model` (Section 6: phi * beta_b, phi = beta^model x
+    beta^model adds model + 1 unit segments along l1 and l3)."""
+    q = n if q is None else q
+    cone = cone_spline(n, q)
+    c = (Fraction(n, 2), Fraction(n, 2) + q)  # the centre: half of sum of the segments
     o = cell_offset(n)
-    r = (3 * n + 3) // 2 + 1
+    r = (n + 2 * q + 3) // 2 + 1
     pieces = {tri: {} for tri in range(4)}
     for tri in range(4):
         for j in itertools.product(range(-r, r + 1), repeat=2):
             base = (o[0] - j[0] + c[0], o[1] - j[1] + c[1])
-            P = box_piece(cone, n, base, TRI_CENTROID[tri])
+            P = box_piece(cone, n, base, TRI_CENTROID[tri], q)
             if P:
                 pieces[tri][j] = P
     if check:
-        self_check(n, pieces, o)
+        self_check(n, pieces, o, q)
     return pieces
 
 
-def self_check(n, pieces, o):
-    deg = 4 * n - 2
+def self_check(n, pieces, o, q=None):
+    q = n if q is None else q
+    deg = 2 * n + 2 * q - 2
     for tri in range(4):
         tot = {}
         for j, P in pieces[tri].items():
@@ -257,7 +266,7 @@ def self_check(n, pieces, o):
         B = pieces[1].get(j, {})
         for s in [Fraction(k, 7) for k in range(0, 4)]:
             assert peval(A, s, s) == peval(B, s, s)
-    if n == 1:
+    if n == 1 and q == 1:
         # lattice values of the unit-mass element: 1/2 at the centre, 1/8 at the axis neighbours
         P0 = pieces[0]
         assert peval(P0[(0, 0)], 0, 0) == Fraction(1, 2)
@@ -268,8 +277,9 @@ def self_check(n, pieces, o):
         assert peval(P0[(0, 0)], Fraction(1, 2), Fraction(1, 2)) == Fraction(1, 4)
 
 
-def monomials(n):
-    deg = 4 * n - 2
+def monomials(n, q=None):
+    q = n if q is None else q
+    deg = 2 * n + 2 * q - 2
     return [(a, b) for a in range(deg + 1) for b in range(deg + 1 - a)]
 
 
@@ -277,22 +287,25 @@ def lcm(a, b):
     return a * b // gcd(a, b)
 
 
-def emit(all_tables, path):
+def emit(all_tables, path, suffix=lambda key: str(key), title=None, label=lambda key: f"order n = {key}"):
     lines = []
     lines.append("// Generated by gen_tables.py -- do not edit.")
-    lines.append("// Exact piecewise-polynomial pieces of the order-n four-direction lattice box spline")
-    lines.append("// (the interpolant of the adaptive step, Section 7) on the reference triangle")
+    for t in (title or ["Exact piecewise-polynomial pieces of the order-n four-direction lattice box spline",
+                        "(the interpolant of the adaptive step, Section 7) on the reference triangle"]):
+        lines.append("// " + t)
     lines.append("// u1 >= |u2| of an interpolation cell.  For anchor q and local offset u:")
     lines.append("//   sum_j g[q+j] beta_n(o + u - j) = (1/DEN) * sum_a u1^a1 u2^a2 * sum_j NUM[j][a] g[q+j]")
     lines.append("#pragma once")
     lines.append("namespace bsf_tables {")
-    for n, (pieces, mono) in all_tables.items():
+    for key, (pieces, mono) in all_tables.items():
+        n = suffix(key)
+        deg = max(a + b for a, b in mono)
         stencil = sorted(pieces[0].keys(), key=lambda j: (j[1], j[0]))
         den = 1
         for j in stencil:
             for m, cf in pieces[0][j].items():
                 den = lcm(den, cf.denominator)
-        lines.append(f"// order n = {n}: {len(stencil)} stencil points, {len(mono)} monomials, degree {4*n-2}")
+        lines.append(f"// {label(key)}: {len(stencil)} stencil points, {len(mono)} monomials, degree {deg}")
         lines.append(f"constexpr int kStencil{n} = {len(stencil)};")
         lines.append(f"constexpr int kMono{n} = {len(mono)};")
         lines.append(f"constexpr double kDen{n} = {den}.0;")
@@ -319,17 +332,32 @@ def emit(all_tables, path):
 
 
 def main():
+    here = os.path.dirname(os.path.abspath(__file__))
     ap = argparse.ArgumentParser()
-    ap.add_argument("--out", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
-                                                  "boxspline_tables.h"))
+    ap.add_argument("--out", default=os.path.join(here, "boxspline_tables.h"))
     ap.add_argument("--orders", default="1,2,3")
+    ap.add_argument("--models-out", default=os.path.join(here, "model_tables.h"),
+                    help="tables of the continuous models (order 1, model degrees 0 and 1); '' to skip")
+    ap.add_argument("--models", default="0,1")
     args = ap.parse_args()
     all_tables = {}
-    for n in [int(s) for s in args.orders.split(",")]:
-        pieces = tables(n)
-        all_tables[n] = (pieces, monomials(n))
-        print(f"n={n}: stencil {len(pieces[0])} points", file=sys.stderr)
-    emit(all_tables, args.out)
+    if args.orders:
+        for n in [int(s) for s in args.orders.split(",")]:
+            pieces = tables(n)
+            all_tables[n] = (pieces, monomials(n))
+            print(f"n={n}: stencil {len(pieces[0])} points", file=sys.stderr)
+        emit(all_tables, args.out, suffix=lambda n: str(n))
+    if args.models_out:
+        # order 1, model degree m: Xi = {l1^(m+2), l2, l3^(m+2), l4}, key 10 + m
+        models = {}
+        for m in [int(v) for v in args.models.split(",")]:
+            pieces = tables(m + 2, q=1)
+            models[10 + m] = (pieces, monomials(m + 2, 1))
+            print(f"order 1, model {m}: stencil {len(pieces[0])} points", file=sys.stderr)
+        emit(models, args.models_out, suffix=lambda k: f"M{k}", label=lambda k: f"order 1, model degree {k - 10}",
+             title=["Exact piecewise-polynomial pieces of the interpolant phi * beta_b of the continuous model",
+                    "of degree m (Section 6, phi = beta^m x beta^m) for the order-1 four-direction filter:",
+                    "the box spline of {l1^(m+2), l2, l3^(m+2), l4}, table key 10 + m, on the reference triangle"])
 
 
 if __name__ == "__main__":

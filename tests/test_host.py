@@ -113,6 +113,15 @@ def test_rep3_groups_header_is_current(tmp_path):
     assert out.read_text() == open(os.path.join(csrc, "rep3_groups.h")).read()
 
 
+def test_model_tables_header_is_current(tmp_path):
+    """model_tables.h is what gen_tables.py writes for the continuous models (degrees 0, 1)."""
+    csrc = os.path.join(ROOT, "paper_0908_3861_amd", "csrc")
+    out = tmp_path / "model_tables.h"
+    subprocess.run([sys.executable, os.path.join(csrc, "gen_tables.py"), "--orders", "", "--models-out", str(out)],
+                   check=True, capture_output=True)
+    assert out.read_text() == open(os.path.join(csrc, "model_tables.h")).read()
+
+
 def test_binding_structs_match_the_header(tmp_path):
     """The ctypes job structures have the C layout of include/bsf.h (field offsets and size),
     checked by compiling the header with gcc."""
