@@ -9,7 +9,9 @@ Mpixel/s, the roofline of the filter call (HIP events on its launch stream) and 
 oracle timed on a bounded pixel sample.
 
 The default run also times the float32-output path on the same inputs (its speedup and its
-error against the oracle at the same pixels, in extra.f32tiled).
+error against the oracle at the same pixels, in extra.f32tiled), reports the cancellation
+factor kappa of the sampled pixels (extra.kappa) and runs a short serving stream
+(extra.serving: p50/p99 latency, Mpixel/s; the full 60 s form is --workload serving).
 
 Other forms (not run by default): --workload small | precision | batched | serving | stage1 |
 ellipse (the scale field of elliptical windows, the step before the filter) | signal1d (the
@@ -250,6 +252,12 @@ def workload_plain(args):
     # the global (paper's literal) stage 1 alone over the same image, padded by the
     # halo of the largest scale: R = (n/2)(a + 2a/sqrt2) + 3n, about 42 at n = 2, a = 16
     extra["stage1_global_alone"] = stage1_alone(job, 42, max(3, args.steps // 2), 2)
+    if args.serving_seconds > 0:
+        # a short run of the serving stream (the full form: --workload serving, 60 s)
+        sv = serving_stream(args, args.serving_seconds, False)
+        for k in ("_pixels", "_wall", "budget_gib", "streams", "pool"):
+            sv.pop(k, None)
+        extra["serving"] = sv
     if W == 2048 and H == 2048:
         key = kernel_source_key()
         roof["traffic"] = MEASURED_TRAFFIC.get(key, {}).get(("plain", args.path))
@@ -350,7 +358,10 @@ def workload_batched(args):
                   extra)
 
 
-def workload_serving(args):
+def serving_stream(args, duration: float, compare: bool) -> dict:
+    """A Poisson stream of requests through the continuous-batching server: square sides
+    log-uniform in [128, max_side], f32/f64 50/50, integer scales U{1..8}, orders U{1,2,3};
+    the rate is 0.7 x the capacity of a closed-loop probe on the same pool (or --rate)."""
     import torch
     from paper_0908_3861_amd import serve
     rng = np.random.default_rng(5)
@@ -364,6 +375,7 @@ def workload_serving(args):
         sc = synth.integer_scales(rng, s, s, 1, 8)
         pool.append((torch.from_numpy(img).pin_memory(), torch.from_numpy(sc).pin_memory(), n,
                      "f64" if f64 else "f32tiled"))
+
     def server(graphs):
         return serve.Server(budget_bytes=args.budget_gib << 30, slots=args.slots, streams=4, a_max=8.0,
                             graphs=graphs, max_group=args.slots)
@@ -378,8 +390,8 @@ def workload_serving(args):
     capacity = len(pool) / probe_s
     srv.close()
     rate = args.rate if args.rate > 0 else 0.7 * capacity
-    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=int(rate * args.duration * 2) + 10))
-    arrivals = arrivals[arrivals < args.duration]
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=int(rate * duration * 2) + 10))
+    arrivals = arrivals[arrivals < duration]
     picks = rng.integers(0, len(pool), size=len(arrivals))
 
     def stream_run(graphs):
@@ -401,18 +413,25 @@ def workload_serving(args):
         return st, wall
 
     st, wall = stream_run(True)
-    extra = {"p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"], "requests": st["completed"],
-             "failed": st["failed"], "launches": st["launches"], "launch_form": "captured batch plans (graph replay)",
-             "arrival_rate_hz": rate, "capacity_probe_hz": capacity, "duration_s": args.duration,
-             "budget_gib": args.budget_gib, "slots": args.slots, "streams": 4, "pool": len(pool)}
-    if args.serving_compare:
+    out = {"p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"], "requests": st["completed"],
+           "failed": st["failed"], "launches": st["launches"], "Mpixel_per_s": st["pixels"] / wall / 1e6,
+           "launch_form": "captured batch plans (graph replay)", "arrival_rate_hz": rate,
+           "capacity_probe_hz": capacity, "duration_s": duration, "budget_gib": args.budget_gib,
+           "slots": args.slots, "streams": 4, "pool": len(pool), "max_side": args.max_side,
+           "_pixels": st["pixels"], "_wall": wall}
+    if compare:
         st_e, wall_e = stream_run(False)
-        extra["eager"] = {"p50_ms": st_e["p50_ms"], "p99_ms": st_e["p99_ms"], "mean_ms": st_e["mean_ms"],
-                          "Mpixel_per_s": st_e["pixels"] / wall_e / 1e6, "launches": st_e["launches"]}
+        out["eager"] = {"p50_ms": st_e["p50_ms"], "p99_ms": st_e["p99_ms"], "mean_ms": st_e["mean_ms"],
+                        "Mpixel_per_s": st_e["pixels"] / wall_e / 1e6, "launches": st_e["launches"]}
+    return out
+
+
+def workload_serving(args):
+    extra = serving_stream(args, args.duration, args.serving_compare)
+    pixels, wall = extra.pop("_pixels"), extra.pop("_wall")
     config = {"workload": "serving: Poisson stream, square sides log-uniform [128, %d], f32/f64 50/50, "
                           "integer scales U{1..8}, orders U{1,2,3}" % args.max_side}
-    return record(st["pixels"] / wall / 1e6, wall, 1, 0, "f64 / f64-mesh+f32-out (mixed)", config,
-                  None, None, extra)
+    return record(pixels / wall / 1e6, wall, 1, 0, "f64 / f64-mesh+f32-out (mixed)", config, None, None, extra)
 
 
 def workload_stage1(args):
@@ -652,6 +671,8 @@ def main():
                              "rect"])
     ap.add_argument("--no-f32-leg", action="store_true", help="plain workload: skip the float32-output leg")
     ap.add_argument("--kappa-seconds", type=float, default=6.0, help="CPU time for the kappa percentiles")
+    ap.add_argument("--serving-seconds", type=float, default=15.0,
+                    help="plain workload: length of the short serving stream (0: skip)")
     ap.add_argument("--serving-compare", action="store_true", help="serving: also run the stream with eager launches")
     ap.add_argument("--signals", type=int, default=1024)
     ap.add_argument("--length", type=int, default=65536)
