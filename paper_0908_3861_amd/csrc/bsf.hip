@@ -13,6 +13,7 @@
 #include <type_traits>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -53,6 +54,13 @@ struct Launch {
     unsigned* push_count; // tiles whose window does not fit go to this list for a later,
     int2* push_list;      //   larger launch: (job, tile); push_cap = 0 flags them instead
     int push_cap;
+    // tier 3 takes 2x2 blocks of tiles: one word per item (job's item_base + the block's
+    // first tile) holds the block's tiles that go there (bit (ty & 1) * 2 + (tx & 1)).
+    // blk_role 1 (tier 1, which sees every tile): clear the word of each block's first
+    // tile; 2 (tier 2): set the tile's bit and push the block, (job, first tile), when it
+    // is the block's first bit.
+    unsigned* blocks;
+    int blk_role;
     // test aid: dump one tile's pre-integrated window instead of filtering
     long long* dbg_window;
     int* dbg_geom;
@@ -128,10 +136,10 @@ __device__ __forceinline__ void walk_step(const Geo& g, LineWalk& w, int sgn) { 
 // that direction cancels, and they keep the integers small near the tile centre.  An
 // anchored line is two independent recursions -- forward from tref (part 0) and backward
 // from it (part 1, which also zeroes tref) -- run by different threads.  CHECK: detect
-// int64 overflow (the recursions wrap modulo 2^64 either way).
-template <int NF, bool CHECK, int DR, int DC, typename V>
+// int64 overflow (the recursions wrap modulo 2^64 either way).  B: loads in flight per
+// thread (more for a window in global memory, whose latency they hide).
+template <int NF, bool CHECK, int DR, int DC, int B, typename V>
 __device__ void scan_line_n(V* S, const Geo& g, int r0, int c0, int len, int tref, int part, unsigned& ovf) {
-    constexpr int B = 8;
     V y[NF];
 #pragma unroll
     for (int k = 0; k < NF; ++k) y[k] = 0;
@@ -213,14 +221,14 @@ __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? l
 
 // Stage 1 on the window (eq. RS steps (1)-(4), n folds each, fused into one pass per
 // direction).  cen: anchor every line at the tile centre (cc, rc) instead of at its start.
-template <int NF, bool CHECK, typename V>
+template <int NF, bool CHECK, int B, typename V>
 __device__ void preintegrate_window_n(V* S, const Geo& g, bool cen, int cc, int rc, unsigned& ovf) {
     const int tid = threadIdx.x, nt = blockDim.x;
     const int W = g.wq, H = g.hq, Wt = W + H - 1;
     const int parts = cen ? 2 : 1;
     for (int it = tid; it < H * parts; it += nt) {  // (1) along (1,0): rows
         const int part = it >= H, r = it - part * H;
-        scan_line_n<NF, CHECK, 0, 1>(S, g, r, 0, Wt - r, cen ? clampi(cc, 0, Wt - r - 1) : -1, part, ovf);
+        scan_line_n<NF, CHECK, 0, 1, B>(S, g, r, 0, Wt - r, cen ? clampi(cc, 0, Wt - r - 1) : -1, part, ovf);
     }
     __syncthreads();
     const int nd = Wt + H - 1;
@@ -230,19 +238,19 @@ __device__ void preintegrate_window_n(V* S, const Geo& g, bool cen, int cc, int 
         const int rs = e < 0 ? -e : 0;
         const int re = std::min(H - 1, (W + H - 2 - e) >> 1);
         const int len = re - rs + 1;
-        scan_line_n<NF, CHECK, 1, 1>(S, g, rs, e + rs, len, cen ? clampi(rc - rs, 0, len - 1) : -1, part, ovf);
+        scan_line_n<NF, CHECK, 1, 1, B>(S, g, rs, e + rs, len, cen ? clampi(rc - rs, 0, len - 1) : -1, part, ovf);
     }
     __syncthreads();
     for (int it = tid; it < Wt * parts; it += nt) {  // (3) along (0,1): columns
         const int part = it >= Wt, c = it - part * Wt;
         const int len = std::min(H, Wt - c);
-        scan_line_n<NF, CHECK, 1, 0>(S, g, 0, c, len, cen ? clampi(rc, 0, len - 1) : -1, part, ovf);
+        scan_line_n<NF, CHECK, 1, 0, B>(S, g, 0, c, len, cen ? clampi(rc, 0, len - 1) : -1, part, ovf);
     }
     __syncthreads();
     for (int it = tid; it < Wt * parts; it += nt) {  // (4) along (-1,1): anti-diagonals c + r = e, read down-right
         const int part = it >= Wt, e = it - part * Wt;
         const int len = std::min(H, e + 1);
-        scan_line_n<NF, CHECK, 1, -1>(S, g, 0, e, len, cen ? clampi(rc, 0, len - 1) : -1, part, ovf);
+        scan_line_n<NF, CHECK, 1, -1, B>(S, g, 0, e, len, cen ? clampi(rc, 0, len - 1) : -1, part, ovf);
     }
     __syncthreads();
 }
@@ -255,19 +263,22 @@ __device__ __forceinline__ double fold_gain(int m, int n) {
     return r;
 }
 
-// Stage 1 with the overflow checks only where an a priori bound does not exclude int64
-// overflow: with |x| < 2^bits, every value of every recursion is below
-// 2^bits * gain(Wt) * gain(hq)^3 (rows are at most Wt = wq + hq - 1 long, the other lines
-// at most hq).
-template <int N, typename V>
+// Whether int64 overflow is possible in stage 1: with |x| < 2^bits, every value of every
+// recursion is below 2^bits * gain(Wt) * gain(hq)^3 (rows are at most Wt = wq + hq - 1
+// long, the other lines at most hq).
+template <int N>
+__device__ __forceinline__ bool stage1_needs_check(const Geo& g, int bits) {
+    const double h = fold_gain(g.hq, N);
+    return !(ldexp(1.0, bits) * fold_gain(g.wq + g.hq - 1, N) * h * h * h < 0x1p62);
+}
+
+// Stage 1 with the overflow checks only where the bound above does not exclude overflow.
+template <int N, int B = 8, typename V>
 __device__ void preintegrate_window(V* S, const Geo& g, bool cen, int cc, int rc, int bits, unsigned& ovf) {
     bool check = false;
-    if constexpr (std::is_integral<V>::value) {
-        const double h = fold_gain(g.hq, N);
-        check = !(ldexp(1.0, bits) * fold_gain(g.wq + g.hq - 1, N) * h * h * h < 0x1p62);
-    }
-    if (check) preintegrate_window_n<N, true>(S, g, cen, cc, rc, ovf);
-    else preintegrate_window_n<N, false>(S, g, cen, cc, rc, ovf);
+    if constexpr (std::is_integral<V>::value) check = stage1_needs_check<N>(g, bits);
+    if (check) preintegrate_window_n<N, true, B>(S, g, cen, cc, rc, ovf);
+    else preintegrate_window_n<N, false, B>(S, g, cen, cc, rc, ovf);
 }
 
 // ---------------------------------------------------------------------------
@@ -873,6 +884,144 @@ __device__ double mesh_f64(const long long* S, int wq, int hq, int mx, int my, f
     return acc;
 }
 
+// ---------------------------------------------------------------------------
+// The mesh over a band of the window (windows held in global scratch, evaluated from LDS
+// in bands of rows).  A pixel's taps come in triples (k2, k4, k3) whose three k1 taps
+// share the anchor row; a triple belongs to the band when its stencil's first window row
+// q2 + stencil_lo lies in [own0, own1).  Each lane walks its own triples, skipping the
+// ones of other bands, so that a wave spends one tap evaluation per owned tap of its
+// busiest lane rather than per triple of the band.  The band buffer S holds window rows
+// row0 .. row0 + nrows - 1 at the window's pitch wq.  The tap geometry is mesh_dd's and
+// mesh_f64's, operation for operation; the taps are summed triple by triple, band by band.
+// ---------------------------------------------------------------------------
+template <int N, int SRC, int LOW = Tab<N>::DEG, int K = N>
+__device__ dd mesh_dd_band(const long long* S, int wq, int nrows, int row0, int own0, int own1, int mx, int my,
+                           float4 a, int k2lo, int k2hi, unsigned& bad, double& E) {
+    const dd isq = {kInvSqrt2Hi, kInvSqrt2Lo};
+    const double a1 = a.x, a3 = a.z;
+    const dd A2 = dd_mul_d(isq, (double)a.y);
+    const dd A4 = dd_mul_d(isq, (double)a.w);
+    constexpr double h = 0.5 * N;
+    constexpr int NP = N + 1;
+    constexpr int jl = stencil_lo<K>();
+    const dd T1 = dd_mul_d(dd_add_d(dd_add(A2, dd_neg(A4)), a1 - 1.0), h);
+    const dd T2 = dd_mul_d(dd_add_d(dd_add(A2, A4), a3 - 3.0), h);
+    cp acc = {0.0, 0.0};
+    const int ntrip = (k2hi - k2lo + 1) * NP * NP;
+    int i = 0, cur = -1;  // the lane's next triple; the (k2, k4) pair B2 was formed for
+    dd B2 = {0.0, 0.0};
+    for (;;) {
+        int k2 = 0, k4 = 0, k3 = 0;
+        dd d2 = {0.0, 0.0};
+        double f2 = 0.0;
+        bool found = false;
+        for (; i < ntrip; ++i) {
+            const int p24 = i / NP;
+            k3 = i - p24 * NP;
+            k2 = k2lo + p24 / NP;
+            k4 = p24 - (p24 / NP) * NP;
+            if (p24 != cur) {
+                const dd D2 = dd_mul_d(A2, (double)k2), D4 = dd_mul_d(A4, (double)k4);
+                B2 = dd_add(T2, dd_neg(dd_add(D2, D4)));
+                cur = p24;
+            }
+            d2 = dd_add_d(B2, -(double)k3 * a3);
+            f2 = Tab<K>::ODD ? rint(d2.hi) : floor(d2.hi);
+            const int s = my + (int)f2 + jl;
+            if (s >= own0 && s < own1) {
+                found = true;
+                break;
+            }
+        }
+        if (!found) break;
+        ++i;
+        const int c24 = fd_binom<N>(k2) * fd_binom<N>(k4);
+        const dd D2 = dd_mul_d(A2, (double)k2), D4 = dd_mul_d(A4, (double)k4);
+        const dd B1 = dd_add(T1, dd_add(D4, dd_neg(D2)));
+        const double oc = Tab<K>::ODD ? 0.0 : 0.5;
+        const dd u2 = dd_add_d(d2, -(f2 + oc));
+        for (int k1 = 0; k1 <= N; ++k1) {
+            const int c124 = c24 * fd_binom<N>(k1);
+            const dd d1 = dd_add_d(B1, -(double)k1 * a1);
+            const double f1 = Tab<K>::ODD ? rint(d1.hi) : floor(d1.hi);
+            const dd u1 = dd_add_d(d1, -(f1 + oc));
+            const Turn t = cell_turn(u1.hi, u2.hi);
+            const dd v1 = dd_turn(t.swap, t.n1, u1, u2);
+            const dd v2 = dd_turn(t.swap, t.n2, u2, u1);
+            const TapFrame<K> fr = tap_frame<K>(mx + (int)f1, my + (int)f2 - row0, t, wq, nrows);
+            if (!fr.lo_ok) {
+                bad = 1;
+                continue;
+            }
+            double Bk = 0.0;
+            const cp P = interp_dd<K, SRC, LOW>(S, fr, v1, v2, Bk, bad);
+            const int c = c124 * fd_binom<N>(k3);
+            const double cs = ((k1 + k2 + k3 + k4) & 1) ? -(double)c : (double)c;
+            acc = cp_axpy(acc, cs, P);
+            if constexpr (LOW < Tab<K>::DEG) E = __fma_rn((double)c, Bk, E);
+        }
+    }
+    return fast_two_sum(acc.s, acc.c);
+}
+
+template <int N, int SRC, int K = N>
+__device__ double mesh_f64_band(const long long* S, int wq, int nrows, int row0, int own0, int own1, int mx, int my,
+                                float4 a, int k2lo, int k2hi, unsigned& bad) {
+    const double a1 = a.x, a3 = a.z;
+    const double A2 = (double)a.y * kInvSqrt2Hi, A4 = (double)a.w * kInvSqrt2Hi;
+    constexpr double h = 0.5 * N;
+    constexpr int NP = N + 1;
+    constexpr int jl = stencil_lo<K>();
+    const double T1 = h * (a1 + A2 - A4 - 1.0);
+    const double T2 = h * (A2 + a3 + A4 - 3.0);
+    double acc = 0.0;
+    const int ntrip = (k2hi - k2lo + 1) * NP * NP;
+    int i = 0;
+    for (;;) {
+        int k2 = 0, k4 = 0, k3 = 0;
+        double d2 = 0.0, f2 = 0.0;
+        bool found = false;
+        for (; i < ntrip; ++i) {
+            const int p24 = i / NP;
+            k3 = i - p24 * NP;
+            k2 = k2lo + p24 / NP;
+            k4 = p24 - (p24 / NP) * NP;
+            const double B2 = T2 - k2 * A2 - k4 * A4;
+            d2 = B2 - k3 * a3;
+            f2 = Tab<K>::ODD ? rint(d2) : floor(d2);
+            const int s = my + (int)f2 + jl;
+            if (s >= own0 && s < own1) {
+                found = true;
+                break;
+            }
+        }
+        if (!found) break;
+        ++i;
+        const int c24 = fd_binom<N>(k2) * fd_binom<N>(k4);
+        const double B1 = T1 - k2 * A2 + k4 * A4;
+        const double oc = Tab<K>::ODD ? 0.0 : 0.5;
+        const double u2 = d2 - f2 - oc;
+        for (int k1 = 0; k1 <= N; ++k1) {
+            const int c124 = c24 * fd_binom<N>(k1);
+            const double d1 = B1 - k1 * a1;
+            const double f1 = Tab<K>::ODD ? rint(d1) : floor(d1);
+            const double u1 = d1 - f1 - oc;
+            const Turn t = cell_turn(u1, u2);
+            const double w1 = t.swap ? u2 : u1, w2 = t.swap ? u1 : u2;
+            const double v1 = t.n1 ? -w1 : w1, v2 = t.n2 ? -w2 : w2;
+            const TapFrame<K> fr = tap_frame<K>(mx + (int)f1, my + (int)f2 - row0, t, wq, nrows);
+            if (!fr.lo_ok) {
+                bad = 1;
+                continue;
+            }
+            const double P = interp_f64<K, SRC>(S, fr, v1, v2, bad);
+            const int c = c124 * fd_binom<N>(k3);
+            acc = __fma_rn(((k1 + k2 + k3 + k4) & 1) ? -(double)c : (double)c, P, acc);
+        }
+    }
+    return acc;
+}
+
 template <int N, int K = N>
 __device__ double finalize_f64(double acc, float4 a) {
     const double prod = ((double)a.x * (double)a.y) * ((double)a.z * (double)a.w);
@@ -1019,6 +1168,7 @@ __device__ __forceinline__ void process_tile(const JobDesc A, int job, int tile,
     __syncthreads();  // the previous item of this workgroup is done with S and the scratch
     const int tx = tile % A.tiles_x, ty = tile / A.tiles_x;
     const int t1 = tx * kTile, t2 = ty * kTile;
+    if (L.blk_role == 1 && tid == 0 && !((tx | ty) & 1)) L.blocks[A.item_base + tile] = 0u;
     const int tw = std::min(kTile, A.width - t1), th = std::min(kTile, A.height - t2);
     const int px = pix % kTile, py = pix / kTile;
     const int m1 = t1 + px, m2 = t2 + py;
@@ -1073,9 +1223,17 @@ __device__ __forceinline__ void process_tile(const JobDesc A, int job, int tile,
         }
         if (L.push_cap > 0) {  // a later launch with more room takes the tile
             if (tid == 0) {
-                const unsigned k = atomicAdd(L.push_count, 1u);
-                if (k < (unsigned)L.push_cap) L.push_list[k] = make_int2(job, tile);
-                else atomicOr(A.err, kErrWindow);
+                int item = tile;
+                bool push = true;
+                if (L.blk_role == 2) {  // by 2x2 blocks: the block's first flagged tile pushes it
+                    item = (ty & ~1) * A.tiles_x + (tx & ~1);
+                    push = atomicOr(L.blocks + A.item_base + item, 1u << ((ty & 1) * 2 + (tx & 1))) == 0u;
+                }
+                if (push) {
+                    const unsigned k = atomicAdd(L.push_count, 1u);
+                    if (k < (unsigned)L.push_cap) L.push_list[k] = make_int2(job, item);
+                    else atomicOr(A.err, kErrWindow);
+                }
             }
             return;
         }
@@ -1299,6 +1457,325 @@ __device__ __forceinline__ void process_tile(const JobDesc A, int job, int tile,
     store(s);
 }
 
+// Tier 3: the flagged 16x16 tiles of one 2x2 block of tiles (bit s of `mask`: the tile
+// at (tx0 + (s & 1), ty0 + (s >> 1)), tx0, ty0 even, the block's first tile `lead`), whose
+// windows exceed any workgroup's LDS, filtered from one restart window over their common
+// extent, pre-integrated in S, a slice of global scratch: stage 1 runs once for up to four
+// tiles (the window of the extent is little larger than one tile's, the reach dominating
+// both).  The mesh reads the window from LB, band_cap elements of LDS, in bands of rows
+// (mesh_dd_band, mesh_f64_band); the float64 path keeps each pixel's sums over the digit
+// passes in LB's last 8 NT doubles.  Otherwise as process_tile.
+template <int N, int PATH, int TK = N>
+__device__ __forceinline__ void process_block(const JobDesc A, int lead, unsigned mask, const Launch L, long long* S,
+                                              Shared& sh_, long long* LB, long long band_cap) {
+    auto& red = sh_.red;
+    auto& redi = sh_.redi;
+    constexpr int SPLIT = split_of<N, PATH>(), NT = threads_of<N, PATH>(), NW = NT / 64;
+    const int tid = threadIdx.x;
+    const int pix = tid % kThreads, half = tid / kThreads;
+    const int k2lo = SPLIT == 1 ? 0 : half * (N + 1) / 2, k2hi = SPLIT == 1 ? N : (half + 1) * (N + 1) / 2 - 1;
+    __syncthreads();  // the previous item of this workgroup is done with S, LB and the scratch
+    const int tx0 = lead % A.tiles_x, ty0 = lead / A.tiles_x;
+    const int px = pix % kTile, py = pix / kTile;
+    // the thread's pixel in sub-tile s
+    struct Px {
+        int m1, m2;
+        bool inside, valid;
+        float4 a;
+    };
+    auto pixel_of = [&](int s) {
+        Px q;
+        const int t1 = (tx0 + (s & 1)) * kTile, t2 = (ty0 + (s >> 1)) * kTile;
+        q.m1 = t1 + px;
+        q.m2 = t2 + py;
+        q.inside = q.m1 < A.width && q.m2 < A.height;
+        q.a = make_float4(0.f, 0.f, 0.f, 0.f);
+        q.valid = false;
+        if (q.inside) {
+            q.a = *reinterpret_cast<const float4*>(A.scales + 4 * ((long long)q.m2 * A.scale_pitch + q.m1));
+            const float av[4] = {q.a.x, q.a.y, q.a.z, q.a.w};
+            q.valid = true;
+#pragma unroll
+            for (int d = 0; d < 4; ++d) q.valid = q.valid && (av[d] >= (float)kScaleMin) && (av[d] <= (float)kScaleMax);
+        }
+        return q;
+    };
+    auto store = [&](const Px& q, double v) {
+        if (!q.inside || half) return;
+        const long long off = (long long)q.m2 * A.out_pitch + q.m1;
+        if (PATH == BSF_PATH_F64)
+            ((double*)A.out)[off] = v;
+        else
+            ((float*)A.out)[off] = (float)v;
+    };
+
+    // 1. the scale vectors of the flagged tiles, their reach and their common extent
+    double R1 = 0.0, R2 = 0.0;
+    int ex0 = A.width, ey0 = A.height, ex1 = 0, ey1 = 0;
+    for (int s = 0; s < 4; ++s) {
+        if (!((mask >> s) & 1u)) continue;
+        const int t1 = (tx0 + (s & 1)) * kTile, t2 = (ty0 + (s >> 1)) * kTile;
+        ex0 = min(ex0, t1);
+        ey0 = min(ey0, t2);
+        ex1 = max(ex1, min(t1 + kTile, A.width));
+        ey1 = max(ey1, min(t2 + kTile, A.height));
+        const Px q = pixel_of(s);
+        if (q.inside && !q.valid && !half) atomicOr(A.err, kErrScale);
+        if (q.valid) {
+            R1 = fmax(R1, reach1(N, q.a.x, q.a.y, q.a.w));
+            R2 = fmax(R2, reach1(N, q.a.z, q.a.y, q.a.w));
+        }
+    }
+    R1 = wave_max(R1);
+    R2 = wave_max(R2);
+    if ((tid & 63) == 0) {
+        red[0][tid >> 6] = R1;
+        red[1][tid >> 6] = R2;
+    }
+    __syncthreads();
+    R1 = red[0][0];
+    R2 = red[1][0];
+#pragma unroll
+    for (int wv = 1; wv < NW; ++wv) {
+        R1 = fmax(R1, red[0][wv]);
+        R2 = fmax(R2, red[1][wv]);
+    }
+
+    // 2. the restart window of the extent
+    const Window w = tile_window<N, TK>(ex0, ey0, ex1 - ex0, ey1 - ey0, R1, R2);
+    const long long need = window_elems(w);
+    const double nan = __builtin_nan("");
+    auto store_all = [&](double v) {
+        for (int s = 0; s < 4; ++s)
+            if ((mask >> s) & 1u) store(pixel_of(s), v);
+    };
+    if (need > L.lds_cap) {
+        if (tid == 0) atomicOr(A.err, kErrWindow);
+        store_all(nan);
+        return;
+    }
+    const Geo g = {w.wq, w.hq, w.wq * w.hq};
+    const int ntri = (g.hq * (g.hq - 1)) / 2;
+    const int cc = (ex0 + ex1) / 2 - w.x0, rc = (ey0 + ey1) / 2 - w.y0;  // centre of the extent
+
+    // Runs body(src, nrows, row0, own0, own1) -- by every thread of the workgroup -- once per
+    // band of the window: rows row0 .. row0 + nrows - 1 copied from S to LB, owning the
+    // triples whose stencil starts in rows [own0, own1) (the first band also those above
+    // the window, the last those below, which the taps then flag).  Consecutive bands
+    // overlap by the stencil's height.  A window too wide for bands of 8 owned rows is read
+    // where it lies, as one band.
+    const long long band_elems = PATH == BSF_PATH_F64 ? band_cap - 8 * NT : band_cap;
+    auto over_bands = [&](auto&& body) {
+        constexpr int span = stencil_hi<TK>() - stencil_lo<TK>();
+        const int rows_cap = band_elems > 0 ? (int)(band_elems / g.wq) : 0;
+        const int own = rows_cap - span;
+        if (own < 8) {
+            body((const long long*)S, g.hq, 0, INT_MIN, INT_MAX);
+            return;
+        }
+        for (int r0 = 0;; r0 += own) {
+            const bool last = r0 + own >= g.hq - span;
+            const int nrows = min(rows_cap, g.hq - r0);
+            __syncthreads();  // the previous band's taps are done with LB
+            const long long* src = S + (long long)r0 * g.wq;
+            for (int i = tid; i < nrows * g.wq; i += NT) LB[i] = src[i];
+            __syncthreads();
+            body((const long long*)LB, nrows, r0, r0 == 0 ? INT_MIN : r0, last ? INT_MAX : r0 + own);
+            if (last) break;
+        }
+    };
+
+    if constexpr (PATH == BSF_PATH_F32_TILED) {
+        // float32 output (as process_tile): float64 running sums of the samples as they are
+        double* Sd = reinterpret_cast<double*>(S);
+        with_dtype(A.in_dtype, [&](auto dt) {
+            constexpr int DT = decltype(dt)::value;
+            load_box<double>(g, tid, NT, [&](int r, int c) { return sample_at<DT>(A, w.x0 + c, w.y0 + r); },
+                             [&](int i, double v) { Sd[i] = v; });
+        });
+        for (int i = tid; i < ntri; i += NT) Sd[g.qn + i] = 0.0;
+        __syncthreads();
+        unsigned unused = 0;
+        preintegrate_window<N>(Sd, g, true, cc, rc, 0, unused);
+        __syncthreads();
+        for (int s = 0; s < 4; ++s) {
+            if (!((mask >> s) & 1u)) continue;
+            const Px q = pixel_of(s);
+            const int mx = q.m1 - w.x0, my = q.m2 - w.y0;
+            unsigned bad = 0;
+            dd m = {0.0, 0.0};
+            over_bands([&](const long long* src, int nrows, int row0, int own0, int own1) {
+                if (q.valid)
+                    m.hi += mesh_f64_band<N, SRC_DBL, TK>(src, g.wq, nrows, row0, own0, own1, mx, my, q.a, k2lo, k2hi, bad);
+            });
+            combine_halves<SPLIT>(m, bad);
+            if (!q.inside || half) continue;
+            double v = q.valid ? finalize_f64<N, TK>(m.hi, q.a) : nan;
+            if (bad) {
+                atomicOr(A.err, kErrWindow);
+                v = nan;
+            }
+            store(q, v);
+        }
+        return;
+    }
+
+    // 3. the exact integer grid of the window (as process_tile)
+    int top = A.in_dtype == BSF_U8 ? 8 : -1100, fine = 0;
+    if (A.in_dtype != BSF_U8)
+        load_box<double, 1>(
+            g, tid, NT,
+            [&](int r, int c) {
+                return A.in_dtype == BSF_F32 ? sample_at<BSF_F32>(A, w.x0 + c, w.y0 + r)
+                                             : sample_at<BSF_F64>(A, w.x0 + c, w.y0 + r);
+            },
+            [&](int, double v) {
+                int t_, f_;
+                sample_grid(v, t_, f_);
+                top = max(top, t_);
+                fine = max(fine, f_);
+            });
+    top = wave_max_i(top);
+    fine = wave_max_i(fine);
+    __syncthreads();
+    if ((tid & 63) == 0) {
+        redi[0][tid >> 6] = top;
+        redi[1][tid >> 6] = fine;
+    }
+    __syncthreads();
+    top = redi[0][0];
+    fine = redi[1][0];
+#pragma unroll
+    for (int wv = 1; wv < NW; ++wv) {
+        top = max(top, redi[0][wv]);
+        fine = max(fine, redi[1][wv]);
+    }
+    const int sh = (top + fine > 53) ? 53 - top : fine;
+    const int bits = max(top + sh, 1);
+
+    // 4. stage 1 + the tiles' meshes, on K digits when int64 would overflow; the sums of
+    //    sub-tile s in acc[s][tid] (hi) and acc[s][NT + tid] (lo) of LB's tail
+    double* acc = reinterpret_cast<double*>(LB + band_elems);
+    unsigned badm = 0;  // bit s: a tap of sub-tile s fell outside the window
+    bool done = false;
+    for (int K = 1; K <= 4 && !done; ++K) {
+        const int B = (bits + K - 1) / K;
+        bool overflowed = false;
+        for (int k = 0; k < K; ++k) {
+            __syncthreads();  // the previous digit's meshes have finished reading the window
+            if (A.in_dtype == BSF_U8)
+                load_box<long long, 4>(
+                    g, tid, NT, [&](int r, int c) { return sample_u8(A, w.x0 + c, w.y0 + r); },
+                    [&](int i, long long v) { S[i] = digit(v, k, K, B); });
+            else
+                load_box<long long, 1>(
+                    g, tid, NT,
+                    [&](int r, int c) {
+                        const double v = A.in_dtype == BSF_F32 ? sample_at<BSF_F32>(A, w.x0 + c, w.y0 + r)
+                                                               : sample_at<BSF_F64>(A, w.x0 + c, w.y0 + r);
+                        return (long long)rint(ldexp(v, sh));
+                    },
+                    [&](int i, long long v) { S[i] = digit(v, k, K, B); });
+            for (int i = tid; i < ntri; i += NT) S[g.qn + i] = 0;
+            __syncthreads();
+            unsigned ovf = 0;
+            preintegrate_window<N>(S, g, true, cc, rc, (K == 1 ? bits : B) + 1, ovf);
+            ovf = __syncthreads_or(ovf);
+            if (ovf) {
+                overflowed = true;
+                break;
+            }
+            unsigned long long mag = 0;
+            for (int i = tid; i < g.qn; i += NT) {
+                const long long v = S[i];
+                mag |= (unsigned long long)(v < 0 ? -v : v);
+            }
+            constexpr int kExact = exact_bits<TK>();
+            const bool fast = !__syncthreads_or((mag >> kExact) != 0ull);
+            if (fast) {
+                for (int i = tid; i < g.qn; i += NT) reinterpret_cast<double*>(S)[i] = (double)S[i];
+                __syncthreads();
+            }
+            const double wk = ldexp(1.0, k * B);
+            for (int s = 0; s < 4; ++s) {
+                if (!((mask >> s) & 1u)) continue;
+                const Px q = pixel_of(s);
+                const int mx = q.m1 - w.x0, my = q.m2 - w.y0;
+                const bool act = q.valid;
+                unsigned bad = 0;
+                bool tried = false, redo = false;
+                const bool wave_split =
+                    __all(!act || (double)q.a.x * q.a.y * q.a.z * q.a.w >= split_min_volume<TK>()) != 0;
+                constexpr int LOW = split_low<TK>(), DEG = Tab<TK>::DEG;
+                const bool try_split = LOW < DEG && K == 1 && wave_split;
+                dd m = {0.0, 0.0};
+                double E = 0.0;
+                over_bands([&](const long long* src, int nrows, int row0, int own0, int own1) {
+                    if (!act) return;
+                    dd part;
+                    if (try_split)
+                        part = fast ? mesh_dd_band<N, SRC_DBL, LOW, TK>(src, g.wq, nrows, row0, own0, own1, mx, my, q.a,
+                                                                        k2lo, k2hi, bad, E)
+                                    : mesh_dd_band<N, SRC_INT, LOW, TK>(src, g.wq, nrows, row0, own0, own1, mx, my, q.a,
+                                                                        k2lo, k2hi, bad, E);
+                    else
+                        part = fast ? mesh_dd_band<N, SRC_DBL, DEG, TK>(src, g.wq, nrows, row0, own0, own1, mx, my, q.a,
+                                                                        k2lo, k2hi, bad, E)
+                                    : mesh_dd_band<N, SRC_INT, DEG, TK>(src, g.wq, nrows, row0, own0, own1, mx, my, q.a,
+                                                                        k2lo, k2hi, bad, E);
+                    m = dd_add(m, part);
+                });
+                // the split evaluation's bound (see process_tile): too large, evaluated again compensated
+                tried = act && try_split;
+                redo = tried && !(E <= 8.0 * fabs(m.hi));
+                if (__syncthreads_or(redo)) {
+                    dd m2 = {0.0, 0.0};
+                    over_bands([&](const long long* src, int nrows, int row0, int own0, int own1) {
+                        if (!redo) return;
+                        const dd part =
+                            fast ? mesh_dd_band<N, SRC_DBL, DEG, TK>(src, g.wq, nrows, row0, own0, own1, mx, my, q.a, k2lo,
+                                                                     k2hi, bad, E)
+                                 : mesh_dd_band<N, SRC_INT, DEG, TK>(src, g.wq, nrows, row0, own0, own1, mx, my, q.a, k2lo,
+                                                                     k2hi, bad, E);
+                        m2 = dd_add(m2, part);
+                    });
+                    if (redo) m = m2;
+                }
+                badm |= bad ? (1u << s) : 0u;
+                dd t = k == 0 ? dd{0.0, 0.0} : dd{acc[(2 * s) * NT + tid], acc[(2 * s + 1) * NT + tid]};
+                if (act) t = dd_add(t, dd_mul_d(m, wk));
+                acc[(2 * s) * NT + tid] = t.hi;
+                acc[(2 * s + 1) * NT + tid] = t.lo;
+                if (L.stats) {
+                    const int nt_ = __popcll(__ballot(tried)), nr_ = __popcll(__ballot(redo));
+                    if ((tid & 63) == 0 && nt_) {
+                        atomicAdd(L.stats, (unsigned long long)nt_);
+                        if (nr_) atomicAdd(L.stats + 1, (unsigned long long)nr_);
+                    }
+                }
+            }
+        }
+        done = !overflowed;
+    }
+    if (!done) {
+        if (tid == 0) atomicOr(A.err, kErrRange);
+        store_all(nan);
+        return;
+    }
+    for (int s = 0; s < 4; ++s) {
+        if (!((mask >> s) & 1u)) continue;
+        const Px q = pixel_of(s);
+        if (!q.inside) continue;
+        double v = q.valid ? ldexp(finalize_dd<N, TK>(dd{acc[(2 * s) * NT + tid], acc[(2 * s + 1) * NT + tid]}, q.a), -sh)
+                           : nan;
+        if ((badm >> s) & 1u) {
+            atomicOr(A.err, kErrWindow);
+            v = nan;
+        }
+        store(q, v);
+    }
+}
+
 // The window of the batch kernels, addressed through the kernel's dynamic LDS symbol.
 extern __shared__ long long g_lds[];
 
@@ -1352,14 +1829,17 @@ __global__ __launch_bounds__((threads_of<N, PATH>())) void overflow_kernel(JobDe
 // Tier 3 of a single job: windows larger than any workgroup's LDS, each workgroup
 // working in its own slice of a global scratch buffer (L2/MALL-resident).
 template <int N, int PATH, int TK = N>
-__global__ __launch_bounds__((threads_of<N, PATH>())) void scratch_kernel(JobDesc A, Launch L, ItemList in, long long* scratch) {
+__global__ __launch_bounds__((threads_of<N, PATH>())) __attribute__((amdgpu_waves_per_eu(N < 3 ? 2 : 1))) void scratch_kernel(
+    JobDesc A, Launch L, ItemList in, long long* scratch, long long band_cap) {
+    extern __shared__ long long LB[];
     __shared__ Shared sh;
     long long* S = scratch + (long long)blockIdx.x * L.lds_cap;
     const int total = (int)min(*in.count, (unsigned)in.cap);
     for (;;) {
         const int i = next_item(in.cursor, sh);
         if (i >= total) break;
-        process_tile<N, PATH, TK>(A, 0, in.items[i].y, L, S, sh);
+        const int lead = in.items[i].y;
+        process_block<N, PATH, TK>(A, lead, L.blocks[A.item_base + lead], L, S, sh, LB, band_cap);
     }
 }
 
@@ -1428,8 +1908,8 @@ __global__ __launch_bounds__((threads_of<N, PATH>())) void batch_overflow_kernel
 }
 
 template <int N, int PATH>
-__global__ __launch_bounds__((threads_of<N, PATH>())) void batch_scratch_kernel(const JobDesc* jobs, const GroupHdr* hdr,
-                                                                                Launch L, ItemList in, long long* scratch) {
+__global__ __launch_bounds__((threads_of<N, PATH>())) __attribute__((amdgpu_waves_per_eu(N < 3 ? 2 : 1))) void batch_scratch_kernel(
+    const JobDesc* jobs, const GroupHdr* hdr, Launch L, ItemList in, long long* scratch, long long band_cap) {
     __shared__ Shared sh;
     long long* S = scratch + (long long)blockIdx.x * L.lds_cap;
     group_lists(*hdr, L, &in);
@@ -1438,7 +1918,8 @@ __global__ __launch_bounds__((threads_of<N, PATH>())) void batch_scratch_kernel(
         const int i = next_item(in.cursor, sh);
         if (i >= total) break;
         const int2 it = in.items[i];
-        process_tile<N, PATH>(jobs[it.x], it.x, it.y, L, S, sh);
+        const JobDesc A = jobs[it.x];
+        process_block<N, PATH>(A, it.y, L.blocks[A.item_base + it.y], L, S, sh, g_lds, band_cap);
     }
 }
 
@@ -1905,19 +2386,20 @@ bsf_status validate(bsf_ctx* c, const bsf_job* j, bool need_out) {
 }
 
 template <int N, int K = N>
-long long window_bound_elems(float a_max) {
+long long window_bound_elems(float a_max, int extent) {
     const double R = reach1(N, a_max, a_max, a_max);
-    return window_elems(tile_window<N, K>(0, 0, kTile, kTile, R, R));
+    return window_elems(tile_window<N, K>(0, 0, extent, extent, R, R));
 }
 
-// the largest window a 16x16 tile of order n (model m: -1 = phi = delta) needs for scales up to a_max
-long long window_bound(int n, float a_max, int model = -1) {
-    if (model == 0) return window_bound_elems<1, table_key(1, 0)>(a_max);
-    if (model == 1) return window_bound_elems<1, table_key(1, 1)>(a_max);
+// the largest window a 16x16 tile (extent 16), or a 2x2 block of tiles in tier 3 (extent
+// 32), of order n (model m: -1 = phi = delta) needs for scales up to a_max
+long long window_bound(int n, float a_max, int model = -1, int extent = kTile) {
+    if (model == 0) return window_bound_elems<1, table_key(1, 0)>(a_max, extent);
+    if (model == 1) return window_bound_elems<1, table_key(1, 1)>(a_max, extent);
     switch (n) {
-        case 1: return window_bound_elems<1>(a_max);
-        case 2: return window_bound_elems<2>(a_max);
-        default: return window_bound_elems<3>(a_max);
+        case 1: return window_bound_elems<1>(a_max, extent);
+        case 2: return window_bound_elems<2>(a_max, extent);
+        default: return window_bound_elems<3>(a_max, extent);
     }
 }
 
@@ -1933,7 +2415,9 @@ void allow_big_lds(K* kernel) {
 using bsf_plan::Plan;
 using bsf_plan::WorkLayout;
 
-Plan plan_tiers(const bsf_ctx* c, long long need, int order) { return bsf_plan::plan_tiers(c->limits(), need, order); }
+Plan plan_tiers(const bsf_ctx* c, long long need, int order, long long need3 = 0) {
+    return bsf_plan::plan_tiers(c->limits(), need, order, need3);
+}
 
 int per_cu(const bsf_ctx* c, long long elems, int order) { return bsf_plan::per_cu(c->limits(), elems, order); }
 
@@ -1951,8 +2435,9 @@ struct Tiers {
 // Tiers over `items` tiles whose overflow lists are la / lb (capacity items each) and
 // whose counters are ctr[0..4]: [0] list A count, [1] list A cursor, [2] tier-1 cursor,
 // [3] list B count, [4] list B cursor.
-Tiers make_tiers_at(const bsf_ctx* c, const Plan& p, unsigned* ctr, int2* la, int2* lb, long long* scratch,
-                    long long items, int order, long long grid3 = 0) {
+// blocks: tier 3's block words, one per item of the whole launch sequence (work_layout).
+Tiers make_tiers_at(const bsf_ctx* c, const Plan& p, unsigned* ctr, int2* la, int2* lb, unsigned* blocks,
+                    long long* scratch, long long items, int order, long long grid3 = 0) {
     Tiers t;
     t.L1 = Launch{};
     t.L1.lds_cap = p.t1;
@@ -1975,15 +2460,18 @@ Tiers make_tiers_at(const bsf_ctx* c, const Plan& p, unsigned* ctr, int2* la, in
         t.inB = ItemList{ctr + 3, lb, ctr + 4, (int)items};
         t.grid3 = (int)(grid3 > 0 ? grid3 : bsf_plan::grid3_of(c->limits(), items));
         t.scratch = scratch;
+        t.L1.blocks = t.L2.blocks = t.L3.blocks = blocks;
+        t.L1.blk_role = 1;
+        t.L2.blk_role = 2;
     }
     return t;
 }
 
 Tiers make_tiers(const bsf_ctx* c, const Plan& p, char* work, const WorkLayout& w, long long items, int order,
                  long long grid3 = 0) {
-    if (!work) return make_tiers_at(c, p, nullptr, nullptr, nullptr, nullptr, items, order);  // tier 1 only
+    if (!work) return make_tiers_at(c, p, nullptr, nullptr, nullptr, nullptr, nullptr, items, order);  // tier 1 only
     return make_tiers_at(c, p, (unsigned*)work, (int2*)(work + w.lists_off), (int2*)(work + w.listb_off),
-                         (long long*)(work + w.scratch_off), items, order, grid3);
+                         (unsigned*)(work + w.blocks_off), (long long*)(work + w.scratch_off), items, order, grid3);
 }
 
 template <int N, int PATH, int TK = N>
@@ -1992,6 +2480,7 @@ hipError_t launch_single(const JobDesc& A, const Plan& p, const Tiers& t, int ti
     if (!once) {
         allow_big_lds(&tile_kernel<N, PATH, TK>);
         allow_big_lds(&overflow_kernel<N, PATH, TK>);
+        allow_big_lds(&scratch_kernel<N, PATH, TK>);
         allow_big_lds(&debug_tile_kernel<N, PATH, TK>);
         once = true;
     }
@@ -2000,8 +2489,8 @@ hipError_t launch_single(const JobDesc& A, const Plan& p, const Tiers& t, int ti
         hipLaunchKernelGGL((overflow_kernel<N, PATH, TK>), dim3(t.grid2), dim3(threads_of<N, PATH>()), (size_t)p.t2 * 8, st, A,
                            t.L2, t.inA);
     if (p.use3)
-        hipLaunchKernelGGL((scratch_kernel<N, PATH, TK>), dim3(t.grid3), dim3(threads_of<N, PATH>()), 0, st, A, t.L3, t.inB,
-                           t.scratch);
+        hipLaunchKernelGGL((scratch_kernel<N, PATH, TK>), dim3(t.grid3), dim3(threads_of<N, PATH>()), (size_t)p.band * 8, st, A,
+                           t.L3, t.inB, t.scratch, p.band);
     return hipGetLastError();
 }
 
@@ -2071,6 +2560,10 @@ long long job_window_need(const bsf_ctx* c, const bsf_job* j, int model = -1) {
     const long long full = ((long long)c->lds_max_bytes - c->lds_static[j->order]) / 8;
     if (j->a_max > 0.0f) return window_bound(j->order, j->a_max, model) + 64;
     return full;
+}
+// the same for the 2x2 blocks of tier 3 (0 without a_max: no tier 3)
+long long job_window_need3(const bsf_job* j, int model = -1) {
+    return j->a_max > 0.0f ? window_bound(j->order, j->a_max, model, 2 * kTile) + 64 : 0;
 }
 
 // Take the next ring slot, wait until its previous call has finished on the device,
@@ -2144,6 +2637,8 @@ long long measure_static_lds_n() {
     static_lds(&batch_overflow_kernel<N, 1>, mx);
     static_lds(&batch_scratch_kernel<N, 0>, mx);
     static_lds(&batch_scratch_kernel<N, 1>, mx);
+    static_lds(&scratch_kernel<N, 0>, mx);
+    static_lds(&scratch_kernel<N, 1>, mx);
     if constexpr (N == 1) {  // the continuous models run at order 1
         static_lds(&tile_kernel<1, 0, table_key(1, 0)>, mx);
         static_lds(&tile_kernel<1, 1, table_key(1, 0)>, mx);
@@ -2151,6 +2646,8 @@ long long measure_static_lds_n() {
         static_lds(&tile_kernel<1, 1, table_key(1, 1)>, mx);
         static_lds(&overflow_kernel<1, 0, table_key(1, 1)>, mx);
         static_lds(&overflow_kernel<1, 1, table_key(1, 1)>, mx);
+        static_lds(&scratch_kernel<1, 0, table_key(1, 1)>, mx);
+        static_lds(&scratch_kernel<1, 1, table_key(1, 1)>, mx);
     }
     return mx;
 }
@@ -2161,6 +2658,7 @@ void opt_in_batch_kernels() {
     if (!once) {
         allow_big_lds(&batch_kernel<N, PATH>);
         allow_big_lds(&batch_overflow_kernel<N, PATH>);
+        allow_big_lds(&batch_scratch_kernel<N, PATH>);
         once = true;
     }
 }
@@ -2187,8 +2685,8 @@ hipError_t launch_batch_group(const bsf_ctx* c, const JobDesc* djobs, const Grou
         hipLaunchKernelGGL((batch_overflow_kernel<N, PATH>), dim3(t.grid2), dim3(threads_of<N, PATH>()), (size_t)p.t2 * 8, st,
                            djobs, hdr, t.L2, t.inA);
     if (p.use3)
-        hipLaunchKernelGGL((batch_scratch_kernel<N, PATH>), dim3(t.grid3), dim3(threads_of<N, PATH>()), 0, st, djobs, hdr, t.L3,
-                           t.inB, t.scratch);
+        hipLaunchKernelGGL((batch_scratch_kernel<N, PATH>), dim3(t.grid3), dim3(threads_of<N, PATH>()), (size_t)p.band * 8, st,
+                           djobs, hdr, t.L3, t.inB, t.scratch, p.band);
     return hipGetLastError();
 }
 
@@ -2431,7 +2929,7 @@ bsf_status bsf_workspace_size(const bsf_job* job, size_t* bytes) {
     const bsf_plan::Limits L = bsf_plan::gfx950_bound();
     const long long tiles = (long long)((job->width + kTile - 1) / kTile) * ((job->height + kTile - 1) / kTile);
     const long long need = job->a_max > 0.0f ? window_bound(job->order, job->a_max) + 64 : bsf_plan::full_cap(L, job->order);
-    *bytes = bsf_plan::single_call_bytes(L, bsf_plan::plan_tiers(L, need, job->order), tiles);
+    *bytes = bsf_plan::single_call_bytes(L, bsf_plan::plan_tiers(L, need, job->order, job_window_need3(job)), tiles);
     return BSF_OK;
 }
 
@@ -2442,7 +2940,7 @@ bsf_status bsf_filter_model(bsf_ctx* c, const bsf_job* j, int model, void* strea
     if (model < -1 || model > 1) return fail(c, BSF_ERR_UNSUPPORTED, "model degree must be -1, 0 or 1");
     if (model >= 0 && j->order != 1)
         return fail(c, BSF_ERR_UNSUPPORTED, "the continuous models are provided at order 1");
-    const Plan p = plan_tiers(c, job_window_need(c, j, model), j->order);
+    const Plan p = plan_tiers(c, job_window_need(c, j, model), j->order, job_window_need3(j, model));
     if (!bsf_plan::plan_fits(c->limits(), p, j->order))
         return fail(c, BSF_ERR_UNSUPPORTED, "the launch's LDS exceeds the device's limit");
     hipStream_t st = (hipStream_t)stream;
@@ -2475,7 +2973,7 @@ bsf_status bsf_filter_noalloc(bsf_ctx* c, const bsf_job* j, void* stream) {
     bsf_status s = validate(c, j, true);
     if (s != BSF_OK) return s;
     if (!c->noalloc) return fail(c, BSF_ERR_HIP, "no fixed work area on this device (" + c->noalloc_error + ")");
-    const Plan p = plan_tiers(c, job_window_need(c, j), j->order);
+    const Plan p = plan_tiers(c, job_window_need(c, j), j->order, job_window_need3(j));
     if (!bsf_plan::plan_fits(c->limits(), p, j->order))
         return fail(c, BSF_ERR_UNSUPPORTED, "the launch's LDS exceeds the device's limit");
     const JobDesc A = make_desc(j, c->d_err);
@@ -2508,7 +3006,7 @@ bsf_status bsf_filter_batched(bsf_ctx* c, const bsf_job* jobs, int njobs, void* 
     if (njobs < 0 || (njobs > 0 && !jobs)) return fail(c, BSF_ERR_INVALID_ARG, "bad batch");
     if (njobs == 0) return BSF_OK;
     constexpr int kVariants = 6;  // (order - 1) * 2 + path
-    long long need[kVariants] = {};
+    long long need[kVariants] = {}, need3[kVariants] = {};
     double vcost[kVariants] = {};
     std::vector<int> order(njobs);
     std::vector<double> cost(njobs);
@@ -2517,6 +3015,7 @@ bsf_status bsf_filter_batched(bsf_ctx* c, const bsf_job* jobs, int njobs, void* 
         if (s != BSF_OK) return fail(c, s, "job " + std::to_string(i) + ": " + c->last);
         const int n = jobs[i].order, v = (n - 1) * 2 + (int)jobs[i].path;
         need[v] = std::max(need[v], job_window_need(c, jobs + i));
+        need3[v] = std::max(need3[v], job_window_need3(jobs + i));
         // per-pixel mesh work ~ (n+1)^4 taps x 7n^2 interpolation weights
         cost[i] = (double)jobs[i].width * jobs[i].height * std::pow(n + 1.0, 4) * 7.0 * n * n;
         vcost[v] += cost[i];
@@ -2556,7 +3055,7 @@ bsf_status bsf_filter_batched(bsf_ctx* c, const bsf_job* jobs, int njobs, void* 
                 ++g.nj;
             }
             g.count = items - g.first;
-            g.p = plan_tiers(c, need[g.v], g.v / 2 + 1);
+            g.p = plan_tiers(c, need[g.v], g.v / 2 + 1, need3[g.v]);
             if (!bsf_plan::plan_fits(c->limits(), g.p, g.v / 2 + 1))
                 return fail(c, BSF_ERR_UNSUPPORTED, "the launch's LDS exceeds the device's limit");
             if (g.p.use3) {
@@ -2592,7 +3091,8 @@ bsf_status bsf_filter_batched(bsf_ctx* c, const bsf_job* jobs, int njobs, void* 
         const Group& g = groups[gi];
         unsigned* ctr = (unsigned*)work + 8 * g.v;  // each variant appears in one group
         const Tiers t = make_tiers_at(c, g.p, ctr, (int2*)(work + w.lists_off), (int2*)(work + w.listb_off),
-                                      (long long*)(work + w.scratch_off), g.count, g.v / 2 + 1);
+                                      (unsigned*)(work + w.blocks_off), (long long*)(work + w.scratch_off), g.count,
+                                      g.v / 2 + 1);
         e = dispatch_batch_group(c, g.v, djobs, dhdr + g.v, g.count, g.p, t, ctr, st);
         if (e != hipSuccess) return hip_fail(c, e, "batch kernel launch");
     }
@@ -2626,7 +3126,7 @@ bsf_status bsf_batch_plan_create(bsf_ctx* c, int max_jobs, long long max_tiles, 
     size_t scratch_bytes = 0;
     for (int v = 0; v < kVariants; ++v) {
         const int n = v / 2 + 1;
-        pv[v] = plan_tiers(c, window_bound(n, a_max) + 64, n);
+        pv[v] = plan_tiers(c, window_bound(n, a_max) + 64, n, window_bound(n, a_max, -1, 2 * kTile) + 64);
         if (!bsf_plan::plan_fits(c->limits(), pv[v], n))
             return fail(c, BSF_ERR_UNSUPPORTED, "the launch's LDS exceeds the device's limit");
         if (pv[v].use3)
@@ -2680,7 +3180,8 @@ bsf_status bsf_batch_plan_create(bsf_ctx* c, int max_jobs, long long max_tiles, 
         for (int v = 0; v < kVariants && le == hipSuccess; ++v) {
             unsigned* ctr = (unsigned*)work + 8 * v;
             const Tiers t = make_tiers_at(c, pv[v], ctr, (int2*)(work + w.lists_off), (int2*)(work + w.listb_off),
-                                          (long long*)(work + w.scratch_off), max_tiles, v / 2 + 1);
+                                          (unsigned*)(work + w.blocks_off), (long long*)(work + w.scratch_off),
+                                          max_tiles, v / 2 + 1);
             le = dispatch_batch_group(c, v, djobs, dhdr + v, max_tiles, pv[v], t, ctr, cs);
         }
         if (le == hipSuccess)

@@ -30,17 +30,19 @@ inline Limits gfx950_bound() {
 }
 
 // Window capacities (int64 elements) of the three launch tiers: tier 1 half the LDS (two
-// workgroups per CU), tier 2 the full LDS, tier 3 a per-workgroup slice of global scratch.
+// workgroups per CU), tier 2 the full LDS, tier 3 a per-workgroup slice of global scratch
+// holding the window of a 2x2 block of tiles, whose mesh reads it from an LDS band buffer
+// of `band` elements (half the LDS).
 struct Plan {
-    long long t1 = 0, t2 = 0, t3 = 0;
+    long long t1 = 0, t2 = 0, t3 = 0, band = 0;
     bool use2 = false, use3 = false;
 };
 
 inline long long full_cap(const Limits& L, int order) { return (L.lds_max - L.lds_static[order]) / 8; }
 inline long long half_cap(const Limits& L, int order) { return (L.lds_max / 2 - L.lds_static[order]) / 8; }
 
-// The tiers for windows of up to `need` elements.
-inline Plan plan_tiers(const Limits& L, long long need, int order) {
+// The tiers for tile windows of up to `need` elements (block windows of up to `need3`).
+inline Plan plan_tiers(const Limits& L, long long need, int order, long long need3 = 0) {
     const long long full = full_cap(L, order), half = half_cap(L, order);
     Plan p;
     if (need <= half) {
@@ -52,7 +54,8 @@ inline Plan plan_tiers(const Limits& L, long long need, int order) {
     } else {
         p.t1 = half;
         p.t2 = full;
-        p.t3 = need;
+        p.t3 = std::max(need, need3);
+        p.band = half;
         p.use2 = p.use3 = true;
     }
     return p;
@@ -64,9 +67,10 @@ inline bool launch_fits(const Limits& L, int order, long long dyn_bytes) {
     return dyn_bytes >= 0 && dyn_bytes + L.lds_static[order] <= L.lds_max;
 }
 
-// Every LDS launch of a plan fits (tier 3 uses no dynamic LDS).
+// Every LDS launch of a plan fits (tier 3's dynamic LDS is its band buffer).
 inline bool plan_fits(const Limits& L, const Plan& p, int order) {
-    return launch_fits(L, order, p.t1 * 8) && (!p.use2 || launch_fits(L, order, p.t2 * 8));
+    return launch_fits(L, order, p.t1 * 8) && (!p.use2 || launch_fits(L, order, p.t2 * 8)) &&
+           (!p.use3 || launch_fits(L, order, p.band * 8));
 }
 
 // Workgroups of a window size that fit one CU's LDS.
@@ -77,15 +81,17 @@ inline int per_cu(const Limits& L, long long elems, int order) {
 // Persistent workgroups of the tier-3 launch: two per CU, at most one per tile.
 inline long long grid3_of(const Limits& L, long long tiles) { return std::min<long long>(tiles, (long long)L.cus * 2); }
 
-// Device work area of one call: counters | list A | list B | job descriptors | scratch.
+// Device work area of one call: counters | list A | list B | tier-3 block words | job
+// descriptors | scratch.
 struct WorkLayout {
-    size_t lists_off = 256, listb_off = 0, jobs_off = 0, scratch_off = 0, total = 0;
+    size_t lists_off = 256, listb_off = 0, blocks_off = 0, jobs_off = 0, scratch_off = 0, total = 0;
 };
 
 inline WorkLayout work_layout(long long items, int njobs, size_t job_desc_bytes, size_t scratch_bytes) {
     WorkLayout w;
     w.listb_off = w.lists_off + (size_t)items * 8;  // (job, tile) pairs of two ints
-    w.jobs_off = ((w.listb_off + (size_t)items * 8) + 63) & ~(size_t)63;
+    w.blocks_off = w.listb_off + (size_t)items * 8;  // one word per item
+    w.jobs_off = ((w.blocks_off + (size_t)items * 4) + 63) & ~(size_t)63;
     w.scratch_off = ((w.jobs_off + (size_t)njobs * job_desc_bytes) + 255) & ~(size_t)255;
     w.total = w.scratch_off + scratch_bytes;
     return w;

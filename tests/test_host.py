@@ -168,6 +168,9 @@ int main() {
                 CHECK((need <= half) == !p.use2);
                 CHECK((need > full) == p.use3);
                 CHECK(!p.use3 || p.t3 == need);                      // tier 3 holds any window
+                const Plan p3 = plan_tiers(L, need, order, 2 * need);  // and any 2x2 block's window
+                CHECK(!p3.use3 || p3.t3 == 2 * need);
+                CHECK(p.use3 == (p.band > 0) && p.band <= half);      // tier 3's LDS band buffer
                 CHECK(p.use3 || (p.use2 ? p.t2 : p.t1) >= need);      // the last LDS tier holds it
                 // the bound used without a device never plans a smaller work area
                 const Limits B = gfx950_bound();
@@ -184,6 +187,11 @@ int main() {
         Limits M = L;
         M.lds_static[2] = 4096;
         CHECK(plan_fits(L, p, 2) && !plan_fits(M, p, 2));
+        // tier 3's band buffer is checked as well
+        Plan q = plan_tiers(L, 10 * full_cap(L, 2), 2);
+        CHECK(q.use3 && plan_fits(L, q, 2));
+        q.band = full_cap(L, 2) + 1;
+        CHECK(!plan_fits(L, q, 2));
     }
     // work area of a fixed buffer: lists, then at least one tier-3 slice
     {
