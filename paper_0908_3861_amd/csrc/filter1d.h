@@ -110,8 +110,45 @@ __device__ __forceinline__ cpair cp_axpy_i(cpair acc, double w, cpair v) {
     const dd t = two_sum(acc.s, h.hi);
     return {t.hi, acc.c + ((t.lo + h.lo) + v.c * w)};
 }
-__device__ __forceinline__ cpair shfl_up_cp(cpair v, int d) {
-    return {__shfl_up(v.s, d, 64), __shfl_up(v.c, d, 64)};
+// A pair moved across lanes by a DPP control (lanes without a source, or outside the row
+// mask, receive zero: bound_ctrl, and zero as the kept value).
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_f64(double v) {
+    unsigned long long b;
+    __builtin_memcpy(&b, &v, 8);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, ROWMASK, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, ROWMASK, 0xf, true);
+    b = ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+    double r;
+    __builtin_memcpy(&r, &b, 8);
+    return r;
+}
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ cpair dpp_cp(cpair v) {
+    return {dpp_f64<CTRL, ROWMASK>(v.s), dpp_f64<CTRL, ROWMASK>(v.c)};
+}
+// Inclusive compensated prefix sum over the wave's 64 lanes at register speed: shifts by 1, 2,
+// 4, 8 within each row of 16 lanes, then the broadcasts of lanes 15 and 31 into the rows above
+// (a lane adding a zero pair keeps its value exactly).
+__device__ __forceinline__ cpair wave_scan_cp(cpair v) {
+    v = cp_sum(dpp_cp<0x111, 0xf>(v), v);  // row_shr:1
+    v = cp_sum(dpp_cp<0x112, 0xf>(v), v);  // row_shr:2
+    v = cp_sum(dpp_cp<0x114, 0xf>(v), v);  // row_shr:4
+    v = cp_sum(dpp_cp<0x118, 0xf>(v), v);  // row_shr:8
+    v = cp_sum(dpp_cp<0x142, 0xa>(v), v);  // row_bcast:15 into rows 1 and 3
+    v = cp_sum(dpp_cp<0x143, 0xc>(v), v);  // row_bcast:31 into rows 2 and 3
+    return v;
+}
+// The pair of a wave-uniform lane l.
+__device__ __forceinline__ double lane_f64(double v, int l) {
+    unsigned long long b;
+    __builtin_memcpy(&b, &v, 8);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+    b = ((unsigned long long)hi << 32) | lo;
+    double r;
+    __builtin_memcpy(&r, &b, 8);
+    return r;
 }
 
 struct Args {
@@ -254,21 +291,15 @@ __global__ __launch_bounds__(kThreads) void filter1d_kernel(Args A) {
                     }
                 }
             }
-            cpair tot = s;
-#pragma unroll
-            for (int d = 1; d < 64; d <<= 1) {
-                const cpair o = shfl_up_cp(tot, d);
-                if (lane >= d) tot = cp_sum(o, tot);
-            }
-            pre = shfl_up_cp(tot, 1);
-            if (lane == 0) pre = {0.0, 0.0};
+            const cpair tot = wave_scan_cp(s);
+            pre = dpp_cp<0x138, 0xf>(tot);  // wave_shr:1, lane 0 receives zero
             // Anchor this fold at the window centre: subtract its value at position ctr (the
             // owner lane's prefix plus its local sum there) from every prefix.  The later folds
             // turn that constant into a polynomial of degree < n, which the mask annihilates;
             // the sums the mask cancels shrink by about 2^n.
             const int ctr = W / 2 - 1;
             const double2 xc = gbuf[ctr];
-            const cpair owner_pre = {__shfl(pre.s, ctr / C, 64), __shfl(pre.c, ctr / C, 64)};
+            const cpair owner_pre = {lane_f64(pre.s, ctr / C), lane_f64(pre.c, ctr / C)};
             const cpair anchor = cp_sum(owner_pre, {xc.x, xc.y});
             pre = cp_sum(pre, {-anchor.s, -anchor.c});
         }
