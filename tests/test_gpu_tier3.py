@@ -1,6 +1,7 @@
-"""GPU parity of the third launch tier: restart windows larger than a workgroup's LDS,
-pre-integrated in a slice of global scratch and read by the mesh from an LDS buffer in bands of
-rows, each pixel's taps taken up by the band that holds the first row of their stencil.
+"""GPU parity of the third launch tier: restart windows larger than a workgroup's LDS, one
+per 2x2 block of tiles, pre-integrated in a slice of global scratch and read by the mesh from an
+LDS buffer in bands of rows, each pixel's taps taken up by the band that holds the first row of
+their stencil.
 
 The central 16x16 tile of each image has scales large enough for a window beyond the full LDS
 (130 to 170 elements square plus the extension triangle, against 20k elements of LDS), so it
@@ -121,24 +122,24 @@ def test_windows_too_wide_for_bands_read_scratch(bsf, torch_dev, n, lo, hi, path
     assert err < (TOL_F64 if path == "f64" else TOL_F32), err
 
 
-@pytest.mark.parametrize("n,path", [(1, "f64"), (2, "f64"), (2, "f32tiled")])
+@pytest.mark.parametrize("n,path", [(1, "f64"), (2, "f64"), (1, "f32tiled"), (2, "f32tiled")])
 def test_full_and_ragged_blocks(bsf, torch_dev, oracle_mod, n, path):
-    """Tier 3 filters 2x2 blocks of tiles from one window: a full block (the four tiles of
-    [0, 32)^2), a block holding only the image's ragged corner tile (8x8 pixels at
-    [32, 40)^2), and the tier-1 tiles between them."""
+    """Tier 3 filters 2x2 blocks of tiles from one window: full blocks (the four blocks of
+    [0, 64)^2), a block holding only the image's ragged corner tile (8x8 pixels at
+    [64, 72)^2), and the tier-1 tiles between."""
     rng = np.random.default_rng(350 + n + (path == "f32tiled"))
-    H = W = 40
+    H = W = 72
     img = synth.unit_grid_image(rng, H, W, np.float32)
     sc = synth.uniform_scales(rng, H, W, 1.0, 3.0)
     lo, hi = (44.0, 48.0) if n == 1 else (16.0, 22.0)
-    sc[:32, :32] = rng.uniform(lo, hi, size=(32, 32, 4)).astype(np.float32)
-    sc[32:, 32:] = rng.uniform(lo, hi, size=(8, 8, 4)).astype(np.float32)
+    sc[:64, :64] = rng.uniform(lo, hi, size=(64, 64, 4)).astype(np.float32)
+    sc[64:, 64:] = rng.uniform(lo, hi, size=(8, 8, 4)).astype(np.float32)
     s, st = filt(bsf, torch_dev, img, sc, n, path, a_max=hi)
     assert st == 0
     assert np.isfinite(s).all()
-    full = rng.choice(32 * 32, 48, replace=False)
-    full = (full // 32) * W + full % 32
-    corner = (np.arange(32, 40)[:, None] * W + np.arange(32, 40)[None, :]).reshape(-1)
+    full = rng.choice(64 * 64, 64, replace=False)
+    full = (full // 64) * W + full % 64
+    corner = (np.arange(64, 72)[:, None] * W + np.arange(64, 72)[None, :]).reshape(-1)
     pix = np.concatenate([full, corner, rng.choice(H * W, 8, replace=False)])
     o = oracle_mod.filter(img.astype(np.float64), sc, n, pixels=pix)
     err = rel_max(s.reshape(-1)[pix], o)
