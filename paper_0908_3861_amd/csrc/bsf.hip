@@ -54,13 +54,6 @@ struct Launch {
     unsigned* push_count; // tiles whose window does not fit go to this list for a later,
     int2* push_list;      //   larger launch: (job, tile); push_cap = 0 flags them instead
     int push_cap;
-    // tier 3 takes 2x2 blocks of tiles: one word per item (job's item_base + the block's
-    // first tile) holds the block's tiles that go there (bit (ty & 1) * 2 + (tx & 1)).
-    // blk_role 1 (tier 1, which sees every tile): clear the word of each block's first
-    // tile; 2 (tier 2): set the tile's bit and push the block, (job, first tile), when it
-    // is the block's first bit.
-    unsigned* blocks;
-    int blk_role;
     // test aid: dump one tile's pre-integrated window instead of filtering
     long long* dbg_window;
     int* dbg_geom;
@@ -1155,10 +1148,14 @@ __device__ __forceinline__ void combine_halves(dd& acc, unsigned& bad) {
     }
 }
 
-// Filter one 16x16 tile of job A (index `job`) with the window in S.
+// Filter one 16x16 tile of job A (index `job`) with the window in S.  blocks (tier 2, when
+// tier 3 follows): tier 3 takes 2x2 blocks of tiles; one word per item (job's item_base +
+// the block's first tile), cleared before tier 1, holds the block's tiles that go there
+// (bit (ty & 1) * 2 + (tx & 1)), and a tile that does not fit sets its bit and pushes the
+// block, (job, first tile), when it is the block's first bit.
 template <int N, int PATH, int TK = N>
 __device__ __forceinline__ void process_tile(const JobDesc A, int job, int tile, const Launch L, long long* S,
-                                             Shared& sh_) {
+                                             Shared& sh_, unsigned* blocks = nullptr) {
     auto& red = sh_.red;
     auto& redi = sh_.redi;
     constexpr int SPLIT = split_of<N, PATH>(), NT = threads_of<N, PATH>(), NW = NT / 64;
@@ -1168,7 +1165,6 @@ __device__ __forceinline__ void process_tile(const JobDesc A, int job, int tile,
     __syncthreads();  // the previous item of this workgroup is done with S and the scratch
     const int tx = tile % A.tiles_x, ty = tile / A.tiles_x;
     const int t1 = tx * kTile, t2 = ty * kTile;
-    if (L.blk_role == 1 && tid == 0 && !((tx | ty) & 1)) L.blocks[A.item_base + tile] = 0u;
     const int tw = std::min(kTile, A.width - t1), th = std::min(kTile, A.height - t2);
     const int px = pix % kTile, py = pix / kTile;
     const int m1 = t1 + px, m2 = t2 + py;
@@ -1225,9 +1221,9 @@ __device__ __forceinline__ void process_tile(const JobDesc A, int job, int tile,
             if (tid == 0) {
                 int item = tile;
                 bool push = true;
-                if (L.blk_role == 2) {  // by 2x2 blocks: the block's first flagged tile pushes it
+                if (blocks) {  // by 2x2 blocks: the block's first flagged tile pushes it
                     item = (ty & ~1) * A.tiles_x + (tx & ~1);
-                    push = atomicOr(L.blocks + A.item_base + item, 1u << ((ty & 1) * 2 + (tx & 1))) == 0u;
+                    push = atomicOr(blocks + A.item_base + item, 1u << ((ty & 1) * 2 + (tx & 1))) == 0u;
                 }
                 if (push) {
                     const unsigned k = atomicAdd(L.push_count, 1u);
@@ -1815,14 +1811,15 @@ struct ItemList {
 
 // Tier 2 of a single job: the tiles that did not fit tier 1's LDS (full LDS here).
 template <int N, int PATH, int TK = N>
-__global__ __launch_bounds__((threads_of<N, PATH>())) void overflow_kernel(JobDesc A, Launch L, ItemList in) {
+__global__ __launch_bounds__((threads_of<N, PATH>())) void overflow_kernel(JobDesc A, Launch L, ItemList in,
+                                                                            unsigned* blocks) {
     extern __shared__ long long S[];
     __shared__ Shared sh;
     const int total = (int)min(*in.count, (unsigned)in.cap);
     for (;;) {
         const int i = next_item(in.cursor, sh);
         if (i >= total) break;
-        process_tile<N, PATH, TK>(A, 0, in.items[i].y, L, S, sh);
+        process_tile<N, PATH, TK>(A, 0, in.items[i].y, L, S, sh, blocks);
     }
 }
 
@@ -1830,7 +1827,7 @@ __global__ __launch_bounds__((threads_of<N, PATH>())) void overflow_kernel(JobDe
 // working in its own slice of a global scratch buffer (L2/MALL-resident).
 template <int N, int PATH, int TK = N>
 __global__ __launch_bounds__((threads_of<N, PATH>())) __attribute__((amdgpu_waves_per_eu(N < 3 ? 2 : 1))) void scratch_kernel(
-    JobDesc A, Launch L, ItemList in, long long* scratch, long long band_cap) {
+    JobDesc A, Launch L, ItemList in, long long* scratch, long long band_cap, const unsigned* blocks) {
     extern __shared__ long long LB[];
     __shared__ Shared sh;
     long long* S = scratch + (long long)blockIdx.x * L.lds_cap;
@@ -1839,7 +1836,7 @@ __global__ __launch_bounds__((threads_of<N, PATH>())) __attribute__((amdgpu_wave
         const int i = next_item(in.cursor, sh);
         if (i >= total) break;
         const int lead = in.items[i].y;
-        process_block<N, PATH, TK>(A, lead, L.blocks[A.item_base + lead], L, S, sh, LB, band_cap);
+        process_block<N, PATH, TK>(A, lead, blocks[A.item_base + lead], L, S, sh, LB, band_cap);
     }
 }
 
@@ -1895,7 +1892,7 @@ __global__ __launch_bounds__((threads_of<N, PATH>())) __attribute__((amdgpu_wave
 
 template <int N, int PATH>
 __global__ __launch_bounds__((threads_of<N, PATH>())) void batch_overflow_kernel(const JobDesc* jobs, const GroupHdr* hdr,
-                                                                                 Launch L, ItemList in) {
+                                                                                 Launch L, ItemList in, unsigned* blocks) {
     __shared__ Shared sh;
     group_lists(*hdr, L, &in);
     const int total = (int)min(*in.count, (unsigned)in.cap);
@@ -1903,13 +1900,14 @@ __global__ __launch_bounds__((threads_of<N, PATH>())) void batch_overflow_kernel
         const int i = next_item(in.cursor, sh);
         if (i >= total) break;
         const int2 it = in.items[i];
-        process_tile<N, PATH>(jobs[it.x], it.x, it.y, L, g_lds, sh);
+        process_tile<N, PATH>(jobs[it.x], it.x, it.y, L, g_lds, sh, blocks);
     }
 }
 
 template <int N, int PATH>
 __global__ __launch_bounds__((threads_of<N, PATH>())) __attribute__((amdgpu_waves_per_eu(N < 3 ? 2 : 1))) void batch_scratch_kernel(
-    const JobDesc* jobs, const GroupHdr* hdr, Launch L, ItemList in, long long* scratch, long long band_cap) {
+    const JobDesc* jobs, const GroupHdr* hdr, Launch L, ItemList in, long long* scratch, long long band_cap,
+    const unsigned* blocks) {
     __shared__ Shared sh;
     long long* S = scratch + (long long)blockIdx.x * L.lds_cap;
     group_lists(*hdr, L, &in);
@@ -1919,7 +1917,7 @@ __global__ __launch_bounds__((threads_of<N, PATH>())) __attribute__((amdgpu_wave
         if (i >= total) break;
         const int2 it = in.items[i];
         const JobDesc A = jobs[it.x];
-        process_block<N, PATH>(A, it.y, L.blocks[A.item_base + it.y], L, S, sh, g_lds, band_cap);
+        process_block<N, PATH>(A, it.y, blocks[A.item_base + it.y], L, S, sh, g_lds, band_cap);
     }
 }
 
@@ -2429,6 +2427,7 @@ struct Tiers {
     Launch L1, L2, L3;
     ItemList inA, inB;
     long long* scratch = nullptr;
+    unsigned* blocks = nullptr;  // tier 3's block words (null without tier 3)
     int grid2 = 1, grid3 = 1;
 };
 
@@ -2460,9 +2459,7 @@ Tiers make_tiers_at(const bsf_ctx* c, const Plan& p, unsigned* ctr, int2* la, in
         t.inB = ItemList{ctr + 3, lb, ctr + 4, (int)items};
         t.grid3 = (int)(grid3 > 0 ? grid3 : bsf_plan::grid3_of(c->limits(), items));
         t.scratch = scratch;
-        t.L1.blocks = t.L2.blocks = t.L3.blocks = blocks;
-        t.L1.blk_role = 1;
-        t.L2.blk_role = 2;
+        t.blocks = blocks;
     }
     return t;
 }
@@ -2472,6 +2469,13 @@ Tiers make_tiers(const bsf_ctx* c, const Plan& p, char* work, const WorkLayout& 
     if (!work) return make_tiers_at(c, p, nullptr, nullptr, nullptr, nullptr, nullptr, items, order);  // tier 1 only
     return make_tiers_at(c, p, (unsigned*)work, (int2*)(work + w.lists_off), (int2*)(work + w.listb_off),
                          (unsigned*)(work + w.blocks_off), (long long*)(work + w.scratch_off), items, order, grid3);
+}
+
+// Tier 3's block words start at zero in every call (a kernel: the words may sit in a
+// captured graph, where memset nodes are avoided).
+void clear_blocks(const Tiers& t, long long items, hipStream_t st) {
+    if (t.blocks)
+        hipLaunchKernelGGL(clear_words, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, st, t.blocks, (int)items);
 }
 
 template <int N, int PATH, int TK = N>
@@ -2487,10 +2491,10 @@ hipError_t launch_single(const JobDesc& A, const Plan& p, const Tiers& t, int ti
     hipLaunchKernelGGL((tile_kernel<N, PATH, TK>), dim3(tiles), dim3(threads_of<N, PATH>()), (size_t)p.t1 * 8, st, A, t.L1);
     if (p.use2)
         hipLaunchKernelGGL((overflow_kernel<N, PATH, TK>), dim3(t.grid2), dim3(threads_of<N, PATH>()), (size_t)p.t2 * 8, st, A,
-                           t.L2, t.inA);
+                           t.L2, t.inA, t.blocks);
     if (p.use3)
         hipLaunchKernelGGL((scratch_kernel<N, PATH, TK>), dim3(t.grid3), dim3(threads_of<N, PATH>()), (size_t)p.band * 8, st, A,
-                           t.L3, t.inB, t.scratch, p.band);
+                           t.L3, t.inB, t.scratch, p.band, t.blocks);
     return hipGetLastError();
 }
 
@@ -2683,10 +2687,10 @@ hipError_t launch_batch_group(const bsf_ctx* c, const JobDesc* djobs, const Grou
                        t.L1, ctr + 2);
     if (p.use2)
         hipLaunchKernelGGL((batch_overflow_kernel<N, PATH>), dim3(t.grid2), dim3(threads_of<N, PATH>()), (size_t)p.t2 * 8, st,
-                           djobs, hdr, t.L2, t.inA);
+                           djobs, hdr, t.L2, t.inA, t.blocks);
     if (p.use3)
         hipLaunchKernelGGL((batch_scratch_kernel<N, PATH>), dim3(t.grid3), dim3(threads_of<N, PATH>()), (size_t)p.band * 8, st,
-                           djobs, hdr, t.L3, t.inB, t.scratch, p.band);
+                           djobs, hdr, t.L3, t.inB, t.scratch, p.band, t.blocks);
     return hipGetLastError();
 }
 
@@ -2957,6 +2961,7 @@ bsf_status bsf_filter_model(bsf_ctx* c, const bsf_job* j, int model, void* strea
         if (s != BSF_OK) return s;
         t = make_tiers(c, p, (char*)c->slot[slot].dev, w, tiles, j->order);
         hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, st, (unsigned*)c->slot[slot].dev);
+        clear_blocks(t, tiles, st);
     } else {
         t = make_tiers(c, p, nullptr, WorkLayout{}, tiles, j->order);
     }
@@ -2993,6 +2998,7 @@ bsf_status bsf_filter_noalloc(bsf_ctx* c, const bsf_job* j, void* stream) {
         t = make_tiers(c, p, (char*)c->noalloc, w, tiles, j->order, f.grid3);
         // the counters must start at zero: a kernel clears them (the area keeps the last call's contents)
         hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, st, (unsigned*)c->noalloc);
+        clear_blocks(t, tiles, st);
     } else {
         t = make_tiers(c, p, nullptr, WorkLayout{}, tiles, j->order);
     }
@@ -3087,6 +3093,11 @@ bsf_status bsf_filter_batched(bsf_ctx* c, const bsf_job* jobs, int njobs, void* 
                        st);
     if (e != hipSuccess) return hip_fail(c, e, "uploading the batch descriptors");
     hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, st, (unsigned*)work);
+    bool any3 = false;
+    for (const Group& g : groups) any3 = any3 || g.p.use3;
+    if (any3)  // tier 3's block words
+        hipLaunchKernelGGL(clear_words, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
+                           (unsigned*)(work + w.blocks_off), (int)total);
     for (size_t gi = 0; gi < groups.size(); ++gi) {
         const Group& g = groups[gi];
         unsigned* ctr = (unsigned*)work + 8 * g.v;  // each variant appears in one group
@@ -3175,6 +3186,11 @@ bsf_status bsf_batch_plan_create(bsf_ctx* c, int max_jobs, long long max_tiles, 
                                        hipMemcpyHostToDevice, cs);
         hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, cs, (unsigned*)work);
         hipLaunchKernelGGL(clear_words, dim3((max_jobs + 255) / 256), dim3(256), 0, cs, derr, max_jobs);
+        bool any3 = false;
+        for (int v = 0; v < kVariants; ++v) any3 = any3 || pv[v].use3;
+        if (any3)  // tier 3's block words
+            hipLaunchKernelGGL(clear_words, dim3((unsigned)((max_tiles + 255) / 256)), dim3(256), 0, cs,
+                               (unsigned*)(work + w.blocks_off), (int)max_tiles);
         const GroupHdr* dhdr = (const GroupHdr*)(work + w.jobs_off);
         const JobDesc* djobs = (const JobDesc*)(work + w.jobs_off) + kHdrSlots;
         for (int v = 0; v < kVariants && le == hipSuccess; ++v) {
