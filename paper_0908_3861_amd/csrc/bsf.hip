@@ -1560,6 +1560,7 @@ __device__ __forceinline__ void process_block(const JobDesc A, int lead, unsigne
     // the window, the last those below, which the taps then flag).  Consecutive bands
     // overlap by the stencil's height.  A window too wide for bands of 8 owned rows is read
     // where it lies, as one band.
+    static_assert(PATH != BSF_PATH_F64 || 8 * NT <= bsf_plan::kBandTail, "the band tail holds the digit sums");
     const long long band_elems = PATH == BSF_PATH_F64 ? band_cap - 8 * NT : band_cap;
     auto over_bands = [&](auto&& body) {
         constexpr int span = stencil_hi<TK>() - stencil_lo<TK>();

@@ -67,10 +67,15 @@ inline bool launch_fits(const Limits& L, int order, long long dyn_bytes) {
     return dyn_bytes >= 0 && dyn_bytes + L.lds_static[order] <= L.lds_max;
 }
 
-// Every LDS launch of a plan fits (tier 3's dynamic LDS is its band buffer).
+// Elements of tier 3's band buffer that the float64 path reserves for its pixels' digit sums
+// (4 tiles x 2 doubles x 256 threads); the buffer must hold more than these.
+constexpr long long kBandTail = 8 * 256;
+
+// Every LDS launch of a plan fits (tier 3's dynamic LDS is its band buffer, which must hold
+// more than its tail).
 inline bool plan_fits(const Limits& L, const Plan& p, int order) {
     return launch_fits(L, order, p.t1 * 8) && (!p.use2 || launch_fits(L, order, p.t2 * 8)) &&
-           (!p.use3 || launch_fits(L, order, p.band * 8));
+           (!p.use3 || (launch_fits(L, order, p.band * 8) && p.band > kBandTail));
 }
 
 // Workgroups of a window size that fit one CU's LDS.

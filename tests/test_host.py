@@ -192,6 +192,8 @@ int main() {
         CHECK(q.use3 && plan_fits(L, q, 2));
         q.band = full_cap(L, 2) + 1;
         CHECK(!plan_fits(L, q, 2));
+        q.band = kBandTail;  // no room beside the float64 path's digit sums
+        CHECK(!plan_fits(L, q, 2));
     }
     // work area of a fixed buffer: lists, then at least one tier-3 slice
     {
