@@ -214,16 +214,20 @@ __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? l
 
 // Stage 1 on the window (eq. RS steps (1)-(4), n folds each, fused into one pass per
 // direction).  cen: anchor every line at the tile centre (cc, rc) instead of at its start.
+// rows_done: step (1) has already run (load_rows_runsum).
 template <int NF, bool CHECK, int B, typename V>
-__device__ void preintegrate_window_n(V* S, const Geo& g, bool cen, int cc, int rc, unsigned& ovf) {
+__device__ void preintegrate_window_n(V* S, const Geo& g, bool cen, int cc, int rc, unsigned& ovf,
+                                      bool rows_done = false) {
     const int tid = threadIdx.x, nt = blockDim.x;
     const int W = g.wq, H = g.hq, Wt = W + H - 1;
     const int parts = cen ? 2 : 1;
-    for (int it = tid; it < H * parts; it += nt) {  // (1) along (1,0): rows
-        const int part = it >= H, r = it - part * H;
-        scan_line_n<NF, CHECK, 0, 1, B>(S, g, r, 0, Wt - r, cen ? clampi(cc, 0, Wt - r - 1) : -1, part, ovf);
+    if (!rows_done) {
+        for (int it = tid; it < H * parts; it += nt) {  // (1) along (1,0): rows
+            const int part = it >= H, r = it - part * H;
+            scan_line_n<NF, CHECK, 0, 1, B>(S, g, r, 0, Wt - r, cen ? clampi(cc, 0, Wt - r - 1) : -1, part, ovf);
+        }
+        __syncthreads();
     }
-    __syncthreads();
     const int nd = Wt + H - 1;
     for (int it = tid; it < nd * parts; it += nt) {  // (2) along (1,1): diagonals c - r = e
         const int part = it >= nd, i = it - part * nd;
@@ -272,6 +276,125 @@ __device__ void preintegrate_window(V* S, const Geo& g, bool cen, int cc, int rc
     if constexpr (std::is_integral<V>::value) check = stage1_needs_check<N>(g, bits);
     if (check) preintegrate_window_n<N, true, B>(S, g, cen, cc, rc, ovf);
     else preintegrate_window_n<N, false, B>(S, g, cen, cc, rc, ovf);
+}
+
+// A 64-bit value moved across the wave's lanes by a DPP control; lanes without a source, or
+// in rows outside ROWMASK, receive zero.
+template <int CTRL, int ROWMASK, typename V>
+__device__ __forceinline__ V dpp64(V v) {
+    static_assert(sizeof(V) == 8, "64-bit lanes");
+    unsigned long long b;
+    __builtin_memcpy(&b, &v, 8);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, ROWMASK, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, ROWMASK, 0xf, true);
+    b = ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+    V r;
+    __builtin_memcpy(&r, &b, 8);
+    return r;
+}
+template <typename V>
+__device__ __forceinline__ V lane64(V v, int l) {
+    unsigned long long b;
+    __builtin_memcpy(&b, &v, 8);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+    b = ((unsigned long long)hi << 32) | lo;
+    V r;
+    __builtin_memcpy(&r, &b, 8);
+    return r;
+}
+// Inclusive prefix sum over the wave's 64 lanes: shifts by 1, 2, 4, 8 within each row of 16
+// lanes, then the broadcasts of lanes 15 and 31 into the rows above.
+template <typename V>
+__device__ __forceinline__ V wave_incl_scan(V v) {
+    v += dpp64<0x111, 0xf>(v);  // row_shr:1
+    v += dpp64<0x112, 0xf>(v);  // row_shr:2
+    v += dpp64<0x114, 0xf>(v);  // row_shr:4
+    v += dpp64<0x118, 0xf>(v);  // row_shr:8
+    v += dpp64<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp64<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
+// The NF-fold running sums y_k[j] = sum_{i <= j} y_{k-1}[i], y_0 = x, of a sequence x(0 ..
+// len-1), by one wave: lane l takes the run of K elements 64 K c + K l .. + K - 1 of chunk c,
+// sums it from zero states, and learns its run's initial states from an exclusive scan, over
+// the wave, of the runs' end states (fold k's end state after a run of K from initial states
+// s_1..s_k is s_k + sum_{m=1}^{k-1} C(K-1+m, m) s_{k-m} plus the run's own sum from zero,
+// so fold by fold the scans are plain sums); the last lane's end states carry into the next
+// chunk.  put(j, y_NF[j]).  Integer sums are exact (modulo 2^64); float64 sums round in
+// another order than a sequential walk.
+template <int NF, int K, typename V, typename X, typename Put>
+__device__ __forceinline__ void wave_runsum(int len, X x, Put put) {
+    const int lane = threadIdx.x & 63;
+    V carry[NF];
+#pragma unroll
+    for (int k = 0; k < NF; ++k) carry[k] = 0;
+    for (int j0 = 0; j0 < len; j0 += 64 * K) {
+        const int jb = j0 + lane * K;
+        V v[K];
+#pragma unroll
+        for (int i = 0; i < K; ++i) v[i] = jb + i < len ? x(jb + i) : V(0);
+        V l[NF][K];  // the run's own sums, from zero states
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            l[0][i] = i ? l[0][i - 1] + v[i] : v[i];
+#pragma unroll
+            for (int k = 1; k < NF; ++k) l[k][i] = i ? l[k][i - 1] + l[k - 1][i] : l[k - 1][i];
+        }
+        V c[NF];  // the run's initial states
+#pragma unroll
+        for (int k = 0; k < NF; ++k) {
+            V z = l[k][K - 1];
+            long long bc = 1;  // C(K-1+m, m)
+#pragma unroll
+            for (int m = 1; m <= k; ++m) {
+                bc = bc * (K - 1 + m) / m;
+                z += (V)bc * c[k - m];
+            }
+            const V inc = wave_incl_scan(z);
+            c[k] = carry[k] + dpp64<0x138, 0xf>(inc);  // wave_shr:1, lane 0 receives zero
+            carry[k] += lane64(inc, 63);
+        }
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            if (jb + i >= len) break;
+            V y = l[NF - 1][i];
+            long long bc = 1;  // C(i+m, m)
+#pragma unroll
+            for (int m = 0; m < NF; ++m) {
+                if (m) bc = bc * (i + m) / m;
+                y += (V)bc * c[NF - 1 - m];
+            }
+            put(jb + i, y);
+        }
+    }
+}
+
+// The window's box loaded from the input and step (1) of stage 1 run along its rows in the
+// same pass (load(r, c) gives box element (r, c); the extension triangle is zero), one wave
+// per row, each row anchored at column clamp(cc) as scan_line_n anchors it: forward from the
+// anchor, the n-fold sums of x[t+1], x[t+2], ...; backward, the n-fold sums of x[t], x[t-1],
+// ... land n columns to the left of their last term, negated for odd n, and the n columns
+// t-n+1 .. t hold zero.  Every element is written once, in runs of K per lane.
+constexpr int kRowRun = 4;  // elements per lane in a run of load_rows_runsum
+
+template <int NF, int K, typename V, typename Load>
+__device__ void load_rows_runsum(V* S, const Geo& g, int cc, Load load) {
+    const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6, lane = threadIdx.x & 63;
+    const int W = g.wq, H = g.hq, Wt = W + H - 1;
+    for (int r = wave; r < H; r += nw) {
+        const int len = Wt - r, t = clampi(cc, 0, len - 1);
+        const int rowbase = r * W, tr = g.qn + r * (H - 1) - ((r * (r - 1)) >> 1) - W;
+        auto at = [&](int c) { return c < W ? rowbase + c : tr + c; };
+        wave_runsum<NF, K, V>(
+            len - t - 1, [&](int j) { return t + 1 + j < W ? load(r, t + 1 + j) : V(0); },
+            [&](int j, V y) { S[at(t + 1 + j)] = y; });
+        wave_runsum<NF, K, V>(
+            max(t - NF + 1, 0), [&](int j) { return load(r, t - j); },
+            [&](int j, V y) { S[at(t - j - NF)] = (NF & 1) ? -y : y; });
+        if (lane < NF && t - lane >= 0) S[at(t - lane)] = 0;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -881,138 +1004,259 @@ __device__ double mesh_f64(const long long* S, int wq, int hq, int mx, int my, f
 // The mesh over a band of the window (windows held in global scratch, evaluated from LDS
 // in bands of rows).  A pixel's taps come in triples (k2, k4, k3) whose three k1 taps
 // share the anchor row; a triple belongs to the band when its stencil's first window row
-// q2 + stencil_lo lies in [own0, own1).  Each lane walks its own triples, skipping the
-// ones of other bands, so that a wave spends one tap evaluation per owned tap of its
-// busiest lane rather than per triple of the band.  The band buffer S holds window rows
-// row0 .. row0 + nrows - 1 at the window's pitch wq.  The tap geometry is mesh_dd's and
-// mesh_f64's, operation for operation; the taps are summed triple by triple, band by band.
-// ---------------------------------------------------------------------------
-template <int N, int SRC, int LOW = Tab<N>::DEG, int K = N>
-__device__ dd mesh_dd_band(const long long* S, int wq, int nrows, int row0, int own0, int own1, int mx, int my,
-                           float4 a, int k2lo, int k2hi, unsigned& bad, double& E) {
+// q2 + stencil_lo lies in [own0, own1).  The band buffer S holds window rows row0 .. row0
+// + nrows - 1 at the window's pitch wq.  The tap geometry is mesh_dd's and mesh_f64's,
+// operation for operation; the taps are summed triple by triple, band by band.
+//
+// The band's triples of a wave's 64 pixels are spread evenly over its lanes.  Each lane
+// lists the triples of its pixel that the band owns (a bit per triple index i = ((k2 -
+// k2lo) (N+1) + k4) (N+1) + k3); a wave scan of the counts numbers the items owner by
+// owner, and the wave evaluates them 64 at a time,
+// lane l taking item base + l: its owner is the last lane whose first item number is at
+// most base + l, its triple the owner's set bit of that rank, its pixel (mx, my, a) read
+// from the owner's lane.  Each owner then adds the values of its items, in item order,
+// from the lanes that evaluated them.  A wave thus spends about (its owned triples) / 64
+// triple evaluations per band instead of its busiest lane's count.  Every lane of the wave
+// calls these with the same band; an inactive pixel owns nothing.
+template <int N, int K, bool DD>
+__device__ __forceinline__ unsigned long long band_owned(int my, float4 a, int k2lo, int k2hi, int own0, int own1) {
+    constexpr int NP = N + 1;
+    constexpr int jl = stencil_lo<K>();
+    constexpr double h = 0.5 * N;
+    const double a3 = a.z;
+    unsigned long long m = 0;
+    int bit = 0;
+    auto own = [&](double d2hi) {
+        const double f2 = Tab<K>::ODD ? rint(d2hi) : floor(d2hi);
+        const int s = my + (int)f2 + jl;
+        if (s >= own0 && s < own1) m |= 1ull << bit;
+        ++bit;
+    };
+    if constexpr (DD) {  // triple_dd's d2
+        const dd isq = {kInvSqrt2Hi, kInvSqrt2Lo};
+        const dd A2 = dd_mul_d(isq, (double)a.y), A4 = dd_mul_d(isq, (double)a.w);
+        const dd T2 = dd_mul_d(dd_add_d(dd_add(A2, A4), a3 - 3.0), h);
+        for (int k2 = k2lo; k2 <= k2hi; ++k2)
+#pragma unroll
+            for (int k4 = 0; k4 < NP; ++k4) {
+                const dd D2 = dd_mul_d(A2, (double)k2), D4 = dd_mul_d(A4, (double)k4);
+                const dd B2 = dd_add(T2, dd_neg(dd_add(D2, D4)));
+#pragma unroll
+                for (int k3 = 0; k3 < NP; ++k3) own(dd_add_d(B2, -(double)k3 * a3).hi);
+            }
+    } else {  // triple_f64's d2
+        const double A2 = (double)a.y * kInvSqrt2Hi, A4 = (double)a.w * kInvSqrt2Hi;
+        const double T2 = h * (A2 + a3 + A4 - 3.0);
+        for (int k2 = k2lo; k2 <= k2hi; ++k2)
+#pragma unroll
+            for (int k4 = 0; k4 < NP; ++k4) {
+                const double B2 = T2 - k2 * A2 - k4 * A4;
+#pragma unroll
+                for (int k3 = 0; k3 < NP; ++k3) own(B2 - k3 * a3);
+            }
+    }
+    return m;
+}
+__device__ __forceinline__ int wave_incl_scan_i(int v) {
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, true);  // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, true);  // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, true);  // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, true);  // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, true);  // row_bcast:15
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, true);  // row_bcast:31
+    return v;
+}
+// Index of the set bit of rank r (r < popcount(m)).
+__device__ __forceinline__ int select_bit(unsigned long long m, int r) {
+    int t = 0;
+#pragma unroll
+    for (int w = 32; w; w >>= 1) {
+        const int low = __popcll(m & ((1ull << w) - 1ull));
+        if (r >= low) {
+            r -= low;
+            m >>= w;
+            t += w;
+        }
+    }
+    return t;
+}
+__device__ __forceinline__ int wave_max_i(int v);
+// The item loop: eval(live, t, mx, my, a) evaluates triple t of the pixel (mx, my, a) into
+// the lane's item value; pull(src, take) then adds lane src's item value to the owner's sums
+// when take holds (called with the same src by the whole wave, j-th item of each owner).
+template <typename Eval, typename Pull>
+__device__ __forceinline__ void spread_items(unsigned long long mask, int mx, int my, float4 a, Eval eval, Pull pull) {
+    const int lane = threadIdx.x & 63;
+    const int cnt = __popcll(mask);
+    const int incl = wave_incl_scan_i(cnt);
+    const int start = incl - cnt;
+    const int total = __builtin_amdgcn_readlane(incl, 63);
+    const unsigned mlo = (unsigned)mask, mhi = (unsigned)(mask >> 32);
+    const int ax = __float_as_int(a.x), ay = __float_as_int(a.y), az = __float_as_int(a.z), aw = __float_as_int(a.w);
+    for (int base = 0; base < total; base += 64) {
+        const int i = base + lane;
+        int o = 0;  // the item's owner
+#pragma unroll
+        for (int step = 32; step; step >>= 1) {
+            const int p = o + step;
+            if (__shfl(start, p) <= i) o = p;
+        }
+        const int rank = i - __shfl(start, o);
+        const unsigned long long mo =
+            ((unsigned long long)(unsigned)__shfl((int)mhi, o) << 32) | (unsigned)__shfl((int)mlo, o);
+        const int omx = __shfl(mx, o), omy = __shfl(my, o);
+        const float4 oa = make_float4(__int_as_float(__shfl(ax, o)), __int_as_float(__shfl(ay, o)),
+                                      __int_as_float(__shfl(az, o)), __int_as_float(__shfl(aw, o)));
+        const bool live = i < total;
+        eval(live, live ? select_bit(mo, rank) : 0, omx, omy, oa);
+        // the owner's items of this round: lanes [j0, j1)
+        const int j0 = max(start, base) - base, j1 = min(incl, base + 64) - base;
+        const int jn = max(j1 - j0, 0);
+        const int jmax = __builtin_amdgcn_readfirstlane(wave_max_i(jn));
+        for (int j = 0; j < jmax; ++j) pull(min(j0 + j, 63), j < jn);
+    }
+}
+
+// The three k1 taps of triple (k2, k4, k3) of a pixel, float64 geometry and sums.
+template <int N, int SRC, int K>
+__device__ __forceinline__ double triple_f64(const long long* S, int wq, int nrows, int row0, int mx, int my,
+                                             float4 a, int k2, int k4, int k3, unsigned& bad) {
+    const double a1 = a.x, a3 = a.z;
+    const double A2 = (double)a.y * kInvSqrt2Hi, A4 = (double)a.w * kInvSqrt2Hi;
+    constexpr double h = 0.5 * N;
+    const double T1 = h * (a1 + A2 - A4 - 1.0);
+    const double T2 = h * (A2 + a3 + A4 - 3.0);
+    const double B2 = T2 - k2 * A2 - k4 * A4;
+    const double d2 = B2 - k3 * a3;
+    const double f2 = Tab<K>::ODD ? rint(d2) : floor(d2);
+    const int c24 = fd_binom<N>(k2) * fd_binom<N>(k4);
+    const double B1 = T1 - k2 * A2 + k4 * A4;
+    const double oc = Tab<K>::ODD ? 0.0 : 0.5;
+    const double u2 = d2 - f2 - oc;
+    double acc = 0.0;
+#pragma unroll
+    for (int k1 = 0; k1 <= N; ++k1) {
+        const int c124 = c24 * fd_binom<N>(k1);
+        const double d1 = B1 - k1 * a1;
+        const double f1 = Tab<K>::ODD ? rint(d1) : floor(d1);
+        const double u1 = d1 - f1 - oc;
+        const Turn t = cell_turn(u1, u2);
+        const double w1 = t.swap ? u2 : u1, w2 = t.swap ? u1 : u2;
+        const double v1 = t.n1 ? -w1 : w1, v2 = t.n2 ? -w2 : w2;
+        const TapFrame<K> fr = tap_frame<K>(mx + (int)f1, my + (int)f2 - row0, t, wq, nrows);
+        if (!fr.lo_ok) {
+            bad = 1;
+            continue;
+        }
+        const double P = interp_f64<K, SRC>(S, fr, v1, v2, bad);
+        const int c = c124 * fd_binom<N>(k3);
+        acc = __fma_rn(((k1 + k2 + k3 + k4) & 1) ? -(double)c : (double)c, P, acc);
+    }
+    return acc;
+}
+// The same in double-double geometry with compensated sums (the split evaluation's
+// bound in E when LOW < DEG).
+template <int N, int SRC, int LOW, int K>
+__device__ __forceinline__ cp triple_dd(const long long* S, int wq, int nrows, int row0, int mx, int my, float4 a,
+                                        int k2, int k4, int k3, unsigned& bad, double& E) {
     const dd isq = {kInvSqrt2Hi, kInvSqrt2Lo};
     const double a1 = a.x, a3 = a.z;
     const dd A2 = dd_mul_d(isq, (double)a.y);
     const dd A4 = dd_mul_d(isq, (double)a.w);
     constexpr double h = 0.5 * N;
-    constexpr int NP = N + 1;
-    constexpr int jl = stencil_lo<K>();
     const dd T1 = dd_mul_d(dd_add_d(dd_add(A2, dd_neg(A4)), a1 - 1.0), h);
     const dd T2 = dd_mul_d(dd_add_d(dd_add(A2, A4), a3 - 3.0), h);
+    const dd D2 = dd_mul_d(A2, (double)k2), D4 = dd_mul_d(A4, (double)k4);
+    const dd B2 = dd_add(T2, dd_neg(dd_add(D2, D4)));
+    const dd d2 = dd_add_d(B2, -(double)k3 * a3);
+    const double f2 = Tab<K>::ODD ? rint(d2.hi) : floor(d2.hi);
+    const int c24 = fd_binom<N>(k2) * fd_binom<N>(k4);
+    const dd B1 = dd_add(T1, dd_add(D4, dd_neg(D2)));
+    const double oc = Tab<K>::ODD ? 0.0 : 0.5;
+    const dd u2 = dd_add_d(d2, -(f2 + oc));
     cp acc = {0.0, 0.0};
-    const int ntrip = (k2hi - k2lo + 1) * NP * NP;
-    int i = 0, cur = -1;  // the lane's next triple; the (k2, k4) pair B2 was formed for
-    dd B2 = {0.0, 0.0};
-    for (;;) {
-        int k2 = 0, k4 = 0, k3 = 0;
-        dd d2 = {0.0, 0.0};
-        double f2 = 0.0;
-        bool found = false;
-        for (; i < ntrip; ++i) {
-            const int p24 = i / NP;
-            k3 = i - p24 * NP;
-            k2 = k2lo + p24 / NP;
-            k4 = p24 - (p24 / NP) * NP;
-            if (p24 != cur) {
-                const dd D2 = dd_mul_d(A2, (double)k2), D4 = dd_mul_d(A4, (double)k4);
-                B2 = dd_add(T2, dd_neg(dd_add(D2, D4)));
-                cur = p24;
-            }
-            d2 = dd_add_d(B2, -(double)k3 * a3);
-            f2 = Tab<K>::ODD ? rint(d2.hi) : floor(d2.hi);
-            const int s = my + (int)f2 + jl;
-            if (s >= own0 && s < own1) {
-                found = true;
-                break;
-            }
+#pragma unroll
+    for (int k1 = 0; k1 <= N; ++k1) {
+        const int c124 = c24 * fd_binom<N>(k1);
+        const dd d1 = dd_add_d(B1, -(double)k1 * a1);
+        const double f1 = Tab<K>::ODD ? rint(d1.hi) : floor(d1.hi);
+        const dd u1 = dd_add_d(d1, -(f1 + oc));
+        const Turn t = cell_turn(u1.hi, u2.hi);
+        const dd v1 = dd_turn(t.swap, t.n1, u1, u2);
+        const dd v2 = dd_turn(t.swap, t.n2, u2, u1);
+        const TapFrame<K> fr = tap_frame<K>(mx + (int)f1, my + (int)f2 - row0, t, wq, nrows);
+        if (!fr.lo_ok) {
+            bad = 1;
+            continue;
         }
-        if (!found) break;
-        ++i;
-        const int c24 = fd_binom<N>(k2) * fd_binom<N>(k4);
-        const dd D2 = dd_mul_d(A2, (double)k2), D4 = dd_mul_d(A4, (double)k4);
-        const dd B1 = dd_add(T1, dd_add(D4, dd_neg(D2)));
-        const double oc = Tab<K>::ODD ? 0.0 : 0.5;
-        const dd u2 = dd_add_d(d2, -(f2 + oc));
-        for (int k1 = 0; k1 <= N; ++k1) {
-            const int c124 = c24 * fd_binom<N>(k1);
-            const dd d1 = dd_add_d(B1, -(double)k1 * a1);
-            const double f1 = Tab<K>::ODD ? rint(d1.hi) : floor(d1.hi);
-            const dd u1 = dd_add_d(d1, -(f1 + oc));
-            const Turn t = cell_turn(u1.hi, u2.hi);
-            const dd v1 = dd_turn(t.swap, t.n1, u1, u2);
-            const dd v2 = dd_turn(t.swap, t.n2, u2, u1);
-            const TapFrame<K> fr = tap_frame<K>(mx + (int)f1, my + (int)f2 - row0, t, wq, nrows);
-            if (!fr.lo_ok) {
-                bad = 1;
-                continue;
-            }
-            double Bk = 0.0;
-            const cp P = interp_dd<K, SRC, LOW>(S, fr, v1, v2, Bk, bad);
-            const int c = c124 * fd_binom<N>(k3);
-            const double cs = ((k1 + k2 + k3 + k4) & 1) ? -(double)c : (double)c;
-            acc = cp_axpy(acc, cs, P);
-            if constexpr (LOW < Tab<K>::DEG) E = __fma_rn((double)c, Bk, E);
-        }
-    }
-    return fast_two_sum(acc.s, acc.c);
-}
-
-template <int N, int SRC, int K = N>
-__device__ double mesh_f64_band(const long long* S, int wq, int nrows, int row0, int own0, int own1, int mx, int my,
-                                float4 a, int k2lo, int k2hi, unsigned& bad) {
-    const double a1 = a.x, a3 = a.z;
-    const double A2 = (double)a.y * kInvSqrt2Hi, A4 = (double)a.w * kInvSqrt2Hi;
-    constexpr double h = 0.5 * N;
-    constexpr int NP = N + 1;
-    constexpr int jl = stencil_lo<K>();
-    const double T1 = h * (a1 + A2 - A4 - 1.0);
-    const double T2 = h * (A2 + a3 + A4 - 3.0);
-    double acc = 0.0;
-    const int ntrip = (k2hi - k2lo + 1) * NP * NP;
-    int i = 0;
-    for (;;) {
-        int k2 = 0, k4 = 0, k3 = 0;
-        double d2 = 0.0, f2 = 0.0;
-        bool found = false;
-        for (; i < ntrip; ++i) {
-            const int p24 = i / NP;
-            k3 = i - p24 * NP;
-            k2 = k2lo + p24 / NP;
-            k4 = p24 - (p24 / NP) * NP;
-            const double B2 = T2 - k2 * A2 - k4 * A4;
-            d2 = B2 - k3 * a3;
-            f2 = Tab<K>::ODD ? rint(d2) : floor(d2);
-            const int s = my + (int)f2 + jl;
-            if (s >= own0 && s < own1) {
-                found = true;
-                break;
-            }
-        }
-        if (!found) break;
-        ++i;
-        const int c24 = fd_binom<N>(k2) * fd_binom<N>(k4);
-        const double B1 = T1 - k2 * A2 + k4 * A4;
-        const double oc = Tab<K>::ODD ? 0.0 : 0.5;
-        const double u2 = d2 - f2 - oc;
-        for (int k1 = 0; k1 <= N; ++k1) {
-            const int c124 = c24 * fd_binom<N>(k1);
-            const double d1 = B1 - k1 * a1;
-            const double f1 = Tab<K>::ODD ? rint(d1) : floor(d1);
-            const double u1 = d1 - f1 - oc;
-            const Turn t = cell_turn(u1, u2);
-            const double w1 = t.swap ? u2 : u1, w2 = t.swap ? u1 : u2;
-            const double v1 = t.n1 ? -w1 : w1, v2 = t.n2 ? -w2 : w2;
-            const TapFrame<K> fr = tap_frame<K>(mx + (int)f1, my + (int)f2 - row0, t, wq, nrows);
-            if (!fr.lo_ok) {
-                bad = 1;
-                continue;
-            }
-            const double P = interp_f64<K, SRC>(S, fr, v1, v2, bad);
-            const int c = c124 * fd_binom<N>(k3);
-            acc = __fma_rn(((k1 + k2 + k3 + k4) & 1) ? -(double)c : (double)c, P, acc);
-        }
+        double Bk = 0.0;
+        const cp P = interp_dd<K, SRC, LOW>(S, fr, v1, v2, Bk, bad);
+        const int c = c124 * fd_binom<N>(k3);
+        const double cs = ((k1 + k2 + k3 + k4) & 1) ? -(double)c : (double)c;
+        acc = cp_axpy(acc, cs, P);
+        if constexpr (LOW < Tab<K>::DEG) E = __fma_rn((double)c, Bk, E);
     }
     return acc;
+}
+
+// A band's float64 mesh sum of the lane's pixel (float32-output path).
+template <int N, int SRC, int K = N>
+__device__ double mesh_f64_band_even(const long long* S, int wq, int nrows, int row0, int own0, int own1, int mx,
+                                     int my, float4 a, bool act, int k2lo, int k2hi, unsigned& bad) {
+    constexpr int NP = N + 1;
+    const unsigned long long mask = act ? band_owned<N, K, false>(my, a, k2lo, k2hi, own0, own1) : 0ull;
+    double acc = 0.0, v = 0.0;
+    unsigned vb = 0;
+    spread_items(
+        mask, mx, my, a,
+        [&](bool live, int t, int omx, int omy, float4 oa) {
+            v = 0.0;
+            vb = 0;
+            if (live)
+                v = triple_f64<N, SRC, K>(S, wq, nrows, row0, omx, omy, oa, k2lo + t / (NP * NP), (t / NP) % NP,
+                                          t % NP, vb);
+        },
+        [&](int src, bool take) {
+            const double x = __shfl(v, src);
+            const unsigned xb = (unsigned)__shfl((int)vb, src);
+            if (take) {
+                acc += x;
+                bad |= xb;
+            }
+        });
+    return acc;
+}
+// A band's double-double mesh sum of the lane's pixel, and its split bound in E.
+template <int N, int SRC, int LOW = Tab<N>::DEG, int K = N>
+__device__ dd mesh_dd_band_even(const long long* S, int wq, int nrows, int row0, int own0, int own1, int mx, int my,
+                                float4 a, bool act, int k2lo, int k2hi, unsigned& bad, double& E) {
+    constexpr int NP = N + 1;
+    const unsigned long long mask = act ? band_owned<N, K, true>(my, a, k2lo, k2hi, own0, own1) : 0ull;
+    cp acc = {0.0, 0.0}, v = {0.0, 0.0};
+    double ve = 0.0;
+    unsigned vb = 0;
+    spread_items(
+        mask, mx, my, a,
+        [&](bool live, int t, int omx, int omy, float4 oa) {
+            v = {0.0, 0.0};
+            ve = 0.0;
+            vb = 0;
+            if (live)
+                v = triple_dd<N, SRC, LOW, K>(S, wq, nrows, row0, omx, omy, oa, k2lo + t / (NP * NP), (t / NP) % NP,
+                                              t % NP, vb, ve);
+        },
+        [&](int src, bool take) {
+            const cp x = {__shfl(v.s, src), __shfl(v.c, src)};
+            const double xe = __shfl(ve, src);
+            const unsigned xb = (unsigned)__shfl((int)vb, src);
+            if (take) {
+                const dd t = two_sum(acc.s, x.s);
+                acc = {t.hi, acc.c + (t.lo + x.c)};
+                E += xe;
+                bad |= xb;
+            }
+        });
+    return fast_two_sum(acc.s, acc.c);
 }
 
 template <int N, int K = N>
@@ -1458,9 +1702,11 @@ __device__ __forceinline__ void process_tile(const JobDesc A, int job, int tile,
 // windows exceed any workgroup's LDS, filtered from one restart window over their common
 // extent, pre-integrated in S, a slice of global scratch: stage 1 runs once for up to four
 // tiles (the window of the extent is little larger than one tile's, the reach dominating
-// both).  The mesh reads the window from LB, band_cap elements of LDS, in bands of rows
-// (mesh_dd_band, mesh_f64_band); the float64 path keeps each pixel's sums over the digit
-// passes in LB's last 8 NT doubles.  Otherwise as process_tile.
+// both).  The float32-output path loads the window and runs the row step of stage 1 in one
+// pass (load_rows_runsum).  The mesh reads the window from LB, band_cap elements of LDS,
+// in bands of rows, each band's triples spread evenly over the wave (mesh_dd_band_even,
+// mesh_f64_band_even); the float64 path keeps each pixel's sums over the digit passes in
+// LB's last 8 NT doubles.  Otherwise as process_tile.
 template <int N, int PATH, int TK = N>
 __device__ __forceinline__ void process_block(const JobDesc A, int lead, unsigned mask, const Launch L, long long* S,
                                               Shared& sh_, long long* LB, long long band_cap) {
@@ -1587,14 +1833,11 @@ __device__ __forceinline__ void process_block(const JobDesc A, int lead, unsigne
         double* Sd = reinterpret_cast<double*>(S);
         with_dtype(A.in_dtype, [&](auto dt) {
             constexpr int DT = decltype(dt)::value;
-            load_box<double>(g, tid, NT, [&](int r, int c) { return sample_at<DT>(A, w.x0 + c, w.y0 + r); },
-                             [&](int i, double v) { Sd[i] = v; });
+            load_rows_runsum<N, kRowRun>(Sd, g, cc, [&](int r, int c) { return sample_at<DT>(A, w.x0 + c, w.y0 + r); });
         });
-        for (int i = tid; i < ntri; i += NT) Sd[g.qn + i] = 0.0;
         __syncthreads();
         unsigned unused = 0;
-        preintegrate_window<N>(Sd, g, true, cc, rc, 0, unused);
-        __syncthreads();
+        preintegrate_window_n<N, false, 8>(Sd, g, true, cc, rc, unused, true);
         for (int s = 0; s < 4; ++s) {
             if (!((mask >> s) & 1u)) continue;
             const Px q = pixel_of(s);
@@ -1602,8 +1845,8 @@ __device__ __forceinline__ void process_block(const JobDesc A, int lead, unsigne
             unsigned bad = 0;
             dd m = {0.0, 0.0};
             over_bands([&](const long long* src, int nrows, int row0, int own0, int own1) {
-                if (q.valid)
-                    m.hi += mesh_f64_band<N, SRC_DBL, TK>(src, g.wq, nrows, row0, own0, own1, mx, my, q.a, k2lo, k2hi, bad);
+                m.hi += mesh_f64_band_even<N, SRC_DBL, TK>(src, g.wq, nrows, row0, own0, own1, mx, my, q.a, q.valid,
+                                                            k2lo, k2hi, bad);
             });
             combine_halves<SPLIT>(m, bad);
             if (!q.inside || half) continue;
@@ -1708,19 +1951,18 @@ __device__ __forceinline__ void process_block(const JobDesc A, int lead, unsigne
                 dd m = {0.0, 0.0};
                 double E = 0.0;
                 over_bands([&](const long long* src, int nrows, int row0, int own0, int own1) {
-                    if (!act) return;
                     dd part;
                     if (try_split)
-                        part = fast ? mesh_dd_band<N, SRC_DBL, LOW, TK>(src, g.wq, nrows, row0, own0, own1, mx, my, q.a,
-                                                                        k2lo, k2hi, bad, E)
-                                    : mesh_dd_band<N, SRC_INT, LOW, TK>(src, g.wq, nrows, row0, own0, own1, mx, my, q.a,
-                                                                        k2lo, k2hi, bad, E);
+                        part = fast ? mesh_dd_band_even<N, SRC_DBL, LOW, TK>(src, g.wq, nrows, row0, own0, own1, mx, my,
+                                                                             q.a, act, k2lo, k2hi, bad, E)
+                                    : mesh_dd_band_even<N, SRC_INT, LOW, TK>(src, g.wq, nrows, row0, own0, own1, mx, my,
+                                                                             q.a, act, k2lo, k2hi, bad, E);
                     else
-                        part = fast ? mesh_dd_band<N, SRC_DBL, DEG, TK>(src, g.wq, nrows, row0, own0, own1, mx, my, q.a,
-                                                                        k2lo, k2hi, bad, E)
-                                    : mesh_dd_band<N, SRC_INT, DEG, TK>(src, g.wq, nrows, row0, own0, own1, mx, my, q.a,
-                                                                        k2lo, k2hi, bad, E);
-                    m = dd_add(m, part);
+                        part = fast ? mesh_dd_band_even<N, SRC_DBL, DEG, TK>(src, g.wq, nrows, row0, own0, own1, mx, my,
+                                                                             q.a, act, k2lo, k2hi, bad, E)
+                                    : mesh_dd_band_even<N, SRC_INT, DEG, TK>(src, g.wq, nrows, row0, own0, own1, mx, my,
+                                                                             q.a, act, k2lo, k2hi, bad, E);
+                    if (act) m = dd_add(m, part);
                 });
                 // the split evaluation's bound (see process_tile): too large, evaluated again compensated
                 tried = act && try_split;
@@ -1728,13 +1970,12 @@ __device__ __forceinline__ void process_block(const JobDesc A, int lead, unsigne
                 if (__syncthreads_or(redo)) {
                     dd m2 = {0.0, 0.0};
                     over_bands([&](const long long* src, int nrows, int row0, int own0, int own1) {
-                        if (!redo) return;
                         const dd part =
-                            fast ? mesh_dd_band<N, SRC_DBL, DEG, TK>(src, g.wq, nrows, row0, own0, own1, mx, my, q.a, k2lo,
-                                                                     k2hi, bad, E)
-                                 : mesh_dd_band<N, SRC_INT, DEG, TK>(src, g.wq, nrows, row0, own0, own1, mx, my, q.a, k2lo,
-                                                                     k2hi, bad, E);
-                        m2 = dd_add(m2, part);
+                            fast ? mesh_dd_band_even<N, SRC_DBL, DEG, TK>(src, g.wq, nrows, row0, own0, own1, mx, my, q.a,
+                                                                          redo, k2lo, k2hi, bad, E)
+                                 : mesh_dd_band_even<N, SRC_INT, DEG, TK>(src, g.wq, nrows, row0, own0, own1, mx, my, q.a,
+                                                                          redo, k2lo, k2hi, bad, E);
+                        if (redo) m2 = dd_add(m2, part);
                     });
                     if (redo) m = m2;
                 }
