@@ -472,11 +472,60 @@ __device__ __forceinline__ cp join_parts(const double* g) {
 // 2^exact_bits<N>() and were converted in place to doubles; one exact part suffices.
 constexpr int SRC_INT = 0, SRC_DBL = 1;
 
+// How the coefficient sums read the window at the LDS offset of a stencil point.
+// PlainRead: the value there.
+struct PlainRead {
+    const long long* S;
+    __device__ __forceinline__ long long i64(int o) const { return S[o]; }
+    __device__ __forceinline__ double dbl(int o) const { return reinterpret_cast<const double*>(S)[o]; }
+};
+// LatRead (integer a1 and a3): the (n+1)^2 taps (k1, k3) of one pair (k2, k4) then share
+// their cell -- their anchors differ by (k1 a1, k3 a3), their offset u and quarter turn
+// agree -- so the sum of their interpolants is one interpolant of the combined window
+//   h[o] = sum_{k1,k3} (-1)^(k1+k3) C(n,k1) C(n,k3) g[o - k1 a1 - k3 a3 wq]
+// (the finite-difference weights of eq. FD along r1 and r3).  Integer windows combine in
+// wrapping int64, exact whenever |h| < 2^63; float64 windows exactly while the values
+// stay below 2^53.
+template <int N>
+struct LatRead {
+    const long long* S;
+    int d1, d3;  // a1 and a3 wq: the offsets of one step of k1 and of k3
+    static constexpr long long w(int k) { return (k == 0 || k == N) ? 1 : N; }  // C(n, k), n <= 3
+    __device__ __forceinline__ long long i64(int o) const {
+        unsigned long long h = 0;
+#pragma unroll
+        for (int k3 = 0; k3 <= N; ++k3) {
+            unsigned long long r = 0;
+#pragma unroll
+            for (int k1 = 0; k1 <= N; ++k1) {
+                const unsigned long long v = (unsigned long long)S[o - k1 * d1 - k3 * d3] * (unsigned long long)w(k1);
+                r = (k1 & 1) ? r - v : r + v;
+            }
+            r *= (unsigned long long)w(k3);
+            h = (k3 & 1) ? h - r : h + r;
+        }
+        return (long long)h;
+    }
+    __device__ __forceinline__ double dbl(int o) const {
+        const double* Sd = reinterpret_cast<const double*>(S);
+        double h = 0.0;
+#pragma unroll
+        for (int k3 = 0; k3 <= N; ++k3) {
+            double r = 0.0;
+#pragma unroll
+            for (int k1 = 0; k1 <= N; ++k1)
+                r = __fma_rn((k1 & 1) ? -(double)w(k1) : (double)w(k1), Sd[o - k1 * d1 - k3 * d3], r);
+            h = __fma_rn((k3 & 1) ? -(double)w(k3) : (double)w(k3), r, h);
+        }
+        return h;
+    }
+};
+
 // G_alpha = sum_j NUM[j][alpha] g[q + R j] for the monomials u1^a u2^b with ALO <= a <= AHI,
 // in PARTS exact partial sums.  Mirror pairs (j, j') enter once, as g + g' for even b
 // and g - g' for odd b.
-template <int N, int SRC, int PARTS, int SHIFT, int ALO, int AHI>
-__device__ __forceinline__ void accumulate_chunk(const long long* S, const TapFrame<N>& fr,
+template <int N, int SRC, int PARTS, int SHIFT, int ALO, int AHI, typename RD>
+__device__ __forceinline__ void accumulate_chunk(const RD& rd, const TapFrame<N>& fr,
                                                  double (&G)[PARTS][mono_index<Tab<N>::DEG>(AHI, Tab<N>::DEG - AHI) -
                                                                     mono_index<Tab<N>::DEG>(ALO, 0) + 1],
                                                  unsigned& bad) {
@@ -484,7 +533,6 @@ __device__ __forceinline__ void accumulate_chunk(const long long* S, const TapFr
     constexpr int DEG = T::DEG;
     constexpr int M0 = mono_index<DEG>(ALO, 0);
     constexpr int CM = mono_index<DEG>(AHI, DEG - AHI) - M0 + 1;
-    const double* Sd = reinterpret_cast<const double*>(S);
 #pragma unroll
     for (int p = 0; p < PARTS; ++p)
 #pragma unroll
@@ -497,20 +545,20 @@ __device__ __forceinline__ void accumulate_chunk(const long long* S, const TapFr
         const int o2 = fr.base + T::jx(jm) * fr.s1 + T::jy(jm) * fr.s2;
         double x[PARTS], xs[PARTS], xd[PARTS];
         if constexpr (SRC == SRC_DBL) {
-            const double g1 = Sd[o1];
+            const double g1 = rd.dbl(o1);
             if (jm == j) {
                 x[0] = g1;
             } else {
-                const double g2 = Sd[o2];
+                const double g2 = rd.dbl(o2);
                 xs[0] = g1 + g2;  // exact: |g| < 2^exact_bits <= 2^50
                 xd[0] = g1 - g2;
             }
         } else {
-            const long long g1 = S[o1];
+            const long long g1 = rd.i64(o1);
             if (jm == j) {
                 split_int<PARTS, SHIFT>(g1, x);
             } else {
-                const long long g2 = S[o2];
+                const long long g2 = rd.i64(o2);
                 split_int<PARTS, SHIFT>(add_ovf(g1, g2, bad), xs);
                 split_int<PARTS, SHIFT>(sub_ovf(g1, g2, bad), xd);
             }
@@ -625,14 +673,13 @@ __device__ __forceinline__ const __attribute__((address_space(4))) typename Rep3
         ((unsigned long long)hi << 32) | lo);
 }
 
-template <int GRP, int SRC, int PARTS, int SHIFT, int M0, int CM>
-__device__ __forceinline__ void accumulate_group3(const long long* S, const TapFrame<3>& fr, double (&G)[PARTS][CM],
+template <int GRP, int SRC, int PARTS, int SHIFT, int M0, int CM, typename RD>
+__device__ __forceinline__ void accumulate_group3(const RD& rd, const TapFrame<3>& fr, double (&G)[PARTS][CM],
                                                   unsigned& bad) {
     using T = Tab<3>;
     constexpr int NC = Rep3Compact<GRP>::NC;
     constexpr Rep3ColMap<GRP> cols{};
     const auto* pts = rep3_points<GRP>();
-    const double* Sd = reinterpret_cast<const double*>(S);
 #pragma unroll 1
     for (int k = 0; k < bsf_tables::kRep3GroupSize[GRP]; ++k) {
         const auto& q = pts[k];
@@ -642,11 +689,11 @@ __device__ __forceinline__ void accumulate_group3(const long long* S, const TapF
         const int o2 = fr.base + __mul24(q.mjx, fr.s1) + __mul24(q.mjy, fr.s2);
         double xs[PARTS], xd[PARTS];
         if constexpr (SRC == SRC_DBL) {
-            const double g1 = Sd[o1], g2 = q.self ? 0.0 : Sd[o2];
+            const double g1 = rd.dbl(o1), g2 = q.self ? 0.0 : rd.dbl(o2);
             xs[0] = g1 + g2;  // exact when the window values are below 2^exact_bits
             xd[0] = g1 - g2;
         } else {
-            const long long g1 = S[o1], g2 = q.self ? 0ll : S[o2];
+            const long long g1 = rd.i64(o1), g2 = q.self ? 0ll : rd.i64(o2);
             split_int<PARTS, SHIFT>(add_ovf(g1, g2, bad), xs);
             split_int<PARTS, SHIFT>(sub_ovf(g1, g2, bad), xd);
         }
@@ -660,11 +707,11 @@ __device__ __forceinline__ void accumulate_group3(const long long* S, const TapF
         }
     }
     if constexpr (GRP + 1 < bsf_tables::kRep3Groups)
-        accumulate_group3<GRP + 1, SRC, PARTS, SHIFT, M0, CM>(S, fr, G, bad);
+        accumulate_group3<GRP + 1, SRC, PARTS, SHIFT, M0, CM>(rd, fr, G, bad);
 }
 
-template <int SRC, int PARTS, int SHIFT, int ALO, int AHI>
-__device__ __forceinline__ void accumulate_chunk3(const long long* S, const TapFrame<3>& fr,
+template <int SRC, int PARTS, int SHIFT, int ALO, int AHI, typename RD>
+__device__ __forceinline__ void accumulate_chunk3(const RD& rd, const TapFrame<3>& fr,
                                                   double (&G)[PARTS][mono_index<10>(AHI, 10 - AHI) -
                                                                      mono_index<10>(ALO, 0) + 1],
                                                   unsigned& bad) {
@@ -675,16 +722,17 @@ __device__ __forceinline__ void accumulate_chunk3(const long long* S, const TapF
     for (int p = 0; p < PARTS; ++p)
 #pragma unroll
         for (int c = 0; c < CM; ++c) G[p][c] = 0.0;
-    accumulate_group3<0, SRC, PARTS, SHIFT, M0, CM>(S, fr, G, bad);
+    accumulate_group3<0, SRC, PARTS, SHIFT, M0, CM>(rd, fr, G, bad);
 }
 
-__device__ __forceinline__ void accumulate_all3_dbl(const long long* S, const TapFrame<3>& fr,
+template <typename RD>
+__device__ __forceinline__ void accumulate_all3_dbl(const RD& rd, const TapFrame<3>& fr,
                                                     double (&G)[1][bsf_tables::kMono3]) {
     using T = Tab<3>;
 #pragma unroll
     for (int c = 0; c < T::M; ++c) G[0][c] = 0.0;
     unsigned unused = 0;
-    accumulate_group3<0, SRC_DBL, 1, 0, 0, T::M>(S, fr, G, unused);
+    accumulate_group3<0, SRC_DBL, 1, 0, 0, T::M>(rd, fr, G, unused);
 }
 
 // Horner over the chunk's u1-powers AHI..ALO (compensated), continuing the running value P.
@@ -781,18 +829,18 @@ __host__ __device__ constexpr int split_low() { return (N == 1 || N >= 10) ? Tab
 template <int N>
 __host__ __device__ constexpr double split_min_volume() { return N == 2 ? 625.0 : 410.0; }
 
-template <int N, int SRC, int ALO, int AHI, bool FIRST, int LOW>
-__device__ __forceinline__ void interp_chunk_dd(const long long* S, const TapFrame<N>& fr, dd v1, dd v2, cp& P,
+template <int N, int SRC, int ALO, int AHI, bool FIRST, int LOW, typename RD>
+__device__ __forceinline__ void interp_chunk_dd(const RD& rd, const TapFrame<N>& fr, dd v1, dd v2, cp& P,
                                                 double& PH, double& B, unsigned& bad) {
     using T = Tab<N>;
     constexpr int PARTS = SRC == SRC_DBL ? 1 : T::SPLIT;
     double G[PARTS][mono_index<T::DEG>(AHI, T::DEG - AHI) - mono_index<T::DEG>(ALO, 0) + 1];
     if constexpr (N == 3 && SRC == SRC_DBL && ALO == 0 && AHI == 10)
-        accumulate_all3_dbl(S, fr, G);
+        accumulate_all3_dbl(rd, fr, G);
     else if constexpr (N == 3)
-        accumulate_chunk3<SRC, PARTS, T::SHIFT, ALO, AHI>(S, fr, G, bad);
+        accumulate_chunk3<SRC, PARTS, T::SHIFT, ALO, AHI>(rd, fr, G, bad);
     else
-        accumulate_chunk<N, SRC, PARTS, T::SHIFT, ALO, AHI>(S, fr, G, bad);
+        accumulate_chunk<N, SRC, PARTS, T::SHIFT, ALO, AHI>(rd, fr, G, bad);
     if constexpr (LOW >= T::DEG)
         horner_chunk_dd<N, PARTS, T::SHIFT, ALO, AHI, FIRST>(G, v1, v2, P);
     else
@@ -815,17 +863,17 @@ __device__ __forceinline__ void horner_chunk_f64(
     }
 }
 
-template <int N, int SRC, int ALO, int AHI, bool FIRST>
-__device__ __forceinline__ void interp_chunk_f64(const long long* S, const TapFrame<N>& fr, double v1, double v2,
+template <int N, int SRC, int ALO, int AHI, bool FIRST, typename RD>
+__device__ __forceinline__ void interp_chunk_f64(const RD& rd, const TapFrame<N>& fr, double v1, double v2,
                                                  double& P, unsigned& bad) {
     using T = Tab<N>;
     double G[1][mono_index<T::DEG>(AHI, T::DEG - AHI) - mono_index<T::DEG>(ALO, 0) + 1];
     if constexpr (N == 3 && SRC == SRC_DBL && ALO == 0 && AHI == 10)
-        accumulate_all3_dbl(S, fr, G);
+        accumulate_all3_dbl(rd, fr, G);
     else if constexpr (N == 3)
-        accumulate_chunk3<SRC, 1, 0, ALO, AHI>(S, fr, G, bad);
+        accumulate_chunk3<SRC, 1, 0, ALO, AHI>(rd, fr, G, bad);
     else
-        accumulate_chunk<N, SRC, 1, 0, ALO, AHI>(S, fr, G, bad);
+        accumulate_chunk<N, SRC, 1, 0, ALO, AHI>(rd, fr, G, bad);
     horner_chunk_f64<N, ALO, AHI, FIRST>(G, v1, v2, P);
 }
 
@@ -834,33 +882,33 @@ __device__ __forceinline__ void interp_chunk_f64(const long long* S, const TapFr
 // to bound registers).
 // With LOW below the degree, B receives the plain part's error weight (see
 // horner_chunk_split) and the plain part is folded into the low word of the result.
-template <int N, int SRC, int LOW>
-__device__ __forceinline__ cp interp_dd(const long long* S, const TapFrame<N>& fr, dd v1, dd v2, double& B,
+template <int N, int SRC, int LOW, typename RD>
+__device__ __forceinline__ cp interp_dd(const RD& rd, const TapFrame<N>& fr, dd v1, dd v2, double& B,
                                         unsigned& bad) {
     using T = Tab<N>;
     cp P = {0.0, 0.0};
     double PH = 0.0;
     if constexpr (N != 3 || SRC == SRC_DBL) {
-        interp_chunk_dd<N, SRC, 0, T::DEG, true, LOW>(S, fr, v1, v2, P, PH, B, bad);
+        interp_chunk_dd<N, SRC, 0, T::DEG, true, LOW>(rd, fr, v1, v2, P, PH, B, bad);
     } else {  // three parts: two u1-chunks (84 and 114 accumulators)
-        interp_chunk_dd<N, SRC, 4, 10, true, LOW>(S, fr, v1, v2, P, PH, B, bad);
-        interp_chunk_dd<N, SRC, 0, 3, false, LOW>(S, fr, v1, v2, P, PH, B, bad);
+        interp_chunk_dd<N, SRC, 4, 10, true, LOW>(rd, fr, v1, v2, P, PH, B, bad);
+        interp_chunk_dd<N, SRC, 0, 3, false, LOW>(rd, fr, v1, v2, P, PH, B, bad);
     }
     if constexpr (LOW < T::DEG) P.c += PH;
     return P;
 }
 
 // the same in plain double
-template <int N, int SRC>
-__device__ __forceinline__ double interp_f64(const long long* S, const TapFrame<N>& fr, double v1, double v2,
+template <int N, int SRC, typename RD>
+__device__ __forceinline__ double interp_f64(const RD& rd, const TapFrame<N>& fr, double v1, double v2,
                                              unsigned& bad) {
     using T = Tab<N>;
     double P = 0.0;
     if constexpr (N != 3 || SRC == SRC_DBL) {
-        interp_chunk_f64<N, SRC, 0, T::DEG, true>(S, fr, v1, v2, P, bad);
+        interp_chunk_f64<N, SRC, 0, T::DEG, true>(rd, fr, v1, v2, P, bad);
     } else {
-        interp_chunk_f64<N, SRC, 4, 10, true>(S, fr, v1, v2, P, bad);
-        interp_chunk_f64<N, SRC, 0, 3, false>(S, fr, v1, v2, P, bad);
+        interp_chunk_f64<N, SRC, 4, 10, true>(rd, fr, v1, v2, P, bad);
+        interp_chunk_f64<N, SRC, 0, 3, false>(rd, fr, v1, v2, P, bad);
     }
     return P;
 }
@@ -935,7 +983,7 @@ __device__ dd mesh_dd(const long long* S, int wq, int hq, int mx, int my, float4
                         continue;
                     }
                     double Bk = 0.0;
-                    const cp P = interp_dd<K, SRC, LOW>(S, fr, v1, v2, Bk, bad);
+                    const cp P = interp_dd<K, SRC, LOW>(PlainRead{S}, fr, v1, v2, Bk, bad);
                     const int c = c124 * fd_binom<N>(k3);
                     const double cs = ((k1 + k2 + k3 + k4) & 1) ? -(double)c : (double)c;
                     acc = cp_axpy(acc, cs, P);
@@ -990,11 +1038,102 @@ __device__ double mesh_f64(const long long* S, int wq, int hq, int mx, int my, f
                         bad = 1;
                         continue;
                     }
-                    const double P = interp_f64<K, SRC>(S, fr, v1, v2, bad);
+                    const double P = interp_f64<K, SRC>(PlainRead{S}, fr, v1, v2, bad);
                     const int c = c124 * fd_binom<N>(k3);
                     acc = __fma_rn(((k1 + k2 + k3 + k4) & 1) ? -(double)c : (double)c, P, acc);
                 }
             }
+        }
+    }
+    return acc;
+}
+
+// Whether a pixel's (k1, k3) taps share their cell: integer a1 and a3.
+__device__ __forceinline__ bool lattice_scales(float4 a) { return a.x == rintf(a.x) && a.z == rintf(a.z); }
+
+// mesh_dd for integer a1 and a3: the (n+1)^2 taps (k1, k3) of each pair (k2, k4) as one
+// interpolant of the combined window (LatRead), so one set of coefficient sums and one
+// polynomial per pair instead of (n+1)^2 of each.  The geometry is mesh_dd's at k1 = k3 =
+// 0 -- the other anchors follow exactly -- and the frame check covers all (k1, k3).  E
+// receives sum |c24| B of the combined polynomials, which bounds the plain parts' error as
+// in mesh_dd.  Integer windows need |values| < 2^(62 - 2n), float64 windows values below
+// 2^(exact_bits - 2n), for the combined sums to stay exact (the caller checks).
+template <int N, int SRC, int LOW = Tab<N>::DEG, int K = N>
+__device__ dd mesh_dd_lat(const long long* S, int wq, int hq, int mx, int my, float4 a, int k2lo, int k2hi,
+                          unsigned& bad, double& E) {
+    const dd isq = {kInvSqrt2Hi, kInvSqrt2Lo};
+    const double a1 = a.x;
+    const int i1 = (int)a.x, i3 = (int)a.z;
+    const dd A2 = dd_mul_d(isq, (double)a.y);
+    const dd A4 = dd_mul_d(isq, (double)a.w);
+    constexpr double h = 0.5 * N;
+    constexpr int jl = stencil_lo<K>(), jh = stencil_hi<K>();
+    const dd T1 = dd_mul_d(dd_add_d(dd_add(A2, dd_neg(A4)), a1 - 1.0), h);
+    const dd T2 = dd_mul_d(dd_add_d(dd_add(A2, A4), (double)a.z - 3.0), h);
+    const LatRead<N> rd = {S, i1, i3 * wq};
+    cp acc = {0.0, 0.0};
+    for (int k2 = k2lo; k2 <= k2hi; ++k2) {
+        for (int k4 = 0; k4 <= N; ++k4) {
+            const int c24 = fd_binom<N>(k2) * fd_binom<N>(k4);
+            const dd D2 = dd_mul_d(A2, (double)k2), D4 = dd_mul_d(A4, (double)k4);
+            const dd d1 = dd_add_d(dd_add(T1, dd_add(D4, dd_neg(D2))), -0.0);
+            const dd d2 = dd_add_d(dd_add(T2, dd_neg(dd_add(D2, D4))), -0.0);
+            const double f1 = Tab<K>::ODD ? rint(d1.hi) : floor(d1.hi);
+            const double f2 = Tab<K>::ODD ? rint(d2.hi) : floor(d2.hi);
+            const double oc = Tab<K>::ODD ? 0.0 : 0.5;
+            const dd u1 = dd_add_d(d1, -(f1 + oc));
+            const dd u2 = dd_add_d(d2, -(f2 + oc));
+            const Turn t = cell_turn(u1.hi, u2.hi);
+            const dd v1 = dd_turn(t.swap, t.n1, u1, u2);
+            const dd v2 = dd_turn(t.swap, t.n2, u2, u1);
+            const int qx = mx + (int)f1, qy = my + (int)f2;
+            const TapFrame<K> fr = tap_frame<K>(qx, qy, t, wq, hq);
+            if (!(qx - N * i1 + jl >= 0 && qx + jh < wq && qy - N * i3 + jl >= 0 && qy + jh < hq)) {
+                bad = 1;
+                continue;
+            }
+            double Bk = 0.0;
+            const cp P = interp_dd<K, SRC, LOW>(rd, fr, v1, v2, Bk, bad);
+            acc = cp_axpy(acc, ((k2 + k4) & 1) ? -(double)c24 : (double)c24, P);
+            if constexpr (LOW < Tab<K>::DEG) E = __fma_rn((double)c24, Bk, E);
+        }
+    }
+    return fast_two_sum(acc.s, acc.c);
+}
+
+// mesh_f64 for integer a1 and a3 (as mesh_dd_lat).
+template <int N, int SRC, int K = N>
+__device__ double mesh_f64_lat(const long long* S, int wq, int hq, int mx, int my, float4 a, int k2lo, int k2hi,
+                               unsigned& bad) {
+    const double a1 = a.x, a3 = a.z;
+    const int i1 = (int)a.x, i3 = (int)a.z;
+    const double A2 = (double)a.y * kInvSqrt2Hi, A4 = (double)a.w * kInvSqrt2Hi;
+    constexpr double h = 0.5 * N;
+    constexpr int jl = stencil_lo<K>(), jh = stencil_hi<K>();
+    const double T1 = h * (a1 + A2 - A4 - 1.0);
+    const double T2 = h * (A2 + a3 + A4 - 3.0);
+    const LatRead<N> rd = {S, i1, i3 * wq};
+    double acc = 0.0;
+    for (int k2 = k2lo; k2 <= k2hi; ++k2) {
+        for (int k4 = 0; k4 <= N; ++k4) {
+            const int c24 = fd_binom<N>(k2) * fd_binom<N>(k4);
+            const double d1 = T1 - k2 * A2 + k4 * A4;
+            const double d2 = T2 - k2 * A2 - k4 * A4;
+            const double f1 = Tab<K>::ODD ? rint(d1) : floor(d1);
+            const double f2 = Tab<K>::ODD ? rint(d2) : floor(d2);
+            const double oc = Tab<K>::ODD ? 0.0 : 0.5;
+            const double u1 = d1 - f1 - oc, u2 = d2 - f2 - oc;
+            const Turn t = cell_turn(u1, u2);
+            const double w1 = t.swap ? u2 : u1, w2 = t.swap ? u1 : u2;
+            const double v1 = t.n1 ? -w1 : w1, v2 = t.n2 ? -w2 : w2;
+            const int qx = mx + (int)f1, qy = my + (int)f2;
+            const TapFrame<K> fr = tap_frame<K>(qx, qy, t, wq, hq);
+            if (!(qx - N * i1 + jl >= 0 && qx + jh < wq && qy - N * i3 + jl >= 0 && qy + jh < hq)) {
+                bad = 1;
+                continue;
+            }
+            const double P = interp_f64<K, SRC>(rd, fr, v1, v2, bad);
+            acc = __fma_rn(((k2 + k4) & 1) ? -(double)c24 : (double)c24, P, acc);
         }
     }
     return acc;
@@ -1148,7 +1287,7 @@ __device__ __forceinline__ double triple_f64(const long long* S, int wq, int nro
             bad = 1;
             continue;
         }
-        const double P = interp_f64<K, SRC>(S, fr, v1, v2, bad);
+        const double P = interp_f64<K, SRC>(PlainRead{S}, fr, v1, v2, bad);
         const int c = c124 * fd_binom<N>(k3);
         acc = __fma_rn(((k1 + k2 + k3 + k4) & 1) ? -(double)c : (double)c, P, acc);
     }
@@ -1190,7 +1329,7 @@ __device__ __forceinline__ cp triple_dd(const long long* S, int wq, int nrows, i
             continue;
         }
         double Bk = 0.0;
-        const cp P = interp_dd<K, SRC, LOW>(S, fr, v1, v2, Bk, bad);
+        const cp P = interp_dd<K, SRC, LOW>(PlainRead{S}, fr, v1, v2, Bk, bad);
         const int c = c124 * fd_binom<N>(k3);
         const double cs = ((k1 + k2 + k3 + k4) & 1) ? -(double)c : (double)c;
         acc = cp_axpy(acc, cs, P);
@@ -1397,7 +1536,11 @@ __device__ __forceinline__ void combine_halves(dd& acc, unsigned& bad) {
 // the block's first tile), cleared before tier 1, holds the block's tiles that go there
 // (bit (ty & 1) * 2 + (tx & 1)), and a tile that does not fit sets its bit and pushes the
 // block, (job, first tile), when it is the block's first bit.
-template <int N, int PATH, int TK = N>
+// LAT = 1: tiles whose pixels all have integer a1, a3 take the combined-tap form of the
+// mesh.  LAT = 0: every tile takes the per-tap form (the single-job tier 1 leaves the tiles
+// whose pixels all have integer a1, a3 to lattice_tile_kernel, so that its per-tap kernel
+// holds no code of the other form).
+template <int N, int PATH, int TK = N, int LAT = 1>
 __device__ __forceinline__ void process_tile(const JobDesc A, int job, int tile, const Launch L, long long* S,
                                              Shared& sh_, unsigned* blocks = nullptr) {
     auto& red = sh_.red;
@@ -1425,6 +1568,9 @@ __device__ __forceinline__ void process_tile(const JobDesc A, int job, int tile,
         for (int d = 0; d < 4; ++d) valid = valid && (av[d] >= (float)kScaleMin) && (av[d] <= (float)kScaleMax);
         if (!valid) atomicOr(A.err, kErrScale);
     }
+    // the combined-tap form is taken tile by tile (every call path then agrees bitwise)
+    bool tile_lat = false;
+    if constexpr (LAT == 1) tile_lat = __syncthreads_and(!inside || (valid && lattice_scales(a))) != 0;
     double R1 = valid ? reach1(N, a.x, a.y, a.w) : 0.0;
     double R2 = valid ? reach1(N, a.z, a.y, a.w) : 0.0;
     R1 = wave_max(R1);
@@ -1515,7 +1661,16 @@ __device__ __forceinline__ void process_tile(const JobDesc A, int job, int tile,
         }
         unsigned bad = 0;
         dd m = {0.0, 0.0};
-        if (inside && valid) m.hi = mesh_f64<N, SRC_DBL, TK>(S, g.wq, g.hq, mx, my, a, k2lo, k2hi, bad);
+        // a wave whose pixels all have integer a1, a3 combines each pair's (k1, k3) taps
+        // a tile whose pixels all have integer a1, a3 combines each pair's (k1, k3) taps
+        const bool lat = tile_lat;
+        if (inside && valid) {
+            if constexpr (LAT == 1)
+                m.hi = lat ? mesh_f64_lat<N, SRC_DBL, TK>(S, g.wq, g.hq, mx, my, a, k2lo, k2hi, bad)
+                           : mesh_f64<N, SRC_DBL, TK>(S, g.wq, g.hq, mx, my, a, k2lo, k2hi, bad);
+            else
+                m.hi = mesh_f64<N, SRC_DBL, TK>(S, g.wq, g.hq, mx, my, a, k2lo, k2hi, bad);
+        }
         combine_halves<SPLIT>(m, bad);
         if (!inside || half) return;
         if (!valid) {
@@ -1622,6 +1777,11 @@ __device__ __forceinline__ void process_tile(const JobDesc A, int job, int tile,
             }
             constexpr int kExact = exact_bits<TK>();  // folded at compile time
             const bool fast = !__syncthreads_or((mag >> kExact) != 0ull);
+            // a tile whose pixels all have integer a1, a3 combines each pair's (k1, k3) taps
+            // (mesh_dd_lat) where the combined window stays exact
+            bool lat = false;
+            if constexpr (LAT == 1)
+                lat = tile_lat && !__syncthreads_or((mag >> (fast ? kExact - 2 * N : 62 - 2 * N)) != 0ull);
             if (fast) {
                 for (int i = tid; i < g.qn; i += NT) reinterpret_cast<double*>(S)[i] = (double)S[i];
                 __syncthreads();
@@ -1645,15 +1805,25 @@ __device__ __forceinline__ void process_tile(const JobDesc A, int job, int tile,
                             // split evaluation; a pixel whose bound on the plain parts' error,
                             // 2^-47 E, exceeds 2^-44 |s| is evaluated again, compensated
                             constexpr int LOW = split_low<TK>();
-                            m = fast ? mesh_dd<N, SRC_DBL, LOW, TK>(S, g.wq, g.hq, mx, my, a, k2lo, k2hi, bad, E)
-                                     : mesh_dd<N, SRC_INT, LOW, TK>(S, g.wq, g.hq, mx, my, a, k2lo, k2hi, bad, E);
+                            if (LAT == 1 && lat)
+                                m = fast ? mesh_dd_lat<N, SRC_DBL, LOW, TK>(S, g.wq, g.hq, mx, my, a, k2lo, k2hi, bad, E)
+                                         : mesh_dd_lat<N, SRC_INT, LOW, TK>(S, g.wq, g.hq, mx, my, a, k2lo, k2hi, bad, E);
+                            else
+                                m = fast ? mesh_dd<N, SRC_DBL, LOW, TK>(S, g.wq, g.hq, mx, my, a, k2lo, k2hi, bad, E)
+                                         : mesh_dd<N, SRC_INT, LOW, TK>(S, g.wq, g.hq, mx, my, a, k2lo, k2hi, bad, E);
                             done_m = E <= 8.0 * fabs(m.hi);
                             redo = !done_m;
                         }
                     }
-                    if (!done_m)
-                        m = fast ? mesh_dd<N, SRC_DBL, Tab<TK>::DEG, TK>(S, g.wq, g.hq, mx, my, a, k2lo, k2hi, bad, E)
-                                 : mesh_dd<N, SRC_INT, Tab<TK>::DEG, TK>(S, g.wq, g.hq, mx, my, a, k2lo, k2hi, bad, E);
+                    if (!done_m) {
+                        constexpr int DEG = Tab<TK>::DEG;
+                        if (LAT == 1 && lat)
+                            m = fast ? mesh_dd_lat<N, SRC_DBL, DEG, TK>(S, g.wq, g.hq, mx, my, a, k2lo, k2hi, bad, E)
+                                     : mesh_dd_lat<N, SRC_INT, DEG, TK>(S, g.wq, g.hq, mx, my, a, k2lo, k2hi, bad, E);
+                        else
+                            m = fast ? mesh_dd<N, SRC_DBL, DEG, TK>(S, g.wq, g.hq, mx, my, a, k2lo, k2hi, bad, E)
+                                     : mesh_dd<N, SRC_INT, DEG, TK>(S, g.wq, g.hq, mx, my, a, k2lo, k2hi, bad, E);
+                    }
                     acc_dd = dd_add(acc_dd, dd_mul_d(m, wk));
                 } else {
                     const double m = fast ? mesh_f64<N, SRC_DBL, TK>(S, g.wq, g.hq, mx, my, a, k2lo, k2hi, bad)
@@ -2014,6 +2184,19 @@ __device__ __forceinline__ void process_block(const JobDesc A, int lead, unsigne
     }
 }
 
+// Whether pixel `pix` of a tile lets the tile take the combined-tap mesh: outside the
+// image, or valid scales with integer a1 and a3.
+__device__ __forceinline__ bool lattice_pixel(const JobDesc& A, int tile, int pix) {
+    const int m1 = (tile % A.tiles_x) * kTile + pix % kTile, m2 = (tile / A.tiles_x) * kTile + pix / kTile;
+    if (m1 >= A.width || m2 >= A.height) return true;
+    const float4 a = *reinterpret_cast<const float4*>(A.scales + 4 * ((long long)m2 * A.scale_pitch + m1));
+    const float av[4] = {a.x, a.y, a.z, a.w};
+    bool q = true;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) q = q && (av[d] >= (float)kScaleMin) && (av[d] <= (float)kScaleMax);
+    return q && lattice_scales(a);
+}
+
 // The window of the batch kernels, addressed through the kernel's dynamic LDS symbol.
 extern __shared__ long long g_lds[];
 
@@ -2023,7 +2206,44 @@ __global__ __launch_bounds__((threads_of<N, PATH>())) __attribute__((amdgpu_wave
     JobDesc A, Launch L) {
     extern __shared__ long long S[];
     __shared__ Shared sh;
-    process_tile<N, PATH, TK>(A, 0, xcd_tile(blockIdx.x, gridDim.x), L, S, sh);
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (__syncthreads_and(lattice_pixel(A, tile, threadIdx.x % kThreads))) return;  // lattice_tile_kernel's
+    process_tile<N, PATH, TK, 0>(A, 0, tile, L, S, sh);
+}
+
+// Tier 1 of the tiles tile_kernel leaves: those whose pixels all have integer a1, a3.
+// Persistent workgroups; workgroup b takes the tiles of dispatch index b, b + G, b + 2G, ...
+// (G the grid, a multiple of 8, so that the XCD order of tile_kernel holds).  One load per
+// thread reads the first pixel of up to a workgroup's width of its tiles at once -- a tile
+// can qualify only if that pixel does -- and only those candidates are checked in full and
+// filtered.  Where no tile qualifies (real scales) the launch costs one load per tile.
+template <int N, int PATH, int TK = N>
+__global__ __launch_bounds__((threads_of<N, PATH>())) __attribute__((amdgpu_waves_per_eu(N < 3 ? 2 : 1))) void lattice_tile_kernel(
+    JobDesc A, Launch L) {
+    extern __shared__ long long S[];
+    __shared__ Shared sh;
+    constexpr int NT = threads_of<N, PATH>(), NW = NT / 64;
+    auto* ballots = reinterpret_cast<unsigned long long*>(sh.red[0]);  // NW words, free between tiles
+    const int tiles = A.tiles_x * A.tiles_y;
+    const int pix = threadIdx.x % kThreads;
+    const int per = tiles > (int)blockIdx.x ? (tiles - (int)blockIdx.x + (int)gridDim.x - 1) / (int)gridDim.x : 0;
+    for (int c0 = 0; c0 < per; c0 += NT) {
+        const int k = c0 + (int)threadIdx.x;
+        const bool cand = k < per && lattice_pixel(A, xcd_tile((int)blockIdx.x + k * (int)gridDim.x, tiles), 0);
+        const unsigned long long b = __ballot(cand);
+        __syncthreads();  // the previous chunk's tiles are done with sh
+        if ((threadIdx.x & 63) == 0) ballots[threadIdx.x >> 6] = b;
+        __syncthreads();
+        unsigned long long bw[NW];
+#pragma unroll
+        for (int wv = 0; wv < NW; ++wv) bw[wv] = ballots[wv];
+#pragma unroll
+        for (int wv = 0; wv < NW; ++wv)
+            for (unsigned long long m = bw[wv]; m; m &= m - 1) {
+                const int tile = xcd_tile((int)blockIdx.x + (c0 + wv * 64 + __ffsll((long long)m) - 1) * (int)gridDim.x, tiles);
+                if (__syncthreads_and(lattice_pixel(A, tile, pix))) process_tile<N, PATH, TK, 1>(A, 0, tile, L, S, sh);
+            }
+    }
 }
 
 // Test aid: stage 1 of one tile.
@@ -2670,7 +2890,7 @@ struct Tiers {
     ItemList inA, inB;
     long long* scratch = nullptr;
     unsigned* blocks = nullptr;  // tier 3's block words (null without tier 3)
-    int grid2 = 1, grid3 = 1;
+    int grid2 = 1, grid3 = 1, grid_lat = 1;
 };
 
 // Tiers over `items` tiles whose overflow lists are la / lb (capacity items each) and
@@ -2687,6 +2907,7 @@ Tiers make_tiers_at(const bsf_ctx* c, const Plan& p, unsigned* ctr, int2* la, in
     t.L2.lds_cap = p.t2;
     t.L3 = t.L1;
     t.L3.lds_cap = p.t3;
+    t.grid_lat = (int)std::max<long long>(8, ((long long)c->cus * per_cu(c, p.t1, order)) & ~7ll);
     if (p.use2) {
         t.L1.push_count = ctr + 0;
         t.L1.push_list = la;
@@ -2725,12 +2946,15 @@ hipError_t launch_single(const JobDesc& A, const Plan& p, const Tiers& t, int ti
     static bool once = false;
     if (!once) {
         allow_big_lds(&tile_kernel<N, PATH, TK>);
+        allow_big_lds(&lattice_tile_kernel<N, PATH, TK>);
         allow_big_lds(&overflow_kernel<N, PATH, TK>);
         allow_big_lds(&scratch_kernel<N, PATH, TK>);
         allow_big_lds(&debug_tile_kernel<N, PATH, TK>);
         once = true;
     }
     hipLaunchKernelGGL((tile_kernel<N, PATH, TK>), dim3(tiles), dim3(threads_of<N, PATH>()), (size_t)p.t1 * 8, st, A, t.L1);
+    hipLaunchKernelGGL((lattice_tile_kernel<N, PATH, TK>), dim3(t.grid_lat), dim3(threads_of<N, PATH>()), (size_t)p.t1 * 8,
+                       st, A, t.L1);
     if (p.use2)
         hipLaunchKernelGGL((overflow_kernel<N, PATH, TK>), dim3(t.grid2), dim3(threads_of<N, PATH>()), (size_t)p.t2 * 8, st, A,
                            t.L2, t.inA, t.blocks);
@@ -2873,6 +3097,8 @@ long long measure_static_lds_n() {
     long long mx = 0;
     static_lds(&tile_kernel<N, 0>, mx);
     static_lds(&tile_kernel<N, 1>, mx);
+    static_lds(&lattice_tile_kernel<N, 0>, mx);
+    static_lds(&lattice_tile_kernel<N, 1>, mx);
     static_lds(&overflow_kernel<N, 0>, mx);
     static_lds(&overflow_kernel<N, 1>, mx);
     static_lds(&debug_tile_kernel<N, 0>, mx);
@@ -2890,6 +3116,10 @@ long long measure_static_lds_n() {
         static_lds(&tile_kernel<1, 1, table_key(1, 0)>, mx);
         static_lds(&tile_kernel<1, 0, table_key(1, 1)>, mx);
         static_lds(&tile_kernel<1, 1, table_key(1, 1)>, mx);
+        static_lds(&lattice_tile_kernel<1, 0, table_key(1, 0)>, mx);
+        static_lds(&lattice_tile_kernel<1, 1, table_key(1, 0)>, mx);
+        static_lds(&lattice_tile_kernel<1, 0, table_key(1, 1)>, mx);
+        static_lds(&lattice_tile_kernel<1, 1, table_key(1, 1)>, mx);
         static_lds(&overflow_kernel<1, 0, table_key(1, 1)>, mx);
         static_lds(&overflow_kernel<1, 1, table_key(1, 1)>, mx);
         static_lds(&scratch_kernel<1, 0, table_key(1, 1)>, mx);
