@@ -44,11 +44,11 @@ PEAK_HBM = 8.0e12          # B/s
 # HBM bytes per launch of the dominant kernel, from rocprofv3 FETCH_SIZE / WRITE_SIZE runs
 # (scaled by a 1 GiB device copy), keyed by the kernel source they were taken on: once
 # the source changes, the figure no longer applies and the bench reports null.
-MEASURED_TRAFFIC = {"6735b44788a6f082": {("plain", "f64"): 148.7e6, ("ellipse", "f32"): 117.5e6,
+MEASURED_TRAFFIC = {"527fbed257448fff": {("plain", "f64"): 148.2e6, ("ellipse", "f32"): 117.5e6,
                                         ("signal1d", "f64"): 1140.7e6, ("signal1d", "f32tiled"): 872.2e6}}
 # Fraction of the chip's VALU issue slots the dominant kernel used (rocprofv3 SQ_INSTS_VALU x 4
 # cycles over 1024 SIMDs x 2.4 GHz x kernel time), keyed the same way.
-MEASURED_VALU_ISSUE = {"6735b44788a6f082": {("plain", "f64"): 0.87, ("signal1d", "f64"): 0.74,
+MEASURED_VALU_ISSUE = {"527fbed257448fff": {("plain", "f64"): 0.86, ("signal1d", "f64"): 0.76,
                                            ("signal1d", "f32tiled"): 0.70}}
 
 
@@ -397,13 +397,20 @@ def serving_stream(args, duration: float, compare: bool) -> dict:
     def stream_run(graphs):
         srv = server(graphs)
         t_start = time.perf_counter()
-        futs = []
+        futs = []  # outstanding requests; finished ones are dropped with their pinned results
         for t_a, k in zip(arrivals, picks):
             now = time.perf_counter() - t_start
             if t_a > now:
                 time.sleep(t_a - now)
             im, sc, n, path = pool[k]
             futs.append(srv.submit(im, sc, n, path))
+            still = []
+            for f in futs:
+                if f.done():
+                    f.result()
+                else:
+                    still.append(f)
+            futs = still
         for f in futs:
             f.result()
         wall = time.perf_counter() - t_start

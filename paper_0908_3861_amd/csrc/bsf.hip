@@ -2218,7 +2218,7 @@ __global__ __launch_bounds__((threads_of<N, PATH>())) __attribute__((amdgpu_wave
 // can qualify only if that pixel does -- and only those candidates are checked in full and
 // filtered.  Where no tile qualifies (real scales) the launch costs one load per tile.
 template <int N, int PATH, int TK = N>
-__global__ __launch_bounds__((threads_of<N, PATH>())) __attribute__((amdgpu_waves_per_eu(N < 3 ? 2 : 1))) void lattice_tile_kernel(
+__global__ __launch_bounds__((threads_of<N, PATH>())) __attribute__((amdgpu_waves_per_eu(N < 3 && PATH == BSF_PATH_F32_TILED ? 2 : 1))) void lattice_tile_kernel(
     JobDesc A, Launch L) {
     extern __shared__ long long S[];
     __shared__ Shared sh;
