@@ -168,3 +168,39 @@ def test_batched_equals_single_with_integer_scales(bsf, torch_dev):
     assert bsf.default_context().device_error() == 0
     for o, s1 in zip(outs, singles):
         assert np.array_equal(o.cpu().numpy().view(np.uint8), s1.view(np.uint8))
+
+
+@pytest.mark.parametrize("path", ["f64", "f32tiled"])
+def test_scattered_integer_tiles_in_a_large_image(bsf, torch_dev, oracle_mod, path):
+    """4,096 tiles, of which a random fifth have integer a1, a3 throughout and another fifth only
+    in their first pixel: the per-tap tier-1 kernel leaves exactly the former to the integer-scale
+    kernel, whose persistent workgroups take several tiles each and check every candidate in full.
+    Every pixel is written once: the output equals the batched form's bitwise (one kernel there
+    decides per tile), and sampled pixels of both kinds of tile match the oracle."""
+    torch = torch_dev
+    rng = np.random.default_rng(470 + (path == "f32tiled"))
+    H = W = 1024
+    img = synth.unit_grid_image(rng, H, W, np.float32)
+    sc = synth.uniform_scales(rng, H, W, 1.0, 4.0)
+    kind = rng.integers(0, 5, size=(H // 16, W // 16))  # 0: integer tile, 1: integer first pixel
+    for ty, tx in zip(*np.nonzero(kind == 0)):
+        blk = sc[ty * 16:(ty + 1) * 16, tx * 16:(tx + 1) * 16]
+        blk[..., 0] = np.round(blk[..., 0])
+        blk[..., 2] = np.round(blk[..., 2])
+    for ty, tx in zip(*np.nonzero(kind == 1)):
+        sc[ty * 16, tx * 16, 0] = np.round(sc[ty * 16, tx * 16, 0])
+        sc[ty * 16, tx * 16, 2] = np.round(sc[ty * 16, tx * 16, 2])
+    ti, ts = torch.from_numpy(img).cuda(), torch.from_numpy(sc).cuda()
+    s = bsf.filter(ti, ts, 2, path=path, a_max=4.0)
+    assert bsf.default_context().device_error() == 0
+    b = bsf.filter_batched([dict(img=ti, scales=ts, order=2, path=path, a_max=4.0)])[0]
+    s, b = s.cpu().numpy(), b.cpu().numpy()
+    assert np.isfinite(s).all()
+    assert np.array_equal(s.view(np.uint8), b.view(np.uint8))
+    tiles = np.concatenate([rng.choice(np.flatnonzero(kind.reshape(-1) == k), 6, replace=False) for k in (0, 1, 2)])
+    pix = np.array([(t // (W // 16)) * 16 * W + (t % (W // 16)) * 16 + int(rng.integers(0, 16)) * W + int(rng.integers(0, 16))
+                    for t in tiles])
+    o = oracle_mod.filter(img.astype(np.float64), sc, 2, pixels=pix)
+    err = rel_max(s.reshape(-1)[pix], o)
+    print(f"scattered integer tiles, {path}: rel_max {err:.3g} over {pix.size} pixels")
+    assert err < (TOL_F64 if path == "f64" else TOL_F32), err
