@@ -2217,9 +2217,11 @@ __global__ __launch_bounds__((threads_of<N, PATH>())) __attribute__((amdgpu_wave
 // thread reads the first pixel of up to a workgroup's width of its tiles at once -- a tile
 // can qualify only if that pixel does -- and only those candidates are checked in full and
 // filtered.  Where no tile qualifies (real scales) the launch costs one load per tile.
+// all != 0 (images of at most one tile per CU): every tile, each taking the form its scales
+// allow, so that such an image needs one tier-1 launch.
 template <int N, int PATH, int TK = N>
 __global__ __launch_bounds__((threads_of<N, PATH>())) __attribute__((amdgpu_waves_per_eu(N < 3 && PATH == BSF_PATH_F32_TILED ? 2 : 1))) void lattice_tile_kernel(
-    JobDesc A, Launch L) {
+    JobDesc A, Launch L, int all) {
     extern __shared__ long long S[];
     __shared__ Shared sh;
     constexpr int NT = threads_of<N, PATH>(), NW = NT / 64;
@@ -2227,6 +2229,11 @@ __global__ __launch_bounds__((threads_of<N, PATH>())) __attribute__((amdgpu_wave
     const int tiles = A.tiles_x * A.tiles_y;
     const int pix = threadIdx.x % kThreads;
     const int per = tiles > (int)blockIdx.x ? (tiles - (int)blockIdx.x + (int)gridDim.x - 1) / (int)gridDim.x : 0;
+    if (all) {
+        for (int k = 0; k < per; ++k)
+            process_tile<N, PATH, TK, 1>(A, 0, xcd_tile((int)blockIdx.x + k * (int)gridDim.x, tiles), L, S, sh);
+        return;
+    }
     for (int c0 = 0; c0 < per; c0 += NT) {
         const int k = c0 + (int)threadIdx.x;
         const bool cand = k < per && lattice_pixel(A, xcd_tile((int)blockIdx.x + k * (int)gridDim.x, tiles), 0);
@@ -2237,7 +2244,6 @@ __global__ __launch_bounds__((threads_of<N, PATH>())) __attribute__((amdgpu_wave
         unsigned long long bw[NW];
 #pragma unroll
         for (int wv = 0; wv < NW; ++wv) bw[wv] = ballots[wv];
-#pragma unroll
         for (int wv = 0; wv < NW; ++wv)
             for (unsigned long long m = bw[wv]; m; m &= m - 1) {
                 const int tile = xcd_tile((int)blockIdx.x + (c0 + wv * 64 + __ffsll((long long)m) - 1) * (int)gridDim.x, tiles);
@@ -2891,6 +2897,7 @@ struct Tiers {
     long long* scratch = nullptr;
     unsigned* blocks = nullptr;  // tier 3's block words (null without tier 3)
     int grid2 = 1, grid3 = 1, grid_lat = 1;
+    int one_launch = 0;  // tiles at or below this: one tier-1 launch (one workgroup per CU)
 };
 
 // Tiers over `items` tiles whose overflow lists are la / lb (capacity items each) and
@@ -2908,6 +2915,7 @@ Tiers make_tiers_at(const bsf_ctx* c, const Plan& p, unsigned* ctr, int2* la, in
     t.L3 = t.L1;
     t.L3.lds_cap = p.t3;
     t.grid_lat = (int)std::max<long long>(8, ((long long)c->cus * per_cu(c, p.t1, order)) & ~7ll);
+    t.one_launch = c->cus;
     if (p.use2) {
         t.L1.push_count = ctr + 0;
         t.L1.push_list = la;
@@ -2952,9 +2960,15 @@ hipError_t launch_single(const JobDesc& A, const Plan& p, const Tiers& t, int ti
         allow_big_lds(&debug_tile_kernel<N, PATH, TK>);
         once = true;
     }
-    hipLaunchKernelGGL((tile_kernel<N, PATH, TK>), dim3(tiles), dim3(threads_of<N, PATH>()), (size_t)p.t1 * 8, st, A, t.L1);
-    hipLaunchKernelGGL((lattice_tile_kernel<N, PATH, TK>), dim3(t.grid_lat), dim3(threads_of<N, PATH>()), (size_t)p.t1 * 8,
-                       st, A, t.L1);
+    if (tiles <= t.one_launch) {  // one workgroup per CU at most: one launch, each tile in its own form
+        hipLaunchKernelGGL((lattice_tile_kernel<N, PATH, TK>), dim3(tiles), dim3(threads_of<N, PATH>()), (size_t)p.t1 * 8,
+                           st, A, t.L1, 1);
+    } else {
+        hipLaunchKernelGGL((tile_kernel<N, PATH, TK>), dim3(tiles), dim3(threads_of<N, PATH>()), (size_t)p.t1 * 8, st, A,
+                           t.L1);
+        hipLaunchKernelGGL((lattice_tile_kernel<N, PATH, TK>), dim3(t.grid_lat), dim3(threads_of<N, PATH>()),
+                           (size_t)p.t1 * 8, st, A, t.L1, 0);
+    }
     if (p.use2)
         hipLaunchKernelGGL((overflow_kernel<N, PATH, TK>), dim3(t.grid2), dim3(threads_of<N, PATH>()), (size_t)p.t2 * 8, st, A,
                            t.L2, t.inA, t.blocks);
