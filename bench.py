@@ -44,11 +44,11 @@ PEAK_HBM = 8.0e12          # B/s
 # HBM bytes per launch of the dominant kernel, from rocprofv3 FETCH_SIZE / WRITE_SIZE runs
 # (scaled by a 1 GiB device copy), keyed by the kernel source they were taken on: once
 # the source changes, the figure no longer applies and the bench reports null.
-MEASURED_TRAFFIC = {"e423d213c248ee03": {("plain", "f64"): 148.5e6, ("ellipse", "f32"): 117.5e6,
+MEASURED_TRAFFIC = {"1e1dbb754bcea6df": {("plain", "f64"): 148.6e6, ("ellipse", "f32"): 117.5e6,
                                         ("signal1d", "f64"): 1140.7e6, ("signal1d", "f32tiled"): 872.2e6}}
 # Fraction of the chip's VALU issue slots the dominant kernel used (rocprofv3 SQ_INSTS_VALU x 4
 # cycles over 1024 SIMDs x 2.4 GHz x kernel time), keyed the same way.
-MEASURED_VALU_ISSUE = {"e423d213c248ee03": {("plain", "f64"): 0.86, ("signal1d", "f64"): 0.75,
+MEASURED_VALU_ISSUE = {"1e1dbb754bcea6df": {("plain", "f64"): 0.86, ("signal1d", "f64"): 0.76,
                                            ("signal1d", "f32tiled"): 0.71}}
 
 

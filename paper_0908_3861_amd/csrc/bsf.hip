@@ -2008,16 +2008,30 @@ __device__ __forceinline__ void process_block(const JobDesc A, int lead, unsigne
         __syncthreads();
         unsigned unused = 0;
         preintegrate_window_n<N, false, 8>(Sd, g, true, cc, rc, unused, true);
+        // band by band, the flagged sub-tiles in turn: each band is copied once for all four
+        double msum[4] = {0.0, 0.0, 0.0, 0.0};
+        unsigned bads[4] = {0u, 0u, 0u, 0u};
+        over_bands([&](const long long* src, int nrows, int row0, int own0, int own1) {
+#pragma unroll 1
+            for (int s = 0; s < 4; ++s) {  // one copy of the mesh code
+                if (!((mask >> s) & 1u)) continue;
+                const Px q = pixel_of(s);
+                unsigned bad = 0;
+                const double part = mesh_f64_band_even<N, SRC_DBL, TK>(src, g.wq, nrows, row0, own0, own1, q.m1 - w.x0,
+                                                                       q.m2 - w.y0, q.a, q.valid, k2lo, k2hi, bad);
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (s == k) {
+                        msum[k] += part;
+                        bads[k] |= bad;
+                    }
+            }
+        });
         for (int s = 0; s < 4; ++s) {
             if (!((mask >> s) & 1u)) continue;
             const Px q = pixel_of(s);
-            const int mx = q.m1 - w.x0, my = q.m2 - w.y0;
-            unsigned bad = 0;
-            dd m = {0.0, 0.0};
-            over_bands([&](const long long* src, int nrows, int row0, int own0, int own1) {
-                m.hi += mesh_f64_band_even<N, SRC_DBL, TK>(src, g.wq, nrows, row0, own0, own1, mx, my, q.a, q.valid,
-                                                            k2lo, k2hi, bad);
-            });
+            unsigned bad = bads[s];
+            dd m = {msum[s], 0.0};
             combine_halves<SPLIT>(m, bad);
             if (!q.inside || half) continue;
             double v = q.valid ? finalize_f64<N, TK>(m.hi, q.a) : nan;
